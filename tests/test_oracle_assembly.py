@@ -1,0 +1,160 @@
+"""Pins of the oracle's fine-level assembly (problem of Section 3.1).
+
+* all-node pattern size: the pattern of a structured mesh is the tensor cube
+  of the 1-D pattern, nnz = (n (p+1)^2 - (n-1))^3, and 2 x 2 x 2 order-1
+  elements give Table 1's coarsest 27 rows / 343 nonzeros;
+* uniform meshes: the 3-D operator equals the Kronecker sum of 1-D operators
+  built here from exact polynomial integration (closed-form GLL nodes);
+* perturbed meshes: 1^T M 1 is the volume, K 1 = 0, bitwise symmetry;
+* Dirichlet structure and the manufactured-solution convergence rate.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from numpy.polynomial import Polynomial
+
+import synth
+from oracle import assembly, ptransfer
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+CLOSED_GLL = {1: [-1.0, 1.0], 2: [-1.0, 0.0, 1.0],
+              3: [-1.0, -1 / math.sqrt(5), 1 / math.sqrt(5), 1.0]}
+
+
+def _lagrange_polys(nodes):
+    out = []
+    for i, xi in enumerate(nodes):
+        others = [x for j, x in enumerate(nodes) if j != i]
+        poly = Polynomial.fromroots(others)
+        out.append(poly / poly(xi))
+    return out
+
+
+def _one_d(n, p):
+    """Global 1-D mass and stiffness on [0, 1], n elements of order p, by
+    exact integration of products of Lagrange polynomials."""
+    polys = _lagrange_polys(CLOSED_GLL[p])
+    h = 1.0 / n
+    Me = np.zeros((p + 1, p + 1))
+    Ke = np.zeros((p + 1, p + 1))
+    for i in range(p + 1):
+        for j in range(p + 1):
+            pm = (polys[i] * polys[j]).integ()
+            pk = (polys[i].deriv() * polys[j].deriv()).integ()
+            Me[i, j] = (pm(1) - pm(-1)) * h / 2
+            Ke[i, j] = (pk(1) - pk(-1)) * 2 / h
+    N = n * p + 1
+    M = np.zeros((N, N))
+    K = np.zeros((N, N))
+    for e in range(n):
+        s = slice(e * p, e * p + p + 1)
+        M[s, s] += Me
+        K[s, s] += Ke
+    return M, K
+
+
+@pytest.mark.parametrize("n,p", [(1, 1), (2, 1), (3, 2), (2, 4), (4, 3)])
+def test_all_node_pattern_formula(n, p):
+    m = synth.hex_mesh(n, p)
+    assert assembly.all_node_pattern_nnz(m.l2g, m.n_nodes) == (n * (p + 1) ** 2 - (n - 1)) ** 3
+
+
+def test_table1_coarsest_level_pin():
+    rows = [l for l in open(os.path.join(GOLDEN, "table1_giamg_hierarchy.txt"))
+            if l.strip() and not l.startswith("#")]
+    order, nel, levels, crow, cnnz = map(int, rows[0].split())
+    assert len(ptransfer.p_schedule(order)) == levels
+    m = synth.hex_mesh(nel, 1)
+    assert m.n_nodes == crow
+    assert assembly.all_node_pattern_nnz(m.l2g, m.n_nodes) == cnnz
+    A, _ = assembly.assemble(m.coords, m.l2g, 1, 1.0, bc="none")
+    assert A.shape == (crow, crow) and A.nnz == cnnz
+
+
+@pytest.mark.parametrize("n,p,lam", [(2, 1, 1.0), (3, 2, 0.5), (2, 3, 10.0)])
+def test_kronecker_sum_uniform(n, p, lam):
+    m = synth.hex_mesh(n, p)
+    A, _ = assembly.assemble(m.coords, m.l2g, p, lam, bc="none")
+    M1, K1 = _one_d(n, p)
+    ref = (np.kron(np.kron(K1, M1), M1) + np.kron(np.kron(M1, K1), M1)
+           + np.kron(np.kron(M1, M1), K1) + lam * np.kron(np.kron(M1, M1), M1))
+    D = A.toarray()
+    assert np.max(np.abs(D - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_q1_uniform_stencil_closed_form():
+    # interior Q1 Laplacian stencil on spacing h: centre 8h/3, neighbours
+    # along an axis 0, across a face diagonal -h/6, across a body diagonal -h/12
+    n = 4
+    h = 1.0 / n
+    m = synth.hex_mesh(n, 1)
+    A, _ = assembly.assemble(m.coords, m.l2g, 1, 0.0, bc="none")
+    L = n + 1
+    c = (2 * L + 2) * L + 2
+    row = A.getrow(c).toarray().ravel()
+    assert abs(row[c] - 8 * h / 3) < 1e-15
+    assert abs(row[c + 1]) < 1e-15
+    assert abs(row[c + L + 1] + h / 6) < 1e-15
+    assert abs(row[c + L * L + L + 1] + h / 12) < 1e-15
+
+
+@pytest.mark.parametrize("n,p", [(3, 2), (2, 4), (2, 6)])
+def test_perturbed_volume_nullspace_symmetry(n, p):
+    m = synth.hex_mesh(n, p, perturb=0.2, seed=7)
+    A1, _ = assembly.assemble(m.coords, m.l2g, p, 1.0, bc="none")
+    A0, _ = assembly.assemble(m.coords, m.l2g, p, 0.0, bc="none")
+    one = np.ones(m.n_nodes)
+    M = A1 - A0
+    assert abs(one @ (M @ one) - 1.0) < 1e-13
+    assert np.max(np.abs(A0 @ one)) < 1e-12
+    assert (A1 - A1.T).nnz == 0 or np.max(np.abs((A1 - A1.T).data)) == 0.0
+
+
+def test_dirichlet_structure():
+    n, p = 3, 2
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=3)
+    A, cons = assembly.assemble(m.coords, m.l2g, p, 1.0)
+    L = n * p + 1
+    assert cons.sum() == L ** 3 - (L - 2) ** 3
+    ci = np.nonzero(cons)[0]
+    for i in ci[:20]:
+        row = A.getrow(i)
+        assert row.nnz == 1 and row.indices[0] == i and row.data[0] == 1.0
+    # no free row stores a constrained column
+    Af = A[~cons][:, cons]
+    assert Af.nnz == 0
+    # pin mode constrains node 0 only
+    Ap, consp = assembly.assemble(m.coords, m.l2g, p, 0.0, bc="pin", pin=0)
+    assert consp.sum() == 1 and consp[0]
+
+
+def _nodal_error(n, p, lam):
+    m = synth.hex_mesh(n, p)
+    A, cons = assembly.assemble(m.coords, m.l2g, p, lam)
+    xq = assembly.quadrature_points(m.coords, m.l2g, p)
+    f = (lam + 3 * math.pi ** 2) * np.prod(np.sin(math.pi * xq), axis=2)
+    b = assembly.load_vector(m.coords, m.l2g, p, f, cons)
+    u = spla.spsolve(A.tocsc(), b)
+    # true GLL node positions on the uniform mesh, from closed forms
+    g = np.array(CLOSED_GLL[p])
+    lat = []
+    for e in range(n):
+        lat.extend(((e + (g[:-1] + 1) / 2) / n).tolist())
+    lat.append(1.0)
+    lat = np.array(lat)
+    X, Y, Z = np.meshgrid(lat, lat, lat, indexing="ij")
+    ue = (np.sin(math.pi * X) * np.sin(math.pi * Y) * np.sin(math.pi * Z)).ravel()
+    return np.max(np.abs(u - ue))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_manufactured_solution_rate(p):
+    e1 = _nodal_error(2, p, 1.0)
+    e2 = _nodal_error(4, p, 1.0)
+    rate = math.log2(e1 / e2)
+    assert rate > p + 0.6, (e1, e2, rate)
