@@ -1,0 +1,266 @@
+/*
+ * giamg.h -- C ABI of the MI355X (gfx950) GIAMG-PCG solver library.
+ *
+ * The library solves A x = b for the high-order finite-element operator
+ * A = K + lambda M (stiffness plus lambda times mass) of GLL-nodal hexahedra,
+ * with conjugate gradients preconditioned by one GIAMG V-cycle per
+ * iteration.  The method is that of Xu, Rasouli, Kirby, Moxey and Sundar,
+ * "A geometrically informed algebraic multigrid preconditioned iterative
+ * approach for solving high-order finite element systems" (arXiv 2512.15121):
+ *
+ *   - problem statement A x = b (Section 2);
+ *   - the V-cycle of Algorithm 1 with Jacobi-accelerated Chebyshev smoothing,
+ *     Galerkin coarse operators R A P with R = P^T and a direct solve on the
+ *     coarsest level (Section 2.1);
+ *   - p-coarsening driven by the element-to-dof map l2g (Section 2.2,
+ *     Algorithms 2-4; prolongation, Algorithm 7, nodal variant);
+ *   - smoothed-aggregation h-coarsening below order 1 (Section 2.5);
+ *   - CG preconditioned by the V-cycle, stopped on the relative residual
+ *     (Section 2.1, end; Section 3.1.1).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: GIAMG_OK (0) on success, a negative GIAMG_E* code on
+ *     error, GIAMG_ENOTCONV (> 0) as a warning when the iteration cap was
+ *     reached.  giamg_last_error() returns a thread-local message describing
+ *     the last error on the calling thread.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the GPU that was current at giamg_setup.  The caller
+ *     owns every array it passes; nothing is retained after a call returns.
+ *   - Work is enqueued on the HIP stream given at setup.  Calls that return
+ *     results to the host synchronise that stream before returning.
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ *     Distinct handles are independent.
+ */
+#ifndef GIAMG_H
+#define GIAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define GIAMG_OK          0
+#define GIAMG_ENOTCONV    1   /* warning: iteration cap reached; x holds the last iterate */
+#define GIAMG_EINVAL     (-1) /* bad argument (sizes, indices, geometry, options) */
+#define GIAMG_ENOMEM     (-2) /* device or host allocation failed; no handle is created */
+#define GIAMG_EHIP       (-3) /* a HIP runtime call failed */
+#define GIAMG_EBREAKDOWN (-4) /* CG breakdown: p^T A p <= 0 or a non-finite value */
+#define GIAMG_ENOTSUP    (-5) /* valid input outside what this build supports */
+
+/* ---- options ----------------------------------------------------------- */
+#define GIAMG_SMOOTHER_CHEBYSHEV 0
+#define GIAMG_SMOOTHER_JACOBI    1
+#define GIAMG_BC_DIRICHLET       0  /* nodes on faces owned by one element are constrained */
+#define GIAMG_BC_PIN             1  /* only pin_node is constrained (pure Neumann + pin) */
+#define GIAMG_PREC_FP64          0  /* everything in double precision, standard PCG */
+#define GIAMG_PREC_MIXED         1  /* FP32 V-cycle (coarsest in FP64) inside FP64 flexible CG */
+
+typedef struct giamg_opts {
+    int32_t  smoother;     /* GIAMG_SMOOTHER_*; default Chebyshev */
+    int32_t  degree;       /* Chebyshev degree or Jacobi sweeps, per pre- and post-smoothing; default 2 */
+    double   omega;        /* Jacobi weight; default 2/3 */
+    int32_t  coarse_max;   /* h-coarsen while a level has more rows than this; default 2000 */
+    int32_t  max_levels;   /* hierarchy depth cap, fine level included; default 10 */
+    int32_t  bc;           /* GIAMG_BC_*; default Dirichlet */
+    int64_t  pin_node;     /* constrained node for GIAMG_BC_PIN; default 0 */
+    int32_t  precision;    /* GIAMG_PREC_*; default FP64 */
+    int32_t  maxit;        /* CG iteration cap; default 500 */
+    uint64_t agg_seed;     /* SplitMix64 seed of the aggregation priorities; default 0 */
+    int32_t  power_iters;  /* power iterations for lambda_max(D^-1 A); default 20 */
+    double   cheb_lo;      /* Chebyshev interval [cheb_lo, cheb_hi] * lambda_max estimate; */
+    double   cheb_hi;      /* defaults 0.1 and 1.1 */
+} giamg_opts;
+
+/* Fill *opts with the defaults listed above. */
+void giamg_default_opts(giamg_opts* opts);
+
+typedef struct giamg_s* giamg_handle;   /* opaque, owned by the library */
+
+typedef struct giamg_info {
+    int32_t iters;         /* CG iterations performed (A p products) */
+    int32_t status;        /* return code of the solve for this right-hand side */
+    double  relres;        /* ||r_k|| / ||b|| of the recursively updated residual at exit */
+    double  true_relres;   /* ||b - A x|| / ||b|| recomputed at exit, FP64 */
+    double  solve_ms;      /* GPU time of the whole solve, HIP events on the handle's stream */
+} giamg_info;
+
+/*
+ * giamg_setup -- build the hierarchy for A = K + lambda M.
+ *
+ * coords   host, double [n_nodes][3]: node coordinates.  Only the eight corner
+ *          nodes of each element are read: an element is the trilinear image
+ *          of its corners (local (i,j,k) in {0,p}^3).
+ * l2g      host, int32 [n_elem][(p+1)^3]: the element-to-dof map of
+ *          Section 2.2.  Column (p+1)^2 i + (p+1) j + k holds the node with
+ *          basis index i along the first, j along the second and k along the
+ *          third reference direction (the tensor ordering of the paper's
+ *          appendix).  Every node must belong to at least one element.
+ * p        order, 1 <= p <= 10.   lambda >= 0 (lambda = 0 needs at least one
+ *          constrained node).
+ * opts     NULL for defaults.
+ * stream   hipStream_t for all work of this handle (NULL = default stream).
+ * out      receives the handle; left untouched on error.
+ *
+ * Discretisation: tensor Lagrange basis on Gauss-Lobatto-Legendre points,
+ * Gauss-Legendre quadrature with p+2 points per direction.  Constrained
+ * nodes get identity rows and columns.  Coarse orders follow
+ * q = p / (smallest prime factor of p) down to 1; coarse levels hold free
+ * nodes only.  Errors: GIAMG_EINVAL, GIAMG_ENOMEM, GIAMG_EHIP, GIAMG_ENOTSUP.
+ */
+int giamg_setup(const double* coords, int64_t n_nodes,
+                const int32_t* l2g, int64_t n_elem, int32_t p,
+                double lambda, const giamg_opts* opts, void* stream,
+                giamg_handle* out);
+
+/* Release every resource of the handle (NULL is ignored). */
+void giamg_free(giamg_handle h);
+
+/*
+ * giamg_solve -- GIAMG-preconditioned CG (Section 2.1) to ||r||/||b|| < tol.
+ *
+ * b        device, double [n_nodes].
+ * x        device, double [n_nodes]: initial guess on entry, solution on exit.
+ * info     host, may be NULL.
+ * FP64 mode runs standard PCG; mixed mode runs flexible CG (Polak-Ribiere
+ * beta) around an FP32 V-cycle whose coarsest solve stays FP64.
+ * Returns GIAMG_OK, GIAMG_ENOTCONV (cap reached), GIAMG_EBREAKDOWN or an
+ * error.  Synchronises the stream.
+ */
+int giamg_solve(giamg_handle h, const double* b, double* x, double tol,
+                giamg_info* info);
+
+/*
+ * giamg_solve_batch -- k independent solves against one hierarchy.
+ *
+ * B, X     device, double [n_nodes][k] row-major (right-hand side j is
+ *          column j); X holds initial guesses on entry.
+ * infos    host, k entries, may be NULL.
+ * Each column runs its own CG scalars and stops on its own; the V-cycle of
+ * all active columns runs as block sparse-matrix times dense-block products
+ * in the handle's precision.  Returns the worst per-column code.
+ */
+int giamg_solve_batch(giamg_handle h, const double* B, double* X, int32_t k,
+                      double tol, giamg_info* infos);
+
+/* ---- hierarchy introspection (host outputs; synchronise the stream) ---- */
+#define GIAMG_LEVEL_P        0   /* p-coarsened level (or the fine level) */
+#define GIAMG_LEVEL_H        1   /* smoothed-aggregation level */
+#define GIAMG_MAT_A          0
+#define GIAMG_MAT_P          1   /* prolongation to the next coarser level */
+#define GIAMG_MAT_R          2   /* restriction R = P^T */
+
+typedef struct giamg_level_desc {
+    int32_t kind;        /* GIAMG_LEVEL_* */
+    int32_t order;       /* polynomial order of the level (1 for h-levels) */
+    int32_t coarsest;    /* 1 on the last level */
+    int32_t pad;
+    int64_t rows;        /* rows of A on this level */
+    int64_t nnz_A, nnz_P, nnz_R;   /* P/R are 0 on the coarsest level */
+    double  lam_hat;     /* lambda_max(D^-1 A) estimate (0 on the coarsest level) */
+} giamg_level_desc;
+
+int giamg_num_levels(giamg_handle h);
+int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out);
+
+/* Copy one CSR operator of a level to host arrays sized from the level
+ * description: row_ptr int64 [rows+1], col int32 [nnz] (ascending within a
+ * row), val double [nnz].  Any pointer may be NULL to skip it. */
+int giamg_level_csr(giamg_handle h, int32_t level, int32_t which,
+                    int64_t* row_ptr, int32_t* col, double* val);
+
+/* p-levels: copy the level's element map, int32 [n_elem][(order+1)^3], -1
+ * for constrained nodes (coarse levels hold free nodes only).  h-levels:
+ * copy the aggregate id of each row of the level above, int32 [rows of the
+ * finer level]; pass the h-level's finer level index. */
+int giamg_level_l2g(giamg_handle h, int32_t level, int32_t* out);
+int giamg_level_aggregates(giamg_handle h, int32_t level, int32_t* out);
+
+/* Constrained-node mask of the fine level, uint8 [n_nodes] (host). */
+int giamg_constrained(giamg_handle h, uint8_t* mask);
+
+/*
+ * giamg_apply -- run one step of the V-cycle on device vectors of a level
+ * (double precision operators), for step-by-step checking.
+ *   GIAMG_OP_SPMV        out = A_l a
+ *   GIAMG_OP_RESIDUAL    out = a - A_l b              (a = f, b = x)
+ *   GIAMG_OP_RESTRICT    out = R_l a                  (out on level l+1)
+ *   GIAMG_OP_PROLONG_ADD out = out + P_l a            (a on level l+1)
+ *   GIAMG_OP_PRESMOOTH   out = pre-smoothing of A_l x = a from x = 0
+ *   GIAMG_OP_POSTSMOOTH  out = post-smoothing of A_l x = a from x = out
+ *   GIAMG_OP_COARSE      out = A_l^-1 a               (coarsest level only)
+ *   GIAMG_OP_VCYCLE      out = V-cycle from level l applied to a
+ * Add GIAMG_OP_FP32 to run the FP32 operators of a mixed-precision handle
+ * on float vectors.  Synchronises the stream.
+ */
+#define GIAMG_OP_SPMV         0
+#define GIAMG_OP_RESIDUAL     1
+#define GIAMG_OP_RESTRICT     2
+#define GIAMG_OP_PROLONG_ADD  3
+#define GIAMG_OP_PRESMOOTH    4
+#define GIAMG_OP_POSTSMOOTH   5
+#define GIAMG_OP_COARSE       6
+#define GIAMG_OP_VCYCLE       7
+#define GIAMG_OP_FP32         256
+int giamg_apply(giamg_handle h, int32_t op, int32_t level,
+                const void* a, const void* b, void* out);
+
+/* Physical coordinates of the fine-level quadrature points, host double
+ * [n_elem][(p+2)^3][3] (tensor Gauss points, first direction slowest). */
+int giamg_quadrature_points(giamg_handle h, double* xq);
+
+/* Load vector b_i = sum_e sum_q w_q |J| f_q phi_i(x_q) from values of f at
+ * those points (host double [n_elem][(p+2)^3]); b = 0 on constrained nodes.
+ * host out b [n_nodes]. */
+int giamg_load_vector(giamg_handle h, const double* fq, double* b);
+
+/* Setup timings in milliseconds: [0] host assembly, [1] p-transfers,
+ * [2] aggregation, [3] device Galerkin products, [4] coarsest factor,
+ * [5] smoother parameters, [6] total.  host out double[7]. */
+int giamg_setup_times(giamg_handle h, double* ms);
+
+
+/* ---- host-side setup steps (CPU only; no GPU or handle needed) ---------
+ * The setup stages that run on the host, exposed for checking.  Results are
+ * returned as a host CSR object owned by the library: query its sizes, copy
+ * it into caller arrays, then free it. */
+typedef struct giamg_hcsr_s* giamg_hcsr;
+
+int  giamg_hcsr_size(giamg_hcsr m, int64_t* rows, int64_t* cols, int64_t* nnz);
+int  giamg_hcsr_copy(giamg_hcsr m, int64_t* row_ptr, int32_t* col, double* val);
+void giamg_hcsr_free(giamg_hcsr m);
+
+/* Constrained-node mask of giamg_setup's boundary rule (faces owned by one
+ * element), uint8 [n_nodes]. */
+int giamg_host_boundary(const int32_t* l2g, int64_t n_elem, int32_t p, int64_t n_nodes,
+                        uint8_t* mask);
+
+/* Fine-level assembly exactly as giamg_setup performs it (bc and pin_node as
+ * in giamg_opts). */
+int giamg_host_assemble(const double* coords, int64_t n_nodes, const int32_t* l2g,
+                        int64_t n_elem, int32_t p, double lambda, int32_t bc,
+                        int64_t pin_node, giamg_hcsr* A_out);
+
+/* One p-coarsening step p -> q (q divides p) of Algorithms 2-4 and 7:
+ * free_mask uint8 [n_fine] marks the free fine nodes, l2g may hold -1 for
+ * constrained nodes; writes l2g_next int32 [n_elem][(q+1)^3] (-1 for
+ * constrained coarse nodes), the coarse size, and P. */
+int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t q,
+                          int64_t n_fine, const uint8_t* free_mask, int32_t* l2g_next,
+                          int64_t* n_coarse, giamg_hcsr* P_out);
+
+/* Smoothed-aggregation transfer of Section 2.5 for a CSR operator (host
+ * arrays, ascending columns): writes agg int32 [n], returns P. */
+int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const double* val,
+                         int64_t n, uint64_t seed, int32_t* agg, int64_t* n_agg,
+                         giamg_hcsr* P_out);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* giamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GIAMG_H */

@@ -1,0 +1,173 @@
+// Internal declarations of the GIAMG library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/giamg.h"
+
+namespace giamg {
+
+// ---- error handling -------------------------------------------------------
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define GIAMG_HIP(call)                                                        \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            throw ::giamg::Error(GIAMG_EHIP, std::string(#call) + ": " +       \
+                                                 hipGetErrorString(e_));       \
+    } while (0)
+
+#define GIAMG_REQUIRE(cond, msg)                                               \
+    do {                                                                       \
+        if (!(cond)) throw ::giamg::Error(GIAMG_EINVAL, msg);                  \
+    } while (0)
+
+// ---- device memory ----------------------------------------------------------
+// Owning device buffer; allocation failures raise GIAMG_ENOMEM.
+template <typename T>
+struct DevBuf {
+    T* ptr = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n) { o.ptr = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); ptr = o.ptr; n = o.n; o.ptr = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count == 0) return;
+        if (hipMalloc(reinterpret_cast<void**>(&ptr), count * sizeof(T)) != hipSuccess) {
+            ptr = nullptr;
+            n = 0;
+            (void)hipGetLastError();
+            throw Error(GIAMG_ENOMEM, "device allocation of " +
+                                          std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        n = 0;
+    }
+    T* get() const { return ptr; }
+};
+
+// Host-side CSR (setup work).
+struct HostCSR {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> val;
+    int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Device CSR: int64 row pointers, int32 ascending columns, FP64 values and an
+// optional FP32 copy of the values sharing the same index arrays.
+struct DevCSR {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    DevBuf<int64_t> rp;
+    DevBuf<int32_t> ci;
+    DevBuf<double> val;
+    DevBuf<float> val32;
+};
+
+// ---- the hierarchy ----------------------------------------------------------
+struct Level {
+    int kind = GIAMG_LEVEL_P;
+    int order = 1;
+    int64_t n = 0;
+    DevCSR A, P, R;                // P, R empty on the coarsest level
+    DevBuf<double> dinv;
+    DevBuf<float> dinv32;
+    double lam_hat = 0.0;
+    // work vectors (FP64 and FP32 sets)
+    DevBuf<double> f, x, r, d0, d1, t;
+    DevBuf<float> f32, x32, r32, d032, d132, t32;
+    // host-side metadata for introspection
+    std::vector<int32_t> l2g;      // p-levels: [n_elem][(order+1)^3], -1 = constrained
+    std::vector<int32_t> agg;      // aggregates of this level's rows (if the next level is h)
+};
+
+struct Handle {
+    hipStream_t stream = nullptr;
+    giamg_opts opts{};
+    int porder = 1;
+    double lambda = 0.0;
+    int64_t n_nodes = 0, n_elem = 0;
+    std::vector<Level> levels;
+    std::vector<uint8_t> constrained;
+    // geometry kept for the load-vector helpers
+    std::vector<double> corners;      // [n_elem][8][3]
+    std::vector<int32_t> l2g;         // fine element map
+    // coarsest level: dense inverse (FP64), rows nc
+    int64_t nc = 0;
+    DevBuf<double> coarse_inv;
+    // PCG state (FP64)
+    DevBuf<double> x, r, z, p, q, rold, tmp;
+    DevBuf<double> partial;           // block partial sums
+    DevBuf<double> scal;              // device scalars, see Scalars in solve.hip
+    double* host_scal = nullptr;      // pinned host mirror
+    int64_t partial_cap = 0;
+    // batched state
+    int32_t batch_k = 0;
+    double setup_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~Handle();
+};
+
+// ---- host setup (setup_host.cpp) -------------------------------------------
+void gll_points(int p, std::vector<double>& x, std::vector<double>& w);
+void gauss_points(int m, std::vector<double>& x, std::vector<double>& w);
+double lagrange_value(const std::vector<double>& nodes, int i, double x);
+double lagrange_derivative(const std::vector<double>& nodes, int i, double x);
+
+std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, int64_t n_nodes);
+void element_corners(const double* coords, const int32_t* l2g, int64_t n_elem, int p,
+                     std::vector<double>& corners);
+HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
+                      int p, int64_t n_nodes, double lambda,
+                      const std::vector<uint8_t>& constrained);
+void quadrature_points(const std::vector<double>& corners, int64_t n_elem, int p, double* xq);
+void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
+                 int p, int64_t n_nodes, const std::vector<uint8_t>& constrained,
+                 const double* fq, double* b);
+
+// p-transfer: returns P (n_fine x n_coarse) and fills the next l2g.
+HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q,
+                   int64_t n_fine, const std::vector<uint8_t>& free_mask,
+                   std::vector<int32_t>& l2g_next, int64_t& n_coarse);
+// smoothed aggregation on a host copy of A: fills agg and returns P.
+HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg,
+                    int64_t& n_agg);
+HostCSR transpose(const HostCSR& M);
+// dense SPD inverse through Cholesky; returns false if not positive definite.
+bool spd_inverse(const std::vector<double>& A, int64_t n, std::vector<double>& inv);
+
+uint64_t splitmix64(uint64_t seed, uint64_t i);
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)>& fn);
+
+// ---- device helpers (kernels_*.hip) ----------------------------------------
+void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32);
+void download_csr(const DevCSR& d, HostCSR& h, hipStream_t s);
+void make_fp32_values(DevCSR& d, hipStream_t s);
+// C = A * B with the full symbolic structure (device SpGEMM).
+void spgemm(const DevCSR& A, const DevCSR& B, DevCSR& C, hipStream_t s);
+
+}  // namespace giamg

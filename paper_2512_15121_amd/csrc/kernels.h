@@ -1,0 +1,91 @@
+// Launch wrappers of the GIAMG device kernels (internal).
+#pragma once
+
+#include "internal.h"
+
+namespace giamg {
+
+// Fused epilogues of the CSR product y_i = sum_j A_ij v_j, applied per row.
+enum SpmvMode : int {
+    SPMV_PLAIN = 0,      // y = A v
+    SPMV_RESID = 1,      // y = f - A v
+    SPMV_ADD = 2,        // y += A v                       (prolongation + correction)
+    SPMV_CHEB_INIT = 3,  // r = dinv (f - A v), d_new = r / theta      (v = x)
+    SPMV_CHEB_STEP = 4,  // r -= dinv A v, d_new = c1 v_i + c2 r, x update (v = d_old)
+    SPMV_JACOBI = 5,     // y = v + omega dinv (f - A v)   (v = x_old, y = x_new)
+    SPMV_DOT = 6,        // y = A v, block partials of v . y
+    SPMV_DINV = 7,       // y = dinv A v
+};
+
+// flags of SPMV_CHEB_STEP
+constexpr int CHEB_ASSIGN = 1;   // x = d_old (+ d_new) instead of x += ...
+constexpr int CHEB_LAST = 2;     // add the new direction as well (last step)
+
+template <typename T>
+struct SpmvArgs {
+    const int64_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const T* val = nullptr;
+    int64_t n = 0;
+    const T* v = nullptr;     // gathered vector
+    T* y = nullptr;           // output (or d_new)
+    const T* f = nullptr;
+    const T* dinv = nullptr;
+    T* r = nullptr;
+    T* x = nullptr;
+    double* partial = nullptr;
+    T c1 = 0, c2 = 0, inv_theta = 0, omega = 0;
+    int flags = 0;
+};
+
+template <typename T>
+void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s);
+// number of block partials SPMV_DOT writes for n rows
+int64_t spmv_blocks(int64_t n);
+
+// row-local kernels
+template <typename T>
+void launch_cheb_init0(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, T inv_theta,
+                       bool write_x, hipStream_t s);
+template <typename T>
+void launch_jacobi0(int64_t n, const T* f, const T* dinv, T* x, T omega, hipStream_t s);
+template <typename T>
+void launch_copy(int64_t n, const T* a, T* b, hipStream_t s);
+template <typename T>
+void launch_add(int64_t n, const T* a, T* b, hipStream_t s);   // b += a
+template <typename Tin, typename Tout>
+void launch_convert(int64_t n, const Tin* a, Tout* b, hipStream_t s);
+template <typename T>
+void launch_coarse_apply(int64_t n, const double* inv, const T* f, T* x, hipStream_t s);
+void launch_fill(int64_t n, double v, double* x, hipStream_t s);
+
+// reductions: block partials then a single-block finalize
+int64_t vec_blocks(int64_t n);
+void launch_dot_partial(int64_t n, const double* a, const double* b, double* partial, hipStream_t s);
+void launch_dot2_partial(int64_t n, const double* a, const double* b, const double* c,
+                         double* partial, hipStream_t s);  // a.b and c.b
+void launch_reduce(int64_t m, const double* partial, int64_t stride, int ncomp, double* out,
+                   hipStream_t s);
+
+// PCG / FCG vector kernels
+// device scalar slots; (S_BB, S_RR) and (S_RZNEW, S_ZROLD) are written as pairs
+enum ScalarSlot : int {
+    S_BB = 0, S_RR = 1, S_RZ = 2, S_PQ = 3, S_ALPHA = 4, S_BETA = 5, S_RZNEW = 6, S_ZROLD = 7,
+    S_FLAG = 8, S_TMP = 9, S_COUNT = 16
+};
+void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const double* p,
+                       const double* q, const double* scal, double* partial, hipStream_t s);
+void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s);
+void launch_pcg_alpha(double* scal, hipStream_t s);                 // alpha = rz / pq, flag
+void launch_pcg_beta(double* scal, bool flexible, bool first, hipStream_t s);
+void launch_residual_init(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                          const double* b, const double* x, double* r, double* partial,
+                          hipStream_t s);  // r = b - A x; partials of b.b, r.r
+void launch_power_start(int64_t n, double* v, hipStream_t s);
+void launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
+
+// blocked (multi right-hand side) kernels, row-major [n][k]
+template <typename T>
+void launch_spmm(int mode, const SpmvArgs<T>& a, int k, hipStream_t s);
+
+}  // namespace giamg

@@ -1,0 +1,602 @@
+// Hierarchy construction and the solve phase of GIAMG-PCG on one GPU.
+//
+// Setup (Section 2): fine assembly on the host, then level by level the
+// p-transfer (Algorithms 2-4, 7) or smoothed-aggregation transfer
+// (Section 2.5) on the host and the Galerkin product R (A P) on the device
+// (Section 2.1), a dense inverse of the coarsest operator, and per level the
+// Jacobi diagonal and the Chebyshev interval from a power iteration.
+//
+// Solve (Section 2.1): CG preconditioned by one V-cycle (Algorithm 1) per
+// iteration, everything on the device; the host reads one small block of
+// scalars per iteration for the stopping test.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace giamg {
+
+namespace {
+using clock_t_ = std::chrono::steady_clock;
+double ms_since(clock_t_::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clock_t_::now() - t0).count();
+}
+}  // namespace
+
+Handle::~Handle() {
+    if (host_scal) (void)hipHostFree(host_scal);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+}
+
+void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
+    d.nrows = h.nrows;
+    d.ncols = h.ncols;
+    d.nnz = h.nnz();
+    d.rp.alloc(h.nrows + 1);
+    d.ci.alloc(d.nnz);
+    d.val.alloc(d.nnz);
+    GIAMG_HIP(hipMemcpyAsync(d.rp.get(), h.rp.data(), (h.nrows + 1) * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
+    if (d.nnz) {
+        GIAMG_HIP(hipMemcpyAsync(d.ci.get(), h.ci.data(), d.nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        GIAMG_HIP(hipMemcpyAsync(d.val.get(), h.val.data(), d.nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (make32) make_fp32_values(d, s);
+    GIAMG_HIP(hipStreamSynchronize(s));
+}
+
+void download_csr(const DevCSR& d, HostCSR& h, hipStream_t s) {
+    h.nrows = d.nrows;
+    h.ncols = d.ncols;
+    h.rp.resize(d.nrows + 1);
+    h.ci.resize(d.nnz);
+    h.val.resize(d.nnz);
+    GIAMG_HIP(hipMemcpyAsync(h.rp.data(), d.rp.get(), (d.nrows + 1) * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+    if (d.nnz) {
+        GIAMG_HIP(hipMemcpyAsync(h.ci.data(), d.ci.get(), d.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GIAMG_HIP(hipMemcpyAsync(h.val.data(), d.val.get(), d.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    GIAMG_HIP(hipStreamSynchronize(s));
+}
+
+void make_fp32_values(DevCSR& d, hipStream_t s) {
+    d.val32.alloc(d.nnz);
+    launch_convert<double, float>(d.nnz, d.val.get(), d.val32.get(), s);
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+namespace {
+
+double device_dot(Handle& H, int64_t n, const double* a, const double* b) {
+    launch_dot_partial(n, a, b, H.partial.get(), H.stream);
+    launch_reduce(vec_blocks(n), H.partial.get(), 0, 1, H.scal.get() + S_TMP, H.stream);
+    GIAMG_HIP(hipMemcpyAsync(H.host_scal + S_TMP, H.scal.get() + S_TMP, sizeof(double),
+                             hipMemcpyDeviceToHost, H.stream));
+    GIAMG_HIP(hipStreamSynchronize(H.stream));
+    return H.host_scal[S_TMP];
+}
+
+// lambda_max(D^-1 A) by power iteration: w = D^-1 A v, estimate ||w||/||v||,
+// v <- w / ||w||.
+double power_estimate(Handle& H, Level& L) {
+    const int64_t n = L.n;
+    DevBuf<double> v(n), w(n);
+    launch_power_start(n, v.get(), H.stream);
+    double lam = 0.0;
+    for (int it = 0; it < H.opts.power_iters; ++it) {
+        SpmvArgs<double> a;
+        a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = L.A.val.get(); a.n = n;
+        a.v = v.get(); a.y = w.get(); a.dinv = L.dinv.get();
+        launch_spmv(SPMV_DINV, a, H.stream);
+        const double ww = std::sqrt(device_dot(H, n, w.get(), w.get()));
+        const double vv = std::sqrt(device_dot(H, n, v.get(), v.get()));
+        if (!(ww > 0.0) || !std::isfinite(ww)) throw Error(GIAMG_EINVAL, "power iteration failed");
+        lam = ww / vv;
+        launch_scale(n, 1.0 / ww, w.get(), v.get(), H.stream);
+    }
+    return lam;
+}
+
+__global__ void dinv_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const double* __restrict__ val, double* __restrict__ dinv,
+                            int* __restrict__ bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int64_t s = rp[i]; s < rp[i + 1]; ++s)
+            if (ci[s] == i) d = val[s];
+        if (!(d > 0.0)) *bad = 1;
+        dinv[i] = 1.0 / d;
+    }
+}
+
+void alloc_level_vectors(Level& L, bool mixed) {
+    const int64_t n = std::max<int64_t>(L.n, 1);
+    L.f.alloc(n); L.x.alloc(n); L.r.alloc(n); L.d0.alloc(n); L.d1.alloc(n); L.t.alloc(n);
+    if (mixed) {
+        L.f32.alloc(n); L.x32.alloc(n); L.r32.alloc(n); L.d032.alloc(n); L.d132.alloc(n); L.t32.alloc(n);
+    }
+}
+
+}  // namespace
+
+void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
+    const giamg_opts& o = H.opts;
+    const bool mixed = o.precision == GIAMG_PREC_MIXED;
+    const int64_t n = H.n_nodes, ne = H.n_elem;
+    auto t_all = clock_t_::now();
+    auto t0 = clock_t_::now();
+    // constrained nodes
+    if (o.bc == GIAMG_BC_DIRICHLET) {
+        H.constrained = boundary_mask(l2g, ne, H.porder, n);
+    } else {
+        H.constrained.assign(n, 0);
+        H.constrained[o.pin_node] = 1;
+    }
+    int64_t ncons = 0;
+    for (auto c : H.constrained) ncons += c;
+    GIAMG_REQUIRE(H.lambda > 0.0 || ncons > 0, "lambda = 0 needs at least one constrained node");
+    element_corners(coords, l2g, ne, H.porder, H.corners);
+    H.l2g.assign(l2g, l2g + ne * (int64_t)(H.porder + 1) * (H.porder + 1) * (H.porder + 1));
+    HostCSR A0 = assemble_fine(H.corners, l2g, ne, H.porder, n, H.lambda, H.constrained);
+    H.setup_ms[0] = ms_since(t0);
+
+    H.levels.clear();
+    H.levels.emplace_back();
+    {
+        Level& L = H.levels.back();
+        L.kind = GIAMG_LEVEL_P;
+        L.order = H.porder;
+        L.n = n;
+        L.l2g = H.l2g;
+        upload_csr(A0, L.A, H.stream, false);
+    }
+    A0 = HostCSR();
+    // p-levels
+    std::vector<uint8_t> free_mask(n);
+    for (int64_t i = 0; i < n; ++i) free_mask[i] = !H.constrained[i];
+    int order = H.porder;
+    while (order > 1 && (int)H.levels.size() < o.max_levels) {
+        int spf = 2;
+        while (spf * spf <= order && order % spf) ++spf;
+        if (order % spf) spf = order;
+        const int q = order / spf;
+        t0 = clock_t_::now();
+        std::vector<int32_t> l2g_next;
+        int64_t nc = 0;
+        Level& F = H.levels.back();
+        HostCSR P = p_transfer(F.l2g, ne, order, q, F.n, free_mask, l2g_next, nc);
+        H.setup_ms[1] += ms_since(t0);
+        if (nc == 0) break;
+        HostCSR R = transpose(P);
+        upload_csr(P, F.P, H.stream, mixed);
+        upload_csr(R, F.R, H.stream, mixed);
+        t0 = clock_t_::now();
+        DevCSR AP;
+        spgemm(F.A, F.P, AP, H.stream);
+        Level C;
+        C.kind = GIAMG_LEVEL_P;
+        C.order = q;
+        C.n = nc;
+        C.l2g = std::move(l2g_next);
+        spgemm(F.R, AP, C.A, H.stream);
+        H.setup_ms[3] += ms_since(t0);
+        H.levels.push_back(std::move(C));
+        free_mask.assign(nc, 1);
+        order = q;
+    }
+    // h-levels (smoothed aggregation) below order 1
+    while (H.levels.back().order == 1 && H.levels.back().n > o.coarse_max &&
+           (int)H.levels.size() < o.max_levels) {
+        Level& F = H.levels.back();
+        t0 = clock_t_::now();
+        HostCSR Ah;
+        download_csr(F.A, Ah, H.stream);
+        int64_t nagg = 0;
+        HostCSR P = sa_transfer(Ah, o.agg_seed, F.agg, nagg);
+        H.setup_ms[2] += ms_since(t0);
+        if (nagg >= F.n || nagg == 0) {
+            F.agg.clear();
+            break;
+        }
+        HostCSR R = transpose(P);
+        upload_csr(P, F.P, H.stream, mixed);
+        upload_csr(R, F.R, H.stream, mixed);
+        t0 = clock_t_::now();
+        DevCSR AP;
+        spgemm(F.A, F.P, AP, H.stream);
+        Level C;
+        C.kind = GIAMG_LEVEL_H;
+        C.order = 1;
+        C.n = nagg;
+        spgemm(F.R, AP, C.A, H.stream);
+        H.setup_ms[3] += ms_since(t0);
+        H.levels.push_back(std::move(C));
+    }
+    // coarsest: dense inverse through Cholesky
+    t0 = clock_t_::now();
+    {
+        Level& Lc = H.levels.back();
+        H.nc = Lc.n;
+        GIAMG_REQUIRE(H.nc <= 16384, "coarsest level too large for the dense solve");
+        HostCSR Ah;
+        download_csr(Lc.A, Ah, H.stream);
+        std::vector<double> dense(H.nc * H.nc, 0.0), inv;
+        for (int64_t i = 0; i < H.nc; ++i)
+            for (int64_t s = Ah.rp[i]; s < Ah.rp[i + 1]; ++s) dense[i * H.nc + Ah.ci[s]] = Ah.val[s];
+        if (H.nc > 0) {
+            if (!spd_inverse(dense, H.nc, inv))
+                throw Error(GIAMG_EINVAL, "coarsest operator is not positive definite");
+            H.coarse_inv.alloc(H.nc * H.nc);
+            GIAMG_HIP(hipMemcpyAsync(H.coarse_inv.get(), inv.data(), inv.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, H.stream));
+            GIAMG_HIP(hipStreamSynchronize(H.stream));
+        }
+    }
+    H.setup_ms[4] = ms_since(t0);
+    // work buffers
+    int64_t maxn = 1;
+    for (auto& L : H.levels) maxn = std::max(maxn, L.n);
+    H.partial_cap = std::max<int64_t>(2 * spmv_blocks(maxn), 2 * vec_blocks(maxn)) + 16;
+    H.partial.alloc(H.partial_cap);
+    H.scal.alloc(S_COUNT);
+    GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), H.stream));
+    if (!H.host_scal) GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&H.host_scal), S_COUNT * sizeof(double)));
+    // smoother data
+    t0 = clock_t_::now();
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+        Level& L = H.levels[l];
+        alloc_level_vectors(L, mixed);
+        if (mixed) make_fp32_values(L.A, H.stream);
+        if (l + 1 == H.levels.size()) break;
+        L.dinv.alloc(L.n);
+        DevBuf<int> bad(1);
+        GIAMG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), H.stream));
+        dinv_kernel<<<(unsigned)std::min<int64_t>((L.n + 255) / 256, 65536), 256, 0, H.stream>>>(
+            L.n, L.A.rp.get(), L.A.ci.get(), L.A.val.get(), L.dinv.get(), bad.get());
+        GIAMG_HIP(hipGetLastError());
+        int hbad = 0;
+        GIAMG_HIP(hipMemcpyAsync(&hbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, H.stream));
+        GIAMG_HIP(hipStreamSynchronize(H.stream));
+        if (hbad) throw Error(GIAMG_EINVAL, "non-positive diagonal on level " + std::to_string(l));
+        if (mixed) {
+            L.dinv32.alloc(L.n);
+            launch_convert<double, float>(L.n, L.dinv.get(), L.dinv32.get(), H.stream);
+        }
+        L.lam_hat = power_estimate(H, L);
+    }
+    H.setup_ms[5] = ms_since(t0);
+    const int64_t nn = std::max<int64_t>(n, 1);
+    H.x.alloc(nn); H.r.alloc(nn); H.z.alloc(nn); H.p.alloc(nn); H.q.alloc(nn); H.rold.alloc(nn);
+    H.tmp.alloc(nn);
+    if (!H.ev0) GIAMG_HIP(hipEventCreate(&H.ev0));
+    if (!H.ev1) GIAMG_HIP(hipEventCreate(&H.ev1));
+    GIAMG_HIP(hipStreamSynchronize(H.stream));
+    H.setup_ms[6] = ms_since(t_all);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T> struct LV;
+template <> struct LV<double> {
+    static const double* A(const Level& L) { return L.A.val.get(); }
+    static const double* P(const Level& L) { return L.P.val.get(); }
+    static const double* R(const Level& L) { return L.R.val.get(); }
+    static const double* dinv(const Level& L) { return L.dinv.get(); }
+    static double* f(Level& L) { return L.f.get(); }
+    static double* x(Level& L) { return L.x.get(); }
+    static double* r(Level& L) { return L.r.get(); }
+    static double* d0(Level& L) { return L.d0.get(); }
+    static double* d1(Level& L) { return L.d1.get(); }
+    static double* t(Level& L) { return L.t.get(); }
+};
+template <> struct LV<float> {
+    static const float* A(const Level& L) { return L.A.val32.get(); }
+    static const float* P(const Level& L) { return L.P.val32.get(); }
+    static const float* R(const Level& L) { return L.R.val32.get(); }
+    static const float* dinv(const Level& L) { return L.dinv32.get(); }
+    static float* f(Level& L) { return L.f32.get(); }
+    static float* x(Level& L) { return L.x32.get(); }
+    static float* r(Level& L) { return L.r32.get(); }
+    static float* d0(Level& L) { return L.d032.get(); }
+    static float* d1(Level& L) { return L.d132.get(); }
+    static float* t(Level& L) { return L.t32.get(); }
+};
+
+template <typename T>
+SpmvArgs<T> args_A(const Level& L) {
+    SpmvArgs<T> a;
+    a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = LV<T>::A(L); a.n = L.n;
+    a.dinv = LV<T>::dinv(L);
+    return a;
+}
+
+struct ChebCoef {
+    double inv_theta;
+    std::vector<double> c1, c2;   // per step j = 1..k-1
+};
+
+ChebCoef cheb_coef(const Handle& H, const Level& L) {
+    const double lo = H.opts.cheb_lo * L.lam_hat, hi = H.opts.cheb_hi * L.lam_hat;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    ChebCoef c;
+    c.inv_theta = 1.0 / theta;
+    double rho = 1.0 / sigma;
+    for (int j = 1; j < H.opts.degree; ++j) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        c.c1.push_back(rn * rho);
+        c.c2.push_back(2.0 * rn / delta);
+        rho = rn;
+    }
+    return c;
+}
+
+
+// Chebyshev acceleration of Jacobi (Saad, Algorithm 12.1, on D^-1 A):
+//   r_0 = D^-1 (f - A x_0), d_0 = r_0 / theta,
+//   x_{j+1} = x_j + d_j,
+//   r_{j+1} = r_j - D^-1 A d_j,
+//   d_{j+1} = rho_{j+1} rho_j d_j + (2 rho_{j+1} / delta) r_{j+1}.
+// The update of x by d_j is deferred into the next product's epilogue (the
+// product gathers d, never x), so no kernel reads and writes x at once.
+// zero_start: pre-smoothing from x = 0 (x is not read).
+template <typename T>
+void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
+    const int k = H.opts.degree;
+    const ChebCoef c = cheb_coef(H, L);
+    T* r = LV<T>::r(L);
+    T* d[2] = {LV<T>::d0(L), LV<T>::d1(L)};
+    if (zero_start) {
+        launch_cheb_init0<T>(L.n, f, LV<T>::dinv(L), r, d[0], x, (T)c.inv_theta, k == 1, H.stream);
+    } else {
+        SpmvArgs<T> a = args_A<T>(L);
+        a.v = x; a.f = f; a.r = r; a.y = d[0]; a.inv_theta = (T)c.inv_theta;
+        launch_spmv(SPMV_CHEB_INIT, a, H.stream);
+        if (k == 1) launch_add<T>(L.n, d[0], x, H.stream);
+    }
+    for (int j = 1; j < k; ++j) {
+        SpmvArgs<T> a = args_A<T>(L);
+        a.v = d[(j - 1) & 1]; a.y = d[j & 1]; a.r = r; a.x = x;
+        a.c1 = (T)c.c1[j - 1]; a.c2 = (T)c.c2[j - 1];
+        a.flags = (j == k - 1 ? CHEB_LAST : 0) | ((zero_start && j == 1) ? CHEB_ASSIGN : 0);
+        launch_spmv(SPMV_CHEB_STEP, a, H.stream);
+    }
+}
+
+// Weighted Jacobi x <- x + omega D^-1 (f - A x), ping-pong between x and d0.
+template <typename T>
+void smooth_jacobi(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
+    const int sweeps = H.opts.degree;
+    const T w = (T)H.opts.omega;
+    T* buf[2] = {x, LV<T>::d0(L)};
+    int cur = 0, start = 0;
+    if (zero_start) {
+        launch_jacobi0<T>(L.n, f, LV<T>::dinv(L), x, w, H.stream);
+        start = 1;
+    }
+    for (int s = start; s < sweeps; ++s) {
+        SpmvArgs<T> a = args_A<T>(L);
+        a.v = buf[cur]; a.y = buf[1 - cur]; a.f = f; a.omega = w;
+        launch_spmv(SPMV_JACOBI, a, H.stream);
+        cur = 1 - cur;
+    }
+    if (cur == 1) launch_copy<T>(L.n, buf[1], x, H.stream);
+}
+
+template <typename T>
+void smooth(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
+    if (H.opts.smoother == GIAMG_SMOOTHER_CHEBYSHEV)
+        smooth_chebyshev<T>(H, L, f, x, zero_start);
+    else
+        smooth_jacobi<T>(H, L, f, x, zero_start);
+}
+
+template <typename T>
+void residual(Handle& H, Level& L, const T* f, const T* x, T* out) {
+    SpmvArgs<T> a = args_A<T>(L);
+    a.v = x; a.f = f; a.y = out;
+    launch_spmv(SPMV_RESID, a, H.stream);
+}
+
+template <typename T>
+void restrict_to(Handle& H, Level& L, const T* r, T* fc) {
+    SpmvArgs<T> a;
+    a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
+    a.v = r; a.y = fc;
+    launch_spmv(SPMV_PLAIN, a, H.stream);
+}
+
+template <typename T>
+void prolong_add(Handle& H, Level& L, const T* ec, T* x) {
+    SpmvArgs<T> a;
+    a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
+    a.v = ec; a.y = x;
+    launch_spmv(SPMV_ADD, a, H.stream);
+}
+
+// Algorithm 1: one V-cycle from level l for right-hand side f, result in x.
+template <typename T>
+void vcycle(Handle& H, size_t l, const T* f, T* x) {
+    Level& L = H.levels[l];
+    if (l + 1 == H.levels.size()) {
+        launch_coarse_apply<T>(H.nc, H.coarse_inv.get(), f, x, H.stream);
+        return;
+    }
+    Level& C = H.levels[l + 1];
+    smooth<T>(H, L, f, x, true);
+    residual<T>(H, L, f, x, LV<T>::t(L));
+    restrict_to<T>(H, L, LV<T>::t(L), LV<T>::f(C));
+    vcycle<T>(H, l + 1, LV<T>::f(C), LV<T>::x(C));
+    prolong_add<T>(H, L, LV<T>::x(C), x);
+    smooth<T>(H, L, f, x, false);
+}
+
+void precondition(Handle& H, const double* r, double* z) {
+    if (H.opts.precision == GIAMG_PREC_MIXED) {
+        Level& L = H.levels[0];
+        launch_convert<double, float>(L.n, r, L.f32.get(), H.stream);
+        vcycle<float>(H, 0, L.f32.get(), L.x32.get());
+        launch_convert<float, double>(L.n, L.x32.get(), z, H.stream);
+    } else {
+        vcycle<double>(H, 0, r, z);
+    }
+}
+
+void fetch_scalars(Handle& H) {
+    GIAMG_HIP(hipMemcpyAsync(H.host_scal, H.scal.get(), S_COUNT * sizeof(double),
+                             hipMemcpyDeviceToHost, H.stream));
+    GIAMG_HIP(hipStreamSynchronize(H.stream));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// CG preconditioned by the V-cycle
+// ---------------------------------------------------------------------------
+int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
+    const int64_t n = H.n_nodes;
+    const Level& L0 = H.levels[0];
+    const bool flexible = H.opts.precision == GIAMG_PREC_MIXED;
+    hipStream_t s = H.stream;
+    const int64_t gs = spmv_blocks(n), gv = vec_blocks(n);
+    GIAMG_HIP(hipEventRecord(H.ev0, s));
+    GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), s));
+    launch_residual_init(n, L0.A.rp.get(), L0.A.ci.get(), L0.A.val.get(), b, x, H.r.get(),
+                         H.partial.get(), s);
+    launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
+    fetch_scalars(H);
+    const double bnorm = std::sqrt(H.host_scal[S_BB]);
+    int status = GIAMG_OK;
+    int iters = 0;
+    double relres = 0.0;
+    if (bnorm == 0.0) {
+        launch_fill(n, 0.0, x, s);
+    } else {
+        relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
+        if (!(relres < tol)) {
+            precondition(H, H.r.get(), H.z.get());
+            launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
+            launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s);
+            launch_pcg_beta(H.scal.get(), flexible, true, s);
+            launch_copy<double>(n, H.z.get(), H.p.get(), s);
+            status = GIAMG_ENOTCONV;
+            for (int k = 1; k <= H.opts.maxit; ++k) {
+                SpmvArgs<double> a;
+                a.rp = L0.A.rp.get(); a.ci = L0.A.ci.get(); a.val = L0.A.val.get(); a.n = n;
+                a.v = H.p.get(); a.y = H.q.get(); a.partial = H.partial.get();
+                launch_spmv(SPMV_DOT, a, s);
+                launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, s);
+                launch_pcg_alpha(H.scal.get(), s);
+                launch_pcg_update(n, x, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
+                                  H.q.get(), H.scal.get(), H.partial.get(), s);
+                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, s);
+                fetch_scalars(H);
+                if (H.host_scal[S_FLAG] != 0.0) {
+                    status = GIAMG_EBREAKDOWN;
+                    break;
+                }
+                iters = k;
+                relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
+                if (!std::isfinite(relres)) {
+                    status = GIAMG_EBREAKDOWN;
+                    break;
+                }
+                if (relres < tol) {
+                    status = GIAMG_OK;
+                    break;
+                }
+                precondition(H, H.r.get(), H.z.get());
+                if (flexible) {
+                    launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), s);
+                    launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, s);
+                } else {
+                    launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
+                    launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s);
+                }
+                launch_pcg_beta(H.scal.get(), flexible, false, s);
+                launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), s);
+            }
+        }
+    }
+    GIAMG_HIP(hipEventRecord(H.ev1, s));
+    // true residual at exit
+    launch_residual_init(n, L0.A.rp.get(), L0.A.ci.get(), L0.A.val.get(), b, x, H.tmp.get(),
+                         H.partial.get(), s);
+    launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
+    fetch_scalars(H);
+    if (info) {
+        float ms = 0.0f;
+        GIAMG_HIP(hipEventElapsedTime(&ms, H.ev0, H.ev1));
+        info->iters = iters;
+        info->status = status;
+        info->relres = relres;
+        info->true_relres = bnorm > 0 ? std::sqrt(H.host_scal[S_RR]) / bnorm : 0.0;
+        info->solve_ms = ms;
+    }
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// single steps for checking
+// ---------------------------------------------------------------------------
+namespace {
+template <typename T>
+void apply_t(Handle& H, int op, size_t l, const T* a, const T* b, T* out) {
+    Level& L = H.levels[l];
+    const bool last = l + 1 == H.levels.size();
+    switch (op) {
+        case GIAMG_OP_SPMV: {
+            SpmvArgs<T> s = args_A<T>(L);
+            s.v = a; s.y = out;
+            launch_spmv(SPMV_PLAIN, s, H.stream);
+            break;
+        }
+        case GIAMG_OP_RESIDUAL: residual<T>(H, L, a, b, out); break;
+        case GIAMG_OP_RESTRICT:
+            GIAMG_REQUIRE(!last, "no restriction on the coarsest level");
+            restrict_to<T>(H, L, a, out);
+            break;
+        case GIAMG_OP_PROLONG_ADD:
+            GIAMG_REQUIRE(!last, "no prolongation on the coarsest level");
+            prolong_add<T>(H, L, a, out);
+            break;
+        case GIAMG_OP_PRESMOOTH:
+            GIAMG_REQUIRE(!last, "no smoother on the coarsest level");
+            smooth<T>(H, L, a, out, true);
+            break;
+        case GIAMG_OP_POSTSMOOTH:
+            GIAMG_REQUIRE(!last, "no smoother on the coarsest level");
+            smooth<T>(H, L, a, out, false);
+            break;
+        case GIAMG_OP_COARSE:
+            GIAMG_REQUIRE(last, "direct solve only on the coarsest level");
+            launch_coarse_apply<T>(H.nc, H.coarse_inv.get(), a, out, H.stream);
+            break;
+        case GIAMG_OP_VCYCLE: vcycle<T>(H, l, a, out); break;
+        default: throw Error(GIAMG_EINVAL, "unknown operation");
+    }
+}
+}  // namespace
+
+void apply(Handle& H, int op, int level, const void* a, const void* b, void* out) {
+    GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
+    if (op & GIAMG_OP_FP32) {
+        GIAMG_REQUIRE(H.opts.precision == GIAMG_PREC_MIXED, "FP32 operators exist only in mixed mode");
+        apply_t<float>(H, op & ~GIAMG_OP_FP32, level, (const float*)a, (const float*)b, (float*)out);
+    } else {
+        apply_t<double>(H, op, level, (const double*)a, (const double*)b, (double*)out);
+    }
+    GIAMG_HIP(hipStreamSynchronize(H.stream));
+}
+
+}  // namespace giamg

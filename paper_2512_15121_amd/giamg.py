@@ -1,0 +1,331 @@
+"""Thin ctypes binding of ``libgiamg.so`` (the C ABI in include/giamg.h).
+
+Argument marshalling only: every step of the setup and solve runs inside the
+library.  PyTorch provides device memory (CUDA/HIP tensors) and the stream;
+results stay on the device.  The binding fails loudly when the library has
+not been built -- there is no fallback implementation.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, asdict
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgiamg.so")
+
+OK, ENOTCONV, EINVAL, ENOMEM, EHIP, EBREAKDOWN, ENOTSUP = 0, 1, -1, -2, -3, -4, -5
+SMOOTHER = {"chebyshev": 0, "jacobi": 1}
+BC = {"dirichlet": 0, "pin": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+LEVEL_KIND = {0: "p", 1: "h"}
+MAT = {"A": 0, "P": 1, "R": 2}
+OP = {"spmv": 0, "residual": 1, "restrict": 2, "prolong_add": 3, "presmooth": 4,
+      "postsmooth": 5, "coarse": 6, "vcycle": 7}
+OP_FP32 = 256
+
+
+class GiamgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"giamg error {code}: {msg}")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("smoother", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("coarse_max", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("pin_node", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("agg_seed", ctypes.c_uint64),
+                ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
+                ("cheb_hi", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+
+class _LevelDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("coarsest", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("nnz_A", ctypes.c_int64),
+                ("nnz_P", ctypes.c_int64), ("nnz_R", ctypes.c_int64),
+                ("lam_hat", ctypes.c_double)]
+
+
+@dataclass
+class Options:
+    smoother: str = "chebyshev"
+    degree: int = 2
+    omega: float = 2.0 / 3.0
+    coarse_max: int = 2000
+    max_levels: int = 10
+    bc: str = "dirichlet"
+    pin_node: int = 0
+    precision: str = "fp64"
+    maxit: int = 500
+    agg_seed: int = 0
+    power_iters: int = 20
+    cheb_lo: float = 0.1
+    cheb_hi: float = 1.1
+
+    def _c(self) -> _Opts:
+        d = asdict(self)
+        d["smoother"] = SMOOTHER[d["smoother"]]
+        d["bc"] = BC[d["bc"]]
+        d["precision"] = PRECISION[d["precision"]]
+        return _Opts(**d)
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    status: int
+    relres: float
+    true_relres: float
+    solve_ms: float
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGNATURES = {
+    "giamg_default_opts": (None, [ctypes.POINTER(_Opts)]),
+    "giamg_setup": (I32, [P, I64, P, I64, I32, F64, ctypes.POINTER(_Opts), P, ctypes.POINTER(P)]),
+    "giamg_free": (None, [P]),
+    "giamg_solve": (I32, [P, P, P, F64, ctypes.POINTER(_Info)]),
+    "giamg_solve_batch": (I32, [P, P, P, I32, F64, ctypes.POINTER(_Info)]),
+    "giamg_num_levels": (I32, [P]),
+    "giamg_level_describe": (I32, [P, I32, ctypes.POINTER(_LevelDesc)]),
+    "giamg_level_csr": (I32, [P, I32, I32, P, P, P]),
+    "giamg_level_l2g": (I32, [P, I32, P]),
+    "giamg_level_aggregates": (I32, [P, I32, P]),
+    "giamg_constrained": (I32, [P, P]),
+    "giamg_apply": (I32, [P, I32, I32, P, P, P]),
+    "giamg_quadrature_points": (I32, [P, P]),
+    "giamg_load_vector": (I32, [P, P, P]),
+    "giamg_setup_times": (I32, [P, P]),
+    "giamg_last_error": (ctypes.c_char_p, []),
+    "giamg_hcsr_size": (I32, [P, P, P, P]),
+    "giamg_hcsr_copy": (I32, [P, P, P, P]),
+    "giamg_hcsr_free": (None, [P]),
+    "giamg_host_boundary": (I32, [P, I64, I32, I64, P]),
+    "giamg_host_assemble": (I32, [P, I64, P, I64, I32, F64, I32, I64, ctypes.POINTER(P)]),
+    "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, P, P, ctypes.POINTER(P)]),
+    "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, P, P, ctypes.POINTER(P)]),
+}
+
+
+def library() -> ctypes.CDLL:
+    """Load libgiamg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc < 0 or rc == ENOTCONV:
+        msg = library().giamg_last_error().decode()
+        if rc < 0:
+            raise GiamgError(rc, msg)
+    return rc
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dev(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """GIAMG-PCG solver for A = K + lambda M on a hexahedral mesh.
+
+    coords: float64 [n_nodes, 3]; l2g: int32 [n_elem, (p+1)^3] in the tensor
+    ordering (p+1)^2 i + (p+1) j + k.  Device work runs on ``stream`` (a
+    torch.cuda.Stream, default: the current stream).
+    """
+
+    def __init__(self, coords, l2g, p, lam, opts: Options = None, stream=None):
+        import torch
+        self.lib = library()
+        self.opts = opts or Options()
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+        self.n_nodes = coords.shape[0]
+        self.n_elem = l2g.shape[0]
+        self.p = int(p)
+        self.stream = stream or torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        co = self.opts._c()
+        _check(self.lib.giamg_setup(_ptr(coords), self.n_nodes, _ptr(l2g), self.n_elem,
+                                    self.p, float(lam), ctypes.byref(co),
+                                    ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            self.lib.giamg_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- solves --------------------------------------------------------------
+    def solve(self, b, x=None, tol=1e-10):
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        info = _Info()
+        rc = self.lib.giamg_solve(self._h, _dev(b), _dev(x), float(tol), ctypes.byref(info))
+        _check(rc)
+        return x, SolveInfo(info.iters, info.status, info.relres, info.true_relres, info.solve_ms)
+
+    def solve_batch(self, B, X=None, tol=1e-10):
+        import torch
+        if X is None:
+            X = torch.zeros_like(B)
+        k = B.shape[1]
+        infos = (_Info * k)()
+        rc = self.lib.giamg_solve_batch(self._h, _dev(B), _dev(X), k, float(tol), infos)
+        _check(rc)
+        return X, [SolveInfo(i.iters, i.status, i.relres, i.true_relres, i.solve_ms) for i in infos]
+
+    # -- introspection -------------------------------------------------------
+    def num_levels(self) -> int:
+        return _check(self.lib.giamg_num_levels(self._h))
+
+    def level(self, l):
+        d = _LevelDesc()
+        _check(self.lib.giamg_level_describe(self._h, l, ctypes.byref(d)))
+        return {"kind": LEVEL_KIND[d.kind], "order": d.order, "coarsest": bool(d.coarsest),
+                "rows": d.rows, "nnz_A": d.nnz_A, "nnz_P": d.nnz_P, "nnz_R": d.nnz_R,
+                "lam_hat": d.lam_hat}
+
+    def level_csr(self, l, which="A"):
+        d = self.level(l)
+        if which == "A":
+            nr, nnz = d["rows"], d["nnz_A"]
+        elif which == "P":
+            nr, nnz = d["rows"], d["nnz_P"]
+        else:
+            nr, nnz = self.level(l + 1)["rows"], d["nnz_R"]
+        rp = np.zeros(nr + 1, dtype=np.int64)
+        ci = np.zeros(nnz, dtype=np.int32)
+        val = np.zeros(nnz, dtype=np.float64)
+        _check(self.lib.giamg_level_csr(self._h, l, MAT[which], _ptr(rp), _ptr(ci), _ptr(val)))
+        return rp, ci, val
+
+    def level_l2g(self, l):
+        d = self.level(l)
+        out = np.zeros((self.n_elem, (d["order"] + 1) ** 3), dtype=np.int32)
+        _check(self.lib.giamg_level_l2g(self._h, l, _ptr(out)))
+        return out
+
+    def level_aggregates(self, l):
+        out = np.zeros(self.level(l)["rows"], dtype=np.int32)
+        _check(self.lib.giamg_level_aggregates(self._h, l, _ptr(out)))
+        return out
+
+    def constrained(self):
+        out = np.zeros(self.n_nodes, dtype=np.uint8)
+        _check(self.lib.giamg_constrained(self._h, _ptr(out)))
+        return out.astype(bool)
+
+    def apply(self, op, level, a, b=None, out=None, fp32=False):
+        code = OP[op] | (OP_FP32 if fp32 else 0)
+        bp = _dev(b) if b is not None else ctypes.c_void_p()
+        _check(self.lib.giamg_apply(self._h, code, level, _dev(a), bp, _dev(out)))
+        return out
+
+    def quadrature_points(self):
+        nq = self.p + 2
+        xq = np.zeros((self.n_elem, nq ** 3, 3))
+        _check(self.lib.giamg_quadrature_points(self._h, _ptr(xq)))
+        return xq
+
+    def load_vector(self, fq):
+        fq = np.ascontiguousarray(fq, dtype=np.float64)
+        b = np.zeros(self.n_nodes)
+        _check(self.lib.giamg_load_vector(self._h, _ptr(fq), _ptr(b)))
+        return b
+
+    def setup_times(self):
+        ms = np.zeros(7)
+        _check(self.lib.giamg_setup_times(self._h, _ptr(ms)))
+        keys = ["assembly", "p_transfer", "aggregation", "galerkin", "coarsest", "smoother", "total"]
+        return dict(zip(keys, ms.tolist()))
+
+
+# ---- host-side setup steps (no GPU) ---------------------------------------
+def _take_hcsr(h):
+    lib = library()
+    rows, cols, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    try:
+        _check(lib.giamg_hcsr_size(h, ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(nnz)))
+        rp = np.zeros(rows.value + 1, dtype=np.int64)
+        ci = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        _check(lib.giamg_hcsr_copy(h, _ptr(rp), _ptr(ci), _ptr(val)))
+    finally:
+        lib.giamg_hcsr_free(h)
+    return rp, ci, val, (rows.value, cols.value)
+
+
+def host_boundary(l2g, p, n_nodes):
+    l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+    mask = np.zeros(n_nodes, dtype=np.uint8)
+    _check(library().giamg_host_boundary(_ptr(l2g), l2g.shape[0], p, n_nodes, _ptr(mask)))
+    return mask.astype(bool)
+
+
+def host_assemble(coords, l2g, p, lam, bc="dirichlet", pin_node=0):
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(library().giamg_host_assemble(_ptr(coords), coords.shape[0], _ptr(l2g), l2g.shape[0],
+                                         p, float(lam), BC[bc], pin_node, ctypes.byref(h)))
+    return _take_hcsr(h)
+
+
+def host_p_transfer(l2g, p, q, n_fine, free_mask):
+    l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+    fm = np.ascontiguousarray(free_mask, dtype=np.uint8)
+    nxt = np.zeros((l2g.shape[0], (q + 1) ** 3), dtype=np.int32)
+    nc = ctypes.c_int64()
+    h = ctypes.c_void_p()
+    _check(library().giamg_host_p_transfer(_ptr(l2g), l2g.shape[0], p, q, n_fine, _ptr(fm),
+                                           _ptr(nxt), ctypes.byref(nc), ctypes.byref(h)))
+    return nxt, nc.value, _take_hcsr(h)
+
+
+def host_aggregate(rp, ci, val, seed=0):
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    n = rp.size - 1
+    agg = np.zeros(n, dtype=np.int32)
+    na = ctypes.c_int64()
+    h = ctypes.c_void_p()
+    _check(library().giamg_host_aggregate(_ptr(rp), _ptr(ci), _ptr(val), n, seed, _ptr(agg),
+                                          ctypes.byref(na), ctypes.byref(h)))
+    return agg, na.value, _take_hcsr(h)

@@ -1,0 +1,88 @@
+"""Host-side setup stages of the library against the oracle (CPU only).
+
+Integer work bit-exact: constrained-node masks, CSR structures of A and P,
+next-level element maps, aggregates.  Floating point within the tolerances
+derived in the design doc: assembled values (different summation orders of the
+same quadrature) and transfer values.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import assembly, ptransfer, sa
+from paper_2512_15121_amd import giamg
+
+
+def _csr(rp, ci, val, shape):
+    return sp.csr_matrix((val, ci, rp), shape=shape)
+
+
+@pytest.mark.parametrize("n,p,pert", [(3, 2, 0.1), (2, 4, 0.2), (3, 3, 0.0), (2, 6, 0.15)])
+def test_boundary_mask_bitexact(n, p, pert):
+    m = synth.hex_mesh(n, p, perturb=pert, seed=1)
+    ref = assembly.boundary_nodes(m.l2g, p, m.n_nodes)
+    got = giamg.host_boundary(m.l2g, p, m.n_nodes)
+    assert np.array_equal(ref, got)
+
+
+@pytest.mark.parametrize("n,p,lam,bc", [(3, 2, 1.0, "dirichlet"), (2, 4, 10.0, "dirichlet"),
+                                        (3, 3, 0.0, "pin"), (2, 5, 0.3, "dirichlet"),
+                                        (1, 1, 1.0, "pin"), (4, 1, 2.0, "dirichlet")])
+def test_assembly_against_oracle(n, p, lam, bc):
+    m = synth.hex_mesh(n, p, perturb=0.15, seed=3)
+    A, _ = assembly.assemble(m.coords, m.l2g, p, lam, bc=bc)
+    rp, ci, val, shape = giamg.host_assemble(m.coords, m.l2g, p, lam, bc=bc)
+    assert np.array_equal(rp, A.indptr) and np.array_equal(ci, A.indices)
+    # |a_ij - a_ij^o| <= 1e-13 max|a|: both sides evaluate the same quadrature
+    scale = np.abs(A.data).max()
+    assert np.max(np.abs(val - A.data)) <= 1e-13 * scale
+    # bitwise symmetric on the library side as well
+    G = _csr(rp, ci, val, shape)
+    assert (G != G.T).nnz == 0
+
+
+def test_assembly_rejects_inverted_element():
+    m = synth.hex_mesh(2, 1)
+    l2g = m.l2g.copy()
+    l2g[0] = l2g[0][[4, 5, 6, 7, 0, 1, 2, 3]]   # mirror element 0 in x
+    with pytest.raises(giamg.GiamgError) as e:
+        giamg.host_assemble(m.coords, l2g, 1, 1.0)
+    assert "Jacobian" in str(e.value)
+
+
+@pytest.mark.parametrize("n,p,q,bc", [(3, 2, 1, "dirichlet"), (3, 4, 2, "dirichlet"),
+                                      (2, 6, 3, "dirichlet"), (2, 4, 2, "pin"), (3, 5, 1, "dirichlet")])
+def test_p_transfer_against_oracle(n, p, q, bc):
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=5)
+    cons = assembly.constrained_mask(m.l2g, p, m.n_nodes, bc, 0)
+    collect, l2g_nx, P = ptransfer.p_level(m.l2g, p, q, m.n_nodes, ~cons)
+    nxt, nc, (rp, ci, val, shape) = giamg.host_p_transfer(m.l2g, p, q, m.n_nodes, ~cons)
+    assert nc == collect.size and shape == P.shape
+    assert np.array_equal(nxt, l2g_nx)
+    assert np.array_equal(rp, P.indptr) and np.array_equal(ci, P.indices)
+    assert np.max(np.abs(val - P.data)) <= 1e-14
+    # second step on the coarse map (constrained entries are -1 there)
+    if q > 1:
+        r = ptransfer.p_schedule(q)[1]
+        free2 = np.ones(nc, dtype=bool)
+        c2, l2, P2 = ptransfer.p_level(l2g_nx, q, r, nc, free2)
+        nx2, nc2, (rp2, ci2, val2, _) = giamg.host_p_transfer(nxt, q, r, nc, free2)
+        assert nc2 == c2.size and np.array_equal(nx2, l2)
+        assert np.array_equal(rp2, P2.indptr) and np.array_equal(ci2, P2.indices)
+        assert np.max(np.abs(val2 - P2.data)) <= 1e-14
+
+
+@pytest.mark.parametrize("n,seed", [(7, 0), (9, 12345), (10, 2 ** 63 + 7)])
+def test_aggregation_against_oracle(n, seed):
+    m = synth.hex_mesh(n, 1, perturb=0.1, seed=4)
+    A, cons = assembly.assemble(m.coords, m.l2g, 1, 1.5)
+    free = np.nonzero(~cons)[0]
+    Af = A[free][:, free].tocsr()
+    Af.sort_indices()
+    agg_o, roots = sa.aggregate(Af, seed)
+    P_o, _, _ = sa.smoothed_prolongation(Af, agg_o, roots.size)
+    agg, na, (rp, ci, val, shape) = giamg.host_aggregate(Af.indptr, Af.indices, Af.data, seed)
+    assert na == roots.size and np.array_equal(agg, agg_o)
+    assert np.array_equal(rp, P_o.indptr) and np.array_equal(ci, P_o.indices)
+    assert np.max(np.abs(val - P_o.data)) <= 1e-15
