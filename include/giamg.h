@@ -85,6 +85,9 @@ typedef struct giamg_info {
     double  relres;        /* ||r_k|| / ||b|| of the recursively updated residual at exit */
     double  true_relres;   /* ||b - A x|| / ||b|| recomputed at exit, FP64 */
     double  solve_ms;      /* GPU time of the whole solve, HIP events on the handle's stream */
+    double  bytes;         /* algorithmic HBM bytes of every kernel the solve launched: each
+                              CSR operator, gathered vector and row-local vector counted once
+                              per launch */
 } giamg_info;
 
 /*
@@ -256,6 +259,25 @@ int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t
 int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const double* val,
                          int64_t n, uint64_t seed, int32_t* agg, int64_t* n_agg,
                          giamg_hcsr* P_out);
+
+/*
+ * giamg_time_kernel -- time one device kernel of a level in the launch
+ * configuration the solve uses: `reps` back-to-back launches between two
+ * HIP events on the handle's stream (contents of the level's work vectors
+ * are overwritten).  kernel:
+ *   GIAMG_KERNEL_CHEB_STEP  fused Chebyshev step on A_l (FP64; FP32 with GIAMG_OP_FP32)
+ *   GIAMG_KERNEL_SPMV       plain y = A_l v
+ *   GIAMG_KERNEL_RESTRICT   y = R_l v
+ *   GIAMG_KERNEL_PROLONG    x += P_l v
+ * ms receives the mean duration of one launch, bytes its algorithmic HBM
+ * bytes (CSR arrays, the gathered vector once, row-local vectors).
+ */
+#define GIAMG_KERNEL_CHEB_STEP 0
+#define GIAMG_KERNEL_SPMV      1
+#define GIAMG_KERNEL_RESTRICT  2
+#define GIAMG_KERNEL_PROLONG   3
+int giamg_time_kernel(giamg_handle h, int32_t kernel, int32_t level, int32_t reps,
+                      double* ms, double* bytes);
 
 /* Thread-local message of the last failing call on this thread. */
 const char* giamg_last_error(void);

@@ -20,6 +20,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g);
 int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info);
 int solve_batch(Handle& H, const double* B, double* X, int32_t k, double tol, giamg_info* infos);
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out);
+void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes);
 }  // namespace giamg
 
 namespace {
@@ -371,6 +372,16 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
         giamg::HostCSR P = giamg::sa_transfer(A, seed, a, *n_agg);
         std::memcpy(agg, a.data(), a.size() * sizeof(int32_t));
         *P_out = new giamg_hcsr_s{std::move(P)};
+        return GIAMG_OK;
+    });
+}
+
+int giamg_time_kernel(giamg_handle h, int32_t kernel, int32_t level, int32_t reps, double* ms,
+                      double* bytes) {
+    return guarded([&]() -> int {
+        bind_device(h);
+        GIAMG_REQUIRE(ms != nullptr && bytes != nullptr, "null output");
+        giamg::time_kernel(h->h, kernel, level, reps, ms, bytes);
         return GIAMG_OK;
     });
 }

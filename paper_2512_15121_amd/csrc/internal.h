@@ -127,6 +127,7 @@ struct Handle {
     int64_t partial_cap = 0;
     // batched state
     int32_t batch_k = 0;
+    double bytes = 0.0;               // algorithmic bytes of launched kernels
     double setup_ms[7] = {0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     ~Handle();

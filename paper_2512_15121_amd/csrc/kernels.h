@@ -36,6 +36,7 @@ struct SpmvArgs {
     double* partial = nullptr;
     T c1 = 0, c2 = 0, inv_theta = 0, omega = 0;
     int flags = 0;
+    int64_t nnz = 0, ncols = 0;   // host-side byte accounting only
 };
 
 template <typename T>

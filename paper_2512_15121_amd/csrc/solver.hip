@@ -318,7 +318,33 @@ SpmvArgs<T> args_A(const Level& L) {
     SpmvArgs<T> a;
     a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = LV<T>::A(L); a.n = L.n;
     a.dinv = LV<T>::dinv(L);
+    a.nnz = L.A.nnz; a.ncols = L.A.ncols;
     return a;
+}
+
+// Algorithmic HBM bytes of one product launch: the CSR arrays, the gathered
+// vector once, and the row-local vectors its epilogue reads and writes.
+template <typename T>
+double spmv_bytes(int mode, const SpmvArgs<T>& a) {
+    const double vb = sizeof(T);
+    double rows = 0;
+    switch (mode) {
+        case SPMV_PLAIN: rows = 1; break;             // y
+        case SPMV_RESID: rows = 2; break;             // f, y
+        case SPMV_ADD: rows = 2; break;               // y read + write
+        case SPMV_CHEB_INIT: rows = 4; break;         // f, dinv, r, d_new
+        case SPMV_CHEB_STEP: rows = (a.flags & CHEB_ASSIGN) ? 5 : 6; break;  // r rw, dinv, d_new, x (r)w
+        case SPMV_JACOBI: rows = 3; break;            // f, dinv, y
+        case SPMV_DOT: rows = 1; break;               // y
+        case SPMV_DINV: rows = 2; break;              // dinv, y
+    }
+    return (vb + 4.0) * a.nnz + 8.0 * (a.n + 1) + vb * a.ncols + rows * vb * a.n;
+}
+
+template <typename T>
+void run_spmv(Handle& H, int mode, const SpmvArgs<T>& a) {
+    H.bytes += spmv_bytes(mode, a);
+    launch_spmv(mode, a, H.stream);
 }
 
 struct ChebCoef {
@@ -357,19 +383,23 @@ void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
     T* r = LV<T>::r(L);
     T* d[2] = {LV<T>::d0(L), LV<T>::d1(L)};
     if (zero_start) {
+        H.bytes += (k == 1 ? 5.0 : 4.0) * sizeof(T) * L.n;
         launch_cheb_init0<T>(L.n, f, LV<T>::dinv(L), r, d[0], x, (T)c.inv_theta, k == 1, H.stream);
     } else {
         SpmvArgs<T> a = args_A<T>(L);
         a.v = x; a.f = f; a.r = r; a.y = d[0]; a.inv_theta = (T)c.inv_theta;
-        launch_spmv(SPMV_CHEB_INIT, a, H.stream);
-        if (k == 1) launch_add<T>(L.n, d[0], x, H.stream);
+        run_spmv(H, SPMV_CHEB_INIT, a);
+        if (k == 1) {
+            H.bytes += 3.0 * sizeof(T) * L.n;
+            launch_add<T>(L.n, d[0], x, H.stream);
+        }
     }
     for (int j = 1; j < k; ++j) {
         SpmvArgs<T> a = args_A<T>(L);
         a.v = d[(j - 1) & 1]; a.y = d[j & 1]; a.r = r; a.x = x;
         a.c1 = (T)c.c1[j - 1]; a.c2 = (T)c.c2[j - 1];
         a.flags = (j == k - 1 ? CHEB_LAST : 0) | ((zero_start && j == 1) ? CHEB_ASSIGN : 0);
-        launch_spmv(SPMV_CHEB_STEP, a, H.stream);
+        run_spmv(H, SPMV_CHEB_STEP, a);
     }
 }
 
@@ -381,16 +411,20 @@ void smooth_jacobi(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
     T* buf[2] = {x, LV<T>::d0(L)};
     int cur = 0, start = 0;
     if (zero_start) {
+        H.bytes += 3.0 * sizeof(T) * L.n;
         launch_jacobi0<T>(L.n, f, LV<T>::dinv(L), x, w, H.stream);
         start = 1;
     }
     for (int s = start; s < sweeps; ++s) {
         SpmvArgs<T> a = args_A<T>(L);
         a.v = buf[cur]; a.y = buf[1 - cur]; a.f = f; a.omega = w;
-        launch_spmv(SPMV_JACOBI, a, H.stream);
+        run_spmv(H, SPMV_JACOBI, a);
         cur = 1 - cur;
     }
-    if (cur == 1) launch_copy<T>(L.n, buf[1], x, H.stream);
+    if (cur == 1) {
+        H.bytes += 2.0 * sizeof(T) * L.n;
+        launch_copy<T>(L.n, buf[1], x, H.stream);
+    }
 }
 
 template <typename T>
@@ -405,23 +439,25 @@ template <typename T>
 void residual(Handle& H, Level& L, const T* f, const T* x, T* out) {
     SpmvArgs<T> a = args_A<T>(L);
     a.v = x; a.f = f; a.y = out;
-    launch_spmv(SPMV_RESID, a, H.stream);
+    run_spmv(H, SPMV_RESID, a);
 }
 
 template <typename T>
 void restrict_to(Handle& H, Level& L, const T* r, T* fc) {
     SpmvArgs<T> a;
     a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
+    a.nnz = L.R.nnz; a.ncols = L.R.ncols;
     a.v = r; a.y = fc;
-    launch_spmv(SPMV_PLAIN, a, H.stream);
+    run_spmv(H, SPMV_PLAIN, a);
 }
 
 template <typename T>
 void prolong_add(Handle& H, Level& L, const T* ec, T* x) {
     SpmvArgs<T> a;
     a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
+    a.nnz = L.P.nnz; a.ncols = L.P.ncols;
     a.v = ec; a.y = x;
-    launch_spmv(SPMV_ADD, a, H.stream);
+    run_spmv(H, SPMV_ADD, a);
 }
 
 // Algorithm 1: one V-cycle from level l for right-hand side f, result in x.
@@ -429,6 +465,7 @@ template <typename T>
 void vcycle(Handle& H, size_t l, const T* f, T* x) {
     Level& L = H.levels[l];
     if (l + 1 == H.levels.size()) {
+        H.bytes += 8.0 * H.nc * H.nc + 2.0 * sizeof(T) * H.nc;
         launch_coarse_apply<T>(H.nc, H.coarse_inv.get(), f, x, H.stream);
         return;
     }
@@ -444,6 +481,7 @@ void vcycle(Handle& H, size_t l, const T* f, T* x) {
 void precondition(Handle& H, const double* r, double* z) {
     if (H.opts.precision == GIAMG_PREC_MIXED) {
         Level& L = H.levels[0];
+        H.bytes += 24.0 * L.n;   // two conversions at the cycle boundary
         launch_convert<double, float>(L.n, r, L.f32.get(), H.stream);
         vcycle<float>(H, 0, L.f32.get(), L.x32.get());
         launch_convert<float, double>(L.n, L.x32.get(), z, H.stream);
@@ -469,8 +507,12 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     const bool flexible = H.opts.precision == GIAMG_PREC_MIXED;
     hipStream_t s = H.stream;
     const int64_t gs = spmv_blocks(n), gv = vec_blocks(n);
+    const double nnz0 = (double)L0.A.nnz;
+    const double spmv0 = 12.0 * nnz0 + 8.0 * (n + 1) + 8.0 * n;   // CSR + gathered vector
+    H.bytes = 0.0;
     GIAMG_HIP(hipEventRecord(H.ev0, s));
     GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), s));
+    H.bytes += spmv0 + 16.0 * n;
     launch_residual_init(n, L0.A.rp.get(), L0.A.ci.get(), L0.A.val.get(), b, x, H.r.get(),
                          H.partial.get(), s);
     launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
@@ -480,11 +522,13 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     int iters = 0;
     double relres = 0.0;
     if (bnorm == 0.0) {
+        H.bytes += 8.0 * n;
         launch_fill(n, 0.0, x, s);
     } else {
         relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
         if (!(relres < tol)) {
             precondition(H, H.r.get(), H.z.get());
+            H.bytes += 32.0 * n;
             launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
             launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s);
             launch_pcg_beta(H.scal.get(), flexible, true, s);
@@ -494,6 +538,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 SpmvArgs<double> a;
                 a.rp = L0.A.rp.get(); a.ci = L0.A.ci.get(); a.val = L0.A.val.get(); a.n = n;
                 a.v = H.p.get(); a.y = H.q.get(); a.partial = H.partial.get();
+                H.bytes += spmv0 + 8.0 * n + (flexible ? 56.0 : 48.0) * n;
                 launch_spmv(SPMV_DOT, a, s);
                 launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, s);
                 launch_pcg_alpha(H.scal.get(), s);
@@ -517,19 +562,23 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 }
                 precondition(H, H.r.get(), H.z.get());
                 if (flexible) {
+                    H.bytes += 24.0 * n;
                     launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), s);
                     launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, s);
                 } else {
+                    H.bytes += 16.0 * n;
                     launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
                     launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s);
                 }
                 launch_pcg_beta(H.scal.get(), flexible, false, s);
+                H.bytes += 24.0 * n;
                 launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), s);
             }
         }
     }
     GIAMG_HIP(hipEventRecord(H.ev1, s));
-    // true residual at exit
+    const double bytes = H.bytes;
+    // true residual at exit (outside the timed region)
     launch_residual_init(n, L0.A.rp.get(), L0.A.ci.get(), L0.A.val.get(), b, x, H.tmp.get(),
                          H.partial.get(), s);
     launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
@@ -542,8 +591,75 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
         info->relres = relres;
         info->true_relres = bnorm > 0 ? std::sqrt(H.host_scal[S_RR]) / bnorm : 0.0;
         info->solve_ms = ms;
+        info->bytes = bytes;
     }
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing in the solve's launch configuration
+// ---------------------------------------------------------------------------
+namespace {
+template <typename T>
+void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double* bytes) {
+    Level& L = H.levels[l];
+    const bool last = l + 1 == H.levels.size();
+    GIAMG_REQUIRE(kernel == GIAMG_KERNEL_SPMV || !last, "no transfer or smoother on the coarsest level");
+    SpmvArgs<T> a;
+    int mode = SPMV_PLAIN;
+    if (kernel == GIAMG_KERNEL_CHEB_STEP || kernel == GIAMG_KERNEL_SPMV) {
+        a = args_A<T>(L);
+        a.v = LV<T>::d0(L); a.y = LV<T>::d1(L);
+        if (kernel == GIAMG_KERNEL_CHEB_STEP) {
+            const ChebCoef c = cheb_coef(H, L);
+            mode = SPMV_CHEB_STEP;
+            a.r = LV<T>::r(L); a.x = LV<T>::x(L);
+            a.c1 = (T)(c.c1.empty() ? 0.0 : c.c1[0]);
+            a.c2 = (T)(c.c2.empty() ? 0.0 : c.c2[0]);
+            a.flags = 0;
+        }
+    } else if (kernel == GIAMG_KERNEL_RESTRICT) {
+        Level& C = H.levels[l + 1];
+        a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
+        a.nnz = L.R.nnz; a.ncols = L.R.ncols;
+        a.v = LV<T>::t(L); a.y = LV<T>::f(C);
+    } else if (kernel == GIAMG_KERNEL_PROLONG) {
+        Level& C = H.levels[l + 1];
+        mode = SPMV_ADD;
+        a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
+        a.nnz = L.P.nnz; a.ncols = L.P.ncols;
+        a.v = LV<T>::x(C); a.y = LV<T>::t(L);
+    } else {
+        throw Error(GIAMG_EINVAL, "unknown kernel");
+    }
+    // defined contents: zeros in every vector the kernel touches
+    for (T* v : {LV<T>::d0(L), LV<T>::d1(L), LV<T>::r(L), LV<T>::x(L), LV<T>::t(L)})
+        GIAMG_HIP(hipMemsetAsync(v, 0, L.n * sizeof(T), H.stream));
+    if (!last) {
+        Level& C = H.levels[l + 1];
+        GIAMG_HIP(hipMemsetAsync(LV<T>::x(C), 0, C.n * sizeof(T), H.stream));
+    }
+    launch_spmv(mode, a, H.stream);   // warm-up
+    GIAMG_HIP(hipEventRecord(H.ev0, H.stream));
+    for (int i = 0; i < reps; ++i) launch_spmv(mode, a, H.stream);
+    GIAMG_HIP(hipEventRecord(H.ev1, H.stream));
+    GIAMG_HIP(hipEventSynchronize(H.ev1));
+    float t = 0.0f;
+    GIAMG_HIP(hipEventElapsedTime(&t, H.ev0, H.ev1));
+    *ms = (double)t / reps;
+    *bytes = spmv_bytes(mode, a);
+}
+}  // namespace
+
+void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes) {
+    GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
+    GIAMG_REQUIRE(reps >= 1, "reps must be >= 1");
+    if (kernel & GIAMG_OP_FP32) {
+        GIAMG_REQUIRE(H.opts.precision == GIAMG_PREC_MIXED, "FP32 operators exist only in mixed mode");
+        time_kernel_t<float>(H, kernel & ~GIAMG_OP_FP32, level, reps, ms, bytes);
+    } else {
+        time_kernel_t<double>(H, kernel, level, reps, ms, bytes);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -558,7 +674,7 @@ void apply_t(Handle& H, int op, size_t l, const T* a, const T* b, T* out) {
         case GIAMG_OP_SPMV: {
             SpmvArgs<T> s = args_A<T>(L);
             s.v = a; s.y = out;
-            launch_spmv(SPMV_PLAIN, s, H.stream);
+            run_spmv(H, SPMV_PLAIN, s);
             break;
         }
         case GIAMG_OP_RESIDUAL: residual<T>(H, L, a, b, out); break;

@@ -44,7 +44,7 @@ class _Opts(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
-                ("solve_ms", ctypes.c_double)]
+                ("solve_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class _LevelDesc(ctypes.Structure):
@@ -86,6 +86,7 @@ class SolveInfo:
     relres: float
     true_relres: float
     solve_ms: float
+    bytes: float
 
 
 _lib = None
@@ -116,7 +117,9 @@ _SIGNATURES = {
     "giamg_host_assemble": (I32, [P, I64, P, I64, I32, F64, I32, I64, ctypes.POINTER(P)]),
     "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, P, P, ctypes.POINTER(P)]),
     "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, P, P, ctypes.POINTER(P)]),
+    "giamg_time_kernel": (I32, [P, I32, I32, I32, P, P]),
 }
+KERNEL = {"cheb_step": 0, "spmv": 1, "restrict": 2, "prolong": 3}
 
 
 def library() -> ctypes.CDLL:
@@ -198,7 +201,7 @@ class Solver:
         info = _Info()
         rc = self.lib.giamg_solve(self._h, _dev(b), _dev(x), float(tol), ctypes.byref(info))
         _check(rc)
-        return x, SolveInfo(info.iters, info.status, info.relres, info.true_relres, info.solve_ms)
+        return x, SolveInfo(info.iters, info.status, info.relres, info.true_relres, info.solve_ms, info.bytes)
 
     def solve_batch(self, B, X=None, tol=1e-10):
         import torch
@@ -208,7 +211,7 @@ class Solver:
         infos = (_Info * k)()
         rc = self.lib.giamg_solve_batch(self._h, _dev(B), _dev(X), k, float(tol), infos)
         _check(rc)
-        return X, [SolveInfo(i.iters, i.status, i.relres, i.true_relres, i.solve_ms) for i in infos]
+        return X, [SolveInfo(i.iters, i.status, i.relres, i.true_relres, i.solve_ms, i.bytes) for i in infos]
 
     # -- introspection -------------------------------------------------------
     def num_levels(self) -> int:
@@ -268,6 +271,13 @@ class Solver:
         b = np.zeros(self.n_nodes)
         _check(self.lib.giamg_load_vector(self._h, _ptr(fq), _ptr(b)))
         return b
+
+    def time_kernel(self, kernel, level=0, reps=20, fp32=False):
+        """Mean duration (ms) and algorithmic bytes of one launch."""
+        ms, by = np.zeros(1), np.zeros(1)
+        code = KERNEL[kernel] | (OP_FP32 if fp32 else 0)
+        _check(self.lib.giamg_time_kernel(self._h, code, level, reps, _ptr(ms), _ptr(by)))
+        return float(ms[0]), float(by[0])
 
     def setup_times(self):
         ms = np.zeros(7)

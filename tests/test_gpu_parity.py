@@ -1,0 +1,279 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bars (derivations in DESIGN.md, "Tolerances"):
+* integer work bit-exact: constrained mask, every level's CSR structure of
+  A, P and R, next-level element maps, aggregates;
+* assembled/Galerkin values: max |a - a_o| <= 1e-12 max |a_o| per level;
+* lambda_max estimate: relative 1e-6;
+* one product: |y - y_o|_i <= 64 eps (|A| |x|)_i;
+* smoothing, V-cycle: ||y - y_o|| <= 1e-11 ||y_o||;
+* FP64 solve at 1e-10: CG iterations within +-1, ||x - x_o|| <= 1e-9 ||x_o||;
+  with a fixed iteration count (tol = 0) the same bound on x.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import hierarchy, krylov, cycle, smoothers, assembly
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2512_15121_amd import giamg
+    giamg.library()            # fails loudly if the HIP library is missing
+    return torch, torch.device("cuda:0")
+
+
+CASES = {
+    # name: (n, p, lam, smoother, perturb, coarse_max, bc)
+    "cfg1_4x4x4_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet"),
+    "p4_6cube_cheb_sa": (6, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet"),
+    "p6_4cube_cheb": (4, 6, 0.5, "chebyshev", 0.1, 2000, "dirichlet"),
+    "p5_7cube_ragged": (7, 5, 3.0, "chebyshev", 0.1, 300, "dirichlet"),
+    "p3_pin_neumann": (5, 3, 0.0, "chebyshev", 0.1, 100, "pin"),
+}
+
+_cache = {}
+
+
+def _case(name):
+    if name not in _cache:
+        n, p, lam, sm, pert, cm, bc = CASES[name]
+        m = synth.hex_mesh(n, p, perturb=pert, seed=2)
+        H = hierarchy.build(m.coords, m.l2g, p, lam,
+                            hierarchy.Options(smoother=sm, coarse_max=cm, bc=bc))
+        _cache[name] = (m, H)
+    return _cache[name]
+
+
+def _solver(name, precision="fp64", **kw):
+    from paper_2512_15121_amd import Solver, Options
+    n, p, lam, sm, pert, cm, bc = CASES[name]
+    m, _ = _case(name)
+    return Solver(m.coords, m.l2g, p, lam,
+                  Options(smoother=sm, coarse_max=cm, bc=bc, precision=precision, **kw))
+
+
+def _to(torch, dev, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(dev)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_bitexact_structure_and_values(torch_dev, name):
+    m, H = _case(name)
+    s = _solver(name)
+    assert s.num_levels() == len(H.levels)
+    assert np.array_equal(s.constrained(), H.constrained)
+    for l, lv in enumerate(H.levels):
+        d = s.level(l)
+        assert d["rows"] == lv.A.shape[0]
+        is_h = l > 0 and H.levels[l - 1].agg is not None
+        assert d["kind"] == ("h" if is_h else "p") and d["order"] == lv.order
+        rp, ci, val = s.level_csr(l, "A")
+        assert np.array_equal(rp, lv.A.indptr) and np.array_equal(ci, lv.A.indices), f"A{l}"
+        assert np.max(np.abs(val - lv.A.data)) <= 1e-12 * np.max(np.abs(lv.A.data)), f"A{l}"
+        if l + 1 < len(H.levels):
+            for which, M in (("P", lv.P), ("R", lv.R)):
+                rp, ci, val = s.level_csr(l, which)
+                assert np.array_equal(rp, M.indptr) and np.array_equal(ci, M.indices), f"{which}{l}"
+                assert np.max(np.abs(val - M.data)) <= 1e-12 * np.max(np.abs(M.data)), f"{which}{l}"
+            assert abs(d["lam_hat"] - lv.lam_hat) <= 1e-6 * lv.lam_hat
+            if lv.agg is not None:
+                assert np.array_equal(s.level_aggregates(l), lv.agg)
+        if lv.l2g is not None and l > 0:
+            assert np.array_equal(s.level_l2g(l), lv.l2g)
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "p3_pin_neumann", "cfg1_4x4x4_p2_jacobi"])
+def test_each_vcycle_step(torch_dev, name):
+    torch, dev = torch_dev
+    m, H = _case(name)
+    s = _solver(name)
+    rng = np.random.default_rng(3)
+    for l, lv in enumerate(H.levels):
+        n = lv.A.shape[0]
+        f = rng.standard_normal(n)
+        x = rng.standard_normal(n)
+        ft, xt = _to(torch, dev, f), _to(torch, dev, x)
+        out = torch.zeros(n, dtype=torch.float64, device=dev)
+        absA = abs(lv.A)
+        # product and residual
+        s.apply("spmv", l, xt, out=out)
+        bound = 64 * EPS * (absA @ np.abs(x)) + 1e-300
+        assert np.all(np.abs(out.cpu().numpy() - lv.A @ x) <= bound)
+        s.apply("residual", l, ft, xt, out=out)
+        assert np.all(np.abs(out.cpu().numpy() - (f - lv.A @ x)) <= bound + 64 * EPS * np.abs(f))
+        if l + 1 == len(H.levels):
+            s.apply("coarse", l, ft, out=out)
+            ref = cycle.coarse_solve(lv, f)
+            assert np.linalg.norm(out.cpu().numpy() - ref) <= 1e-11 * np.linalg.norm(ref)
+            continue
+        nc = H.levels[l + 1].A.shape[0]
+        outc = torch.zeros(nc, dtype=torch.float64, device=dev)
+        s.apply("restrict", l, ft, out=outc)
+        ref = lv.R @ f
+        assert np.all(np.abs(outc.cpu().numpy() - ref) <= 64 * EPS * (abs(lv.R) @ np.abs(f)) + 1e-300)
+        ec = rng.standard_normal(nc)
+        y = xt.clone()
+        s.apply("prolong_add", l, _to(torch, dev, ec), out=y)
+        ref = x + lv.P @ ec
+        assert np.all(np.abs(y.cpu().numpy() - ref) <= 64 * EPS * (np.abs(x) + abs(lv.P) @ np.abs(ec)))
+        # smoothing from zero and from an iterate
+        s.apply("presmooth", l, ft, out=out)
+        ref = cycle.smooth(H, lv, f, None)
+        assert np.linalg.norm(out.cpu().numpy() - ref) <= 1e-11 * np.linalg.norm(ref)
+        y = xt.clone()
+        s.apply("postsmooth", l, ft, out=y)
+        ref = cycle.smooth(H, lv, f, x)
+        assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-11 * np.linalg.norm(ref)
+        # the whole cycle from this level
+        s.apply("vcycle", l, ft, out=out)
+        ref = cycle.vcycle(H, f, l)
+        assert np.linalg.norm(out.cpu().numpy() - ref) <= 1e-11 * np.linalg.norm(ref)
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_solve_parity(torch_dev, name):
+    torch, dev = torch_dev
+    m, H = _case(name)
+    b = synth.normal_rhs(m.n_nodes, 12)
+    if CASES[name][6] == "pin":
+        b = synth.pinned_normal_batch(m.n_nodes, 1, 14)[:, 0].copy()
+    s = _solver(name)
+    x, info = s.solve(_to(torch, dev, b), tol=1e-10)
+    ref = krylov.giamg_pcg(H, b, tol=1e-10)
+    assert info.status == 0 and ref.converged
+    assert abs(info.iters - ref.iters) <= 1
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    assert info.true_relres < 1e-9
+    # fixed iteration count: the stopping boundary plays no part
+    k = min(info.iters, ref.iters)
+    from paper_2512_15121_amd import Solver, Options
+    n_, p, lam, sm, pert, cm, bc = CASES[name]
+    s2 = Solver(m.coords, m.l2g, p, lam, Options(smoother=sm, coarse_max=cm, bc=bc, maxit=k))
+    x2, info2 = s2.solve(_to(torch, dev, b), tol=0.0)
+    ref2 = krylov.giamg_pcg(H, b, tol=0.0, maxit=k)
+    assert info2.iters == k == ref2.iters
+    assert np.linalg.norm(x2.cpu().numpy() - ref2.x) <= 1e-9 * np.linalg.norm(ref2.x)
+    assert abs(info2.relres - ref2.history[-1]) <= 1e-6 * ref2.history[-1]
+    s.close()
+    s2.close()
+
+
+def test_cfg1_manufactured_rhs_and_load_vector(torch_dev):
+    torch, dev = torch_dev
+    name = "cfg1_4x4x4_p2_jacobi"
+    m, H = _case(name)
+    s = _solver(name)
+    xq = s.quadrature_points()
+    xq_o = assembly.quadrature_points(m.coords, m.l2g, 2)
+    assert np.max(np.abs(xq - xq_o)) <= 1e-15
+    lam = CASES[name][2]
+    fq = (lam + 3 * math.pi ** 2) * np.prod(np.sin(math.pi * xq), axis=2)
+    b = s.load_vector(fq)
+    b_o = assembly.load_vector(m.coords, m.l2g, 2, fq, H.constrained)
+    assert np.max(np.abs(b - b_o)) <= 1e-14 * np.max(np.abs(b_o))
+    x, info = s.solve(_to(torch, dev, b), tol=1e-10)
+    ref = krylov.giamg_pcg(H, b_o, tol=1e-10)
+    assert abs(info.iters - ref.iters) <= 1
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    s.close()
+
+
+def test_mixed_precision_solve(torch_dev):
+    torch, dev = torch_dev
+    name = "p4_6cube_cheb_sa"
+    m, H = _case(name)
+    b = synth.normal_rhs(m.n_nodes, 12)
+    s = _solver(name, precision="mixed")
+    x, info = s.solve(_to(torch, dev, b), tol=1e-10)
+    ref = krylov.giamg_pcg(H, b, tol=1e-10)
+    assert info.status == 0 and info.true_relres < 1e-9
+    err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+    assert err <= 1e-8, err
+    # FP32 product of the fine operator: rounding bound (m + 2) 2^-24 (|A||x|)_i
+    rng = np.random.default_rng(1)
+    lv = H.levels[0]
+    xv = rng.standard_normal(lv.A.shape[0])
+    out = torch.zeros(lv.A.shape[0], dtype=torch.float32, device=dev)
+    s.apply("spmv", 0, _to(torch, dev, xv, torch.float32), out=out, fp32=True)
+    mrow = np.diff(lv.A.indptr)
+    bound = (mrow + 2) * 2.0 ** -24 * (abs(lv.A) @ np.abs(xv))
+    assert np.all(np.abs(out.cpu().numpy().astype(np.float64) - lv.A @ xv) <= bound)
+    s.close()
+
+
+def test_edge_cases(torch_dev):
+    torch, dev = torch_dev
+    from paper_2512_15121_amd import Solver, Options, giamg
+    name = "cfg1_4x4x4_p2_jacobi"
+    m, H = _case(name)
+    s = _solver(name)
+    n = m.n_nodes
+    # zero right-hand side: x = 0 without iterating
+    x, info = s.solve(torch.zeros(n, dtype=torch.float64, device=dev),
+                      torch.ones(n, dtype=torch.float64, device=dev))
+    assert info.iters == 0 and torch.count_nonzero(x).item() == 0
+    # initial guess already the solution
+    b = synth.normal_rhs(n, 5)
+    ref = krylov.giamg_pcg(H, b, tol=1e-13)
+    x, info = s.solve(_to(torch, dev, b), _to(torch, dev, ref.x), tol=1e-10)
+    assert info.iters == 0
+    # non-finite right-hand side: breakdown, reported
+    bad = b.copy()
+    bad[3] = np.nan
+    with pytest.raises(giamg.GiamgError) as e:
+        s.solve(_to(torch, dev, bad))
+    assert e.value.code == giamg.EBREAKDOWN
+    s.close()
+    # iteration cap: a warning code, the last iterate returned
+    s1 = Solver(m.coords, m.l2g, 2, 1.0, Options(smoother="jacobi", maxit=1))
+    x, info = s1.solve(_to(torch, dev, b))
+    assert info.status == giamg.ENOTCONV and info.iters == 1
+    s1.close()
+    # single element of order 2: one free node, one level
+    m1 = synth.hex_mesh(1, 2)
+    s2 = Solver(m1.coords, m1.l2g, 2, 1.0)
+    assert s2.num_levels() == 1
+    b1 = synth.normal_rhs(m1.n_nodes, 1)
+    x, info = s2.solve(_to(torch, dev, b1))
+    H1 = hierarchy.build(m1.coords, m1.l2g, 2, 1.0)
+    assert np.allclose(x.cpu().numpy(), np.linalg.solve(H1.levels[0].A.toarray(), b1), rtol=1e-12)
+    s2.close()
+    # order 1 small enough to be the coarsest level itself
+    m3 = synth.hex_mesh(3, 1, perturb=0.1, seed=1)
+    s3 = Solver(m3.coords, m3.l2g, 1, 2.0)
+    assert s3.num_levels() == 1
+    s3.close()
+    # bad geometry is rejected with a message
+    l2g = m.l2g.copy()
+    l2g[0] = l2g[0][::-1]
+    with pytest.raises(giamg.GiamgError):
+        Solver(m.coords, l2g, 2, 1.0)
+
+
+def test_determinism(torch_dev):
+    torch, dev = torch_dev
+    name = "p5_7cube_ragged"
+    m, H = _case(name)
+    b = _to(torch, dev, synth.normal_rhs(m.n_nodes, 3))
+    s = _solver(name)
+    x1, i1 = s.solve(b)
+    x2, i2 = s.solve(b)
+    assert i1.iters == i2.iters and torch.equal(x1, x2)
+    s.close()
