@@ -86,7 +86,12 @@ struct DevCSR {
     DevBuf<int32_t> ci;
     DevBuf<double> val;
     DevBuf<float> val32;
+    DevBuf<int64_t> rblk;   // row blocks of the streaming product kernel
+    int64_t nblk = 0;
+    int lanes = 64;
 };
+// Build the row blocks of d from a host copy of its row pointers.
+void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
 
 // ---- the hierarchy ----------------------------------------------------------
 struct Level {

@@ -15,7 +15,12 @@ enum SpmvMode : int {
     SPMV_JACOBI = 5,     // y = v + omega dinv (f - A v)   (v = x_old, y = x_new)
     SPMV_DOT = 6,        // y = A v, block partials of v . y
     SPMV_DINV = 7,       // y = dinv A v
+    SPMV_RINIT = 8,      // y = f - A v, block partials of f . f and y . y
 };
+
+// Nonzeros one block stages in LDS; rows longer than this get a block each.
+constexpr int SPMV_CAP = 4096;
+constexpr int SPMV_THREADS = 512;
 
 // flags of SPMV_CHEB_STEP
 constexpr int CHEB_ASSIGN = 1;   // x = d_old (+ d_new) instead of x += ...
@@ -36,13 +41,17 @@ struct SpmvArgs {
     double* partial = nullptr;
     T c1 = 0, c2 = 0, inv_theta = 0, omega = 0;
     int flags = 0;
-    int64_t nnz = 0, ncols = 0;   // host-side byte accounting only
+    const int64_t* rblk = nullptr;   // row-block boundaries (nblk + 1 entries)
+    int64_t nblk = 0;
+    int lanes = 64;                  // lanes that reduce one row
+    int64_t nnz = 0, ncols = 0;      // host-side byte accounting only
 };
 
 template <typename T>
 void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s);
-// number of block partials SPMV_DOT writes for n rows
-int64_t spmv_blocks(int64_t n);
+// Greedy row blocking of a CSR operator: consecutive rows while their
+// nonzeros fit SPMV_CAP; the reduction width follows the mean row length.
+void make_row_blocks(const int64_t* rp, int64_t n, std::vector<int64_t>& blocks, int& lanes);
 
 // row-local kernels
 template <typename T>
@@ -65,8 +74,10 @@ int64_t vec_blocks(int64_t n);
 void launch_dot_partial(int64_t n, const double* a, const double* b, double* partial, hipStream_t s);
 void launch_dot2_partial(int64_t n, const double* a, const double* b, const double* c,
                          double* partial, hipStream_t s);  // a.b and c.b
+// CG scalar finalisations applied after a reduction (see ScalarSlot)
+enum FinishKind : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA_FIRST = 2, FIN_BETA = 3, FIN_BETA_FLEX = 4 };
 void launch_reduce(int64_t m, const double* partial, int64_t stride, int ncomp, double* out,
-                   hipStream_t s);
+                   hipStream_t s, int fin = 0, double* scal = nullptr);
 
 // PCG / FCG vector kernels
 // device scalar slots; (S_BB, S_RR) and (S_RZNEW, S_ZROLD) are written as pairs
@@ -77,11 +88,6 @@ enum ScalarSlot : int {
 void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const double* p,
                        const double* q, const double* scal, double* partial, hipStream_t s);
 void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s);
-void launch_pcg_alpha(double* scal, hipStream_t s);                 // alpha = rz / pq, flag
-void launch_pcg_beta(double* scal, bool flexible, bool first, hipStream_t s);
-void launch_residual_init(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
-                          const double* b, const double* x, double* r, double* partial,
-                          hipStream_t s);  // r = b - A x; partials of b.b, r.r
 void launch_power_start(int64_t n, double* v, hipStream_t s);
 void launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
 

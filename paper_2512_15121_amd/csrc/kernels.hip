@@ -3,9 +3,10 @@
 // The solve is HBM-bound sparse work: CSR products of the level operators
 // (Algorithm 1: smoothing, residual, restriction, prolongation), vector
 // updates and dot products of CG.  Design:
-//  * one 64-lane wavefront per row, rows of a block contiguous, CSR values
-//    and column indices streamed with non-temporal loads so the cache keeps
-//    the gathered vector;
+//  * a block streams a contiguous run of up to 4096 nonzeros (whole rows)
+//    with coalesced non-temporal loads, so the cache keeps the gathered
+//    vector, stages the products in LDS and reduces each row with a lane
+//    group sized to the operator's mean row length;
 //  * blocks remapped so each of the eight XCDs works on a contiguous slice
 //    of rows (its L2 then holds the slice of the gathered vector);
 //  * every smoother/CG vector update fused into the product's row epilogue;
@@ -20,12 +21,10 @@
 namespace giamg {
 
 constexpr int WAVE = 64;
-constexpr int SPMV_WAVES = 4;                   // waves per block
-constexpr int SPMV_RPW = 4;                     // consecutive rows per wave
-constexpr int SPMV_ROWS = SPMV_WAVES * SPMV_RPW;
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_MAX_BLOCKS = 2048;
 constexpr int RED_THREADS = 1024;
+constexpr int64_t SPMV_MAX_ROWS = SPMV_THREADS;   // rows per block
 
 // Hardware dispatches block b to XCD (b mod 8).  Logical block ids are
 // reassigned so that each XCD receives one contiguous range.
@@ -41,99 +40,234 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// sum over aligned groups of L lanes; every lane of the group gets the sum
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-int64_t spmv_blocks(int64_t n) { return (n + SPMV_ROWS - 1) / SPMV_ROWS; }
-
-// Row-sum of the CSR product for one row, all lanes receive the result.
-template <typename T>
-__device__ __forceinline__ T row_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                     const T* __restrict__ val, const T* __restrict__ v,
-                                     int64_t row, int lane) {
-    const int64_t s = rp[row], e = rp[row + 1];
-    T acc0 = 0, acc1 = 0;
-    int64_t j = s + lane;
-    for (; j + WAVE < e; j += 2 * WAVE) {
-        const int32_t c0 = ldnt(ci + j), c1 = ldnt(ci + j + WAVE);
-        const T a0 = ldnt(val + j), a1 = ldnt(val + j + WAVE);
-        acc0 += a0 * v[c0];
-        acc1 += a1 * v[c1];
+void make_row_blocks(const int64_t* rp, int64_t n, std::vector<int64_t>& blocks, int& lanes) {
+    blocks.clear();
+    blocks.push_back(0);
+    int64_t acc = 0, rows = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t len = rp[r + 1] - rp[r];
+        if (rows > 0 && (acc + len > SPMV_CAP || rows == SPMV_MAX_ROWS)) {
+            blocks.push_back(r);
+            acc = 0;
+            rows = 0;
+        }
+        acc += len;
+        ++rows;
     }
-    if (j < e) acc0 += ldnt(val + j) * v[ldnt(ci + j)];
-    return wave_sum(acc0 + acc1);
+    if (n > 0) blocks.push_back(n);
+    const double mean = n > 0 ? (double)rp[n] / (double)n : 0.0;
+    lanes = mean > 24 ? 16 : mean > 6 ? 4 : 1;
+}
+
+// Row-local operands of an epilogue, loaded before the row sum is known.
+template <typename T>
+struct RowIn {
+    T f, dinv, r, x, v, y;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void epilogue_load(const SpmvArgs<T>& a, int64_t row, RowIn<T>& in) {
+    if constexpr (MODE == SPMV_RESID || MODE == SPMV_CHEB_INIT || MODE == SPMV_JACOBI ||
+                  MODE == SPMV_RINIT)
+        in.f = a.f[row];
+    if constexpr (MODE == SPMV_CHEB_INIT || MODE == SPMV_CHEB_STEP || MODE == SPMV_JACOBI ||
+                  MODE == SPMV_DINV)
+        in.dinv = a.dinv[row];
+    if constexpr (MODE == SPMV_CHEB_STEP) {
+        in.r = a.r[row];
+        in.x = (a.flags & CHEB_ASSIGN) ? T(0) : a.x[row];
+    }
+    if constexpr (MODE == SPMV_CHEB_STEP || MODE == SPMV_JACOBI || MODE == SPMV_DOT)
+        in.v = a.v[row];
+    if constexpr (MODE == SPMV_ADD) in.y = a.y[row];
+}
+
+// Row epilogue: y is (A v)_row.  `dot` collects this row's share of a block
+// partial (DOT: v.y; RINIT: f.f in dot, y.y in dot2).
+template <typename T, int MODE>
+__device__ __forceinline__ void epilogue_store(const SpmvArgs<T>& a, int64_t row, T y,
+                                               const RowIn<T>& in, double& dot, double& dot2) {
+    if constexpr (MODE == SPMV_PLAIN) {
+        a.y[row] = y;
+    } else if constexpr (MODE == SPMV_RESID) {
+        a.y[row] = in.f - y;
+    } else if constexpr (MODE == SPMV_ADD) {
+        a.y[row] = in.y + y;
+    } else if constexpr (MODE == SPMV_CHEB_INIT) {
+        const T res = in.dinv * (in.f - y);
+        a.r[row] = res;
+        a.y[row] = res * a.inv_theta;
+    } else if constexpr (MODE == SPMV_CHEB_STEP) {
+        const T rr = in.r - in.dinv * y;
+        const T dn = a.c1 * in.v + a.c2 * rr;
+        a.r[row] = rr;
+        a.y[row] = dn;
+        const T inc = (a.flags & CHEB_LAST) ? in.v + dn : in.v;
+        a.x[row] = in.x + inc;
+    } else if constexpr (MODE == SPMV_JACOBI) {
+        a.y[row] = in.v + a.omega * in.dinv * (in.f - y);
+    } else if constexpr (MODE == SPMV_DOT) {
+        a.y[row] = y;
+        dot += (double)in.v * (double)y;
+    } else if constexpr (MODE == SPMV_DINV) {
+        a.y[row] = in.dinv * y;
+    } else if constexpr (MODE == SPMV_RINIT) {
+        const T ri = in.f - y;
+        a.y[row] = ri;
+        dot += (double)in.f * (double)in.f;
+        dot2 += (double)ri * (double)ri;
+    }
+}
+
+template <int MODE>
+constexpr bool has_partials() { return MODE == SPMV_DOT || MODE == SPMV_RINIT; }
+
+// Fixed-order block sum of two values per thread; red holds 2*SPMV_THREADS.
+__device__ __forceinline__ void block_sum2(double* red, int tid, double a, double b) {
+    red[tid] = a;
+    red[SPMV_THREADS + tid] = b;
+    __syncthreads();
+    for (int o = SPMV_THREADS / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            red[tid] += red[tid + o];
+            red[SPMV_THREADS + tid] += red[SPMV_THREADS + tid + o];
+        }
+        __syncthreads();
+    }
+}
+
+// Streaming CSR product.  A block owns a run of at most SPMV_THREADS whole
+// rows whose nonzeros (at most SPMV_CAP = 8 per thread) are contiguous:
+//  0. thread t prefetches the row-local operands of row r0 + t;
+//  1. every thread issues its eight column/value loads at once (coalesced,
+//     non-temporal), gathers the vector and stages the products in LDS;
+//  2. groups of L lanes sum the rows from LDS in a fixed order;
+//  3. thread t finishes row r0 + t (coalesced row-local stores).
+// A row longer than SPMV_CAP has a block of its own, summed straight from
+// memory by the whole block.
+template <typename T, int MODE, int L>
+__global__ void __launch_bounds__(SPMV_THREADS) spmv_stream_kernel(SpmvArgs<T> a) {
+    constexpr int PER = SPMV_CAP / SPMV_THREADS;
+    __shared__ T prod[SPMV_CAP];
+    __shared__ T rowsum[SPMV_THREADS];
+    double* red = reinterpret_cast<double*>(prod);   // reused once products are consumed
+    const int tid = threadIdx.x;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t r0 = a.rblk[lb], r1 = a.rblk[lb + 1];
+    const int64_t base = a.rp[r0];
+    const int64_t cnt = a.rp[r1] - base;
+    const int32_t* __restrict__ ci = a.ci + base;
+    const T* __restrict__ val = a.val + base;
+    const T* __restrict__ v = a.v;
+    double dot = 0.0, dot2 = 0.0;
+    if (cnt > SPMV_CAP) {
+        // one long row: block-wide strided sum, fixed-order tree
+        RowIn<T> in{};
+        if (tid == 0) epilogue_load<T, MODE>(a, r0, in);
+        T acc0 = 0, acc1 = 0;
+        int64_t i = tid;
+        for (; i + SPMV_THREADS < cnt; i += 2 * SPMV_THREADS) {
+            const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + SPMV_THREADS);
+            const T a0 = ldnt(val + i), a1 = ldnt(val + i + SPMV_THREADS);
+            acc0 += a0 * v[c0];
+            acc1 += a1 * v[c1];
+        }
+        if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
+        block_sum2(red, tid, (double)(acc0 + acc1), 0.0);
+        const T y = (T)red[0];
+        __syncthreads();
+        if (tid == 0) {
+            epilogue_store<T, MODE>(a, r0, y, in, dot, dot2);
+            if constexpr (has_partials<MODE>()) {
+                a.partial[lb] = dot;
+                if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
+            }
+        }
+        return;
+    }
+    const int nrows = (int)(r1 - r0);
+    const int n = (int)cnt;
+    // 0. row-local operands of this thread's row
+    RowIn<T> in{};
+    const bool own = tid < nrows;
+    if (own) epilogue_load<T, MODE>(a, r0 + tid, in);
+    // 1. stream the nonzeros: all loads first, then the gathers
+    int32_t c[PER];
+    T av[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = tid + k * SPMV_THREADS;
+        if (idx < n) {
+            c[k] = ldnt(ci + idx);
+            av[k] = ldnt(val + idx);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = tid + k * SPMV_THREADS;
+        if (idx < n) prod[idx] = av[k] * v[c[k]];
+    }
+    __syncthreads();
+    // 2. row sums, L lanes per row
+    const int g = tid / L, gl = tid % L;
+    for (int rr = g; rr < nrows; rr += SPMV_THREADS / L) {
+        const int s = (int)(a.rp[r0 + rr] - base), e = (int)(a.rp[r0 + rr + 1] - base);
+        T acc = 0;
+        for (int j = s + gl; j < e; j += L) acc += prod[j];
+        acc = group_sum<L>(acc);
+        if (gl == 0) rowsum[rr] = acc;
+    }
+    __syncthreads();
+    // 3. row epilogues
+    if (own) epilogue_store<T, MODE>(a, r0 + tid, rowsum[tid], in, dot, dot2);
+    if constexpr (has_partials<MODE>()) {
+        block_sum2(red, tid, dot, dot2);
+        if (tid == 0) {
+            a.partial[lb] = red[0];
+            if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = red[SPMV_THREADS];
+        }
+    }
 }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(SPMV_WAVES* WAVE) spmv_kernel(SpmvArgs<T> a) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x / WAVE;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t row0 = (lb * SPMV_WAVES + wave) * SPMV_RPW;
-    double dot = 0.0;
-    for (int k = 0; k < SPMV_RPW; ++k) {
-        const int64_t row = row0 + k;
-        if (row >= a.n) break;
-        const T y = row_dot(a.rp, a.ci, a.val, a.v, row, lane);
-        if (lane == 0) {
-            if constexpr (MODE == SPMV_PLAIN) {
-                a.y[row] = y;
-            } else if constexpr (MODE == SPMV_RESID) {
-                a.y[row] = a.f[row] - y;
-            } else if constexpr (MODE == SPMV_ADD) {
-                a.y[row] += y;
-            } else if constexpr (MODE == SPMV_CHEB_INIT) {
-                const T res = a.dinv[row] * (a.f[row] - y);
-                a.r[row] = res;
-                a.y[row] = res * a.inv_theta;
-            } else if constexpr (MODE == SPMV_CHEB_STEP) {
-                const T rr = a.r[row] - a.dinv[row] * y;
-                const T dold = a.v[row];
-                const T dn = a.c1 * dold + a.c2 * rr;
-                a.r[row] = rr;
-                a.y[row] = dn;
-                const T inc = (a.flags & CHEB_LAST) ? dold + dn : dold;
-                if (a.flags & CHEB_ASSIGN)
-                    a.x[row] = inc;
-                else
-                    a.x[row] += inc;
-            } else if constexpr (MODE == SPMV_JACOBI) {
-                a.y[row] = a.v[row] + a.omega * a.dinv[row] * (a.f[row] - y);
-            } else if constexpr (MODE == SPMV_DOT) {
-                a.y[row] = y;
-                dot += (double)a.v[row] * (double)y;
-            } else if constexpr (MODE == SPMV_DINV) {
-                a.y[row] = a.dinv[row] * y;
-            }
-        }
-    }
-    if constexpr (MODE == SPMV_DOT) {
-        __shared__ double red[SPMV_WAVES];
-        if (lane == 0) red[wave] = dot;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < SPMV_WAVES; ++w) s += red[w];
-            a.partial[lb] = s;
-        }
+void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
+    switch (a.lanes) {
+        case 64: spmv_stream_kernel<T, MODE, 64><<<grid, block, 0, s>>>(a); break;
+        case 16: spmv_stream_kernel<T, MODE, 16><<<grid, block, 0, s>>>(a); break;
+        case 4: spmv_stream_kernel<T, MODE, 4><<<grid, block, 0, s>>>(a); break;
+        case 1: spmv_stream_kernel<T, MODE, 1><<<grid, block, 0, s>>>(a); break;
+        default: throw Error(GIAMG_EINVAL, "unsupported reduction width");
     }
 }
 
 template <typename T>
 void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s) {
-    if (a.n <= 0) return;
-    const dim3 grid((unsigned)spmv_blocks(a.n)), block(SPMV_WAVES * WAVE);
+    if (a.n <= 0 || a.nblk <= 0) return;
+    if (a.rblk == nullptr) throw Error(GIAMG_EINVAL, "operator without row blocks");
     switch (mode) {
-        case SPMV_PLAIN: spmv_kernel<T, SPMV_PLAIN><<<grid, block, 0, s>>>(a); break;
-        case SPMV_RESID: spmv_kernel<T, SPMV_RESID><<<grid, block, 0, s>>>(a); break;
-        case SPMV_ADD: spmv_kernel<T, SPMV_ADD><<<grid, block, 0, s>>>(a); break;
-        case SPMV_CHEB_INIT: spmv_kernel<T, SPMV_CHEB_INIT><<<grid, block, 0, s>>>(a); break;
-        case SPMV_CHEB_STEP: spmv_kernel<T, SPMV_CHEB_STEP><<<grid, block, 0, s>>>(a); break;
-        case SPMV_JACOBI: spmv_kernel<T, SPMV_JACOBI><<<grid, block, 0, s>>>(a); break;
-        case SPMV_DOT: spmv_kernel<T, SPMV_DOT><<<grid, block, 0, s>>>(a); break;
-        case SPMV_DINV: spmv_kernel<T, SPMV_DINV><<<grid, block, 0, s>>>(a); break;
+        case SPMV_PLAIN: launch_spmv_mode<T, SPMV_PLAIN>(a, s); break;
+        case SPMV_RESID: launch_spmv_mode<T, SPMV_RESID>(a, s); break;
+        case SPMV_ADD: launch_spmv_mode<T, SPMV_ADD>(a, s); break;
+        case SPMV_CHEB_INIT: launch_spmv_mode<T, SPMV_CHEB_INIT>(a, s); break;
+        case SPMV_CHEB_STEP: launch_spmv_mode<T, SPMV_CHEB_STEP>(a, s); break;
+        case SPMV_JACOBI: launch_spmv_mode<T, SPMV_JACOBI>(a, s); break;
+        case SPMV_DOT: launch_spmv_mode<T, SPMV_DOT>(a, s); break;
+        case SPMV_DINV: launch_spmv_mode<T, SPMV_DINV>(a, s); break;
+        case SPMV_RINIT: launch_spmv_mode<T, SPMV_RINIT>(a, s); break;
         default: throw Error(GIAMG_EINVAL, "unknown product mode");
     }
     GIAMG_HIP(hipGetLastError());
@@ -345,10 +479,34 @@ void launch_dot2_partial(int64_t n, const double* a, const double* b, const doub
     GIAMG_HIP(hipGetLastError());
 }
 
-// out[c] = sum_{i<m} partial[c*stride + i] for c < ncomp, fixed order.
+// out[c] = sum_{i<m} partial[c*stride + i] for c < ncomp, fixed order; then
+// thread 0 applies the CG scalar update `fin` to the scalar block.
+__device__ void cg_finish(int fin, double* scal) {
+    if (fin == FIN_ALPHA) {
+        const double pq = scal[S_PQ];
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(scal[S_RZ])) {
+            scal[S_FLAG] = 1.0;
+            scal[S_ALPHA] = 0.0;
+        } else {
+            scal[S_ALPHA] = scal[S_RZ] / pq;
+        }
+    } else if (fin == FIN_BETA_FIRST || fin == FIN_BETA || fin == FIN_BETA_FLEX) {
+        const double rzn = scal[S_RZNEW];
+        if (fin == FIN_BETA_FIRST)
+            scal[S_BETA] = 0.0;
+        else if (fin == FIN_BETA_FLEX)
+            scal[S_BETA] = (rzn - scal[S_ZROLD]) / scal[S_RZ];
+        else
+            scal[S_BETA] = rzn / scal[S_RZ];
+        if (!isfinite(rzn)) scal[S_FLAG] = 1.0;
+        scal[S_RZ] = rzn;
+    }
+}
+
 __global__ void __launch_bounds__(RED_THREADS) reduce_kernel(int64_t m, const double* __restrict__ partial,
                                                              int64_t stride, int ncomp,
-                                                             double* __restrict__ out) {
+                                                             double* out, int fin,
+                                                             double* scal) {   // out may lie inside scal
     __shared__ double sh[RED_THREADS];
     for (int c = 0; c < ncomp; ++c) {
         double s = 0.0;
@@ -356,10 +514,14 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_kernel(int64_t m, const do
         s = block_sum<RED_THREADS>(s, sh);
         if (threadIdx.x == 0) out[c] = s;
     }
+    if (fin != FIN_NONE && threadIdx.x == 0) {
+        __threadfence_block();
+        cg_finish(fin, scal);
+    }
 }
 void launch_reduce(int64_t m, const double* partial, int64_t stride, int ncomp, double* out,
-                   hipStream_t s) {
-    reduce_kernel<<<1, RED_THREADS, 0, s>>>(m, partial, stride, ncomp, out);
+                   hipStream_t s, int fin, double* scal) {
+    reduce_kernel<<<1, RED_THREADS, 0, s>>>(m, partial, stride, ncomp, out, fin, scal);
     GIAMG_HIP(hipGetLastError());
 }
 
@@ -403,83 +565,6 @@ __global__ void pcg_direction_kernel(int64_t n, const double* __restrict__ z, do
 }
 void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s) {
     pcg_direction_kernel<<<vgrid(n), VEC_THREADS, 0, s>>>(n, z, p, scal);
-    GIAMG_HIP(hipGetLastError());
-}
-
-__global__ void pcg_alpha_kernel(double* scal) {
-    const double pq = scal[S_PQ];
-    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(scal[S_RZ])) {
-        scal[S_FLAG] = 1.0;
-        scal[S_ALPHA] = 0.0;
-    } else {
-        scal[S_ALPHA] = scal[S_RZ] / pq;
-    }
-}
-void launch_pcg_alpha(double* scal, hipStream_t s) {
-    pcg_alpha_kernel<<<1, 1, 0, s>>>(scal);
-    GIAMG_HIP(hipGetLastError());
-}
-
-__global__ void pcg_beta_kernel(double* scal, int flexible, int first) {
-    const double rzn = scal[S_RZNEW];
-    if (first) {
-        scal[S_BETA] = 0.0;
-    } else if (flexible) {
-        scal[S_BETA] = (rzn - scal[S_ZROLD]) / scal[S_RZ];
-    } else {
-        scal[S_BETA] = rzn / scal[S_RZ];
-    }
-    if (!isfinite(rzn)) scal[S_FLAG] = 1.0;
-    scal[S_RZ] = rzn;
-}
-void launch_pcg_beta(double* scal, bool flexible, bool first, hipStream_t s) {
-    pcg_beta_kernel<<<1, 1, 0, s>>>(scal, flexible ? 1 : 0, first ? 1 : 0);
-    GIAMG_HIP(hipGetLastError());
-}
-
-// r = b - A x with block partials of b.b (first half) and r.r (second half)
-__global__ void __launch_bounds__(SPMV_WAVES* WAVE) residual_init_kernel(
-    int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-    const double* __restrict__ val, const double* __restrict__ b, const double* __restrict__ x,
-    double* __restrict__ r, double* __restrict__ partial) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x / WAVE;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t row0 = (lb * SPMV_WAVES + wave) * SPMV_RPW;
-    double bb = 0.0, rr = 0.0;
-    for (int k = 0; k < SPMV_RPW; ++k) {
-        const int64_t row = row0 + k;
-        if (row >= n) break;
-        const double y = row_dot(rp, ci, val, x, row, lane);
-        if (lane == 0) {
-            const double bi = b[row];
-            const double ri = bi - y;
-            r[row] = ri;
-            bb += bi * bi;
-            rr += ri * ri;
-        }
-    }
-    __shared__ double red[2][SPMV_WAVES];
-    if (lane == 0) {
-        red[0][wave] = bb;
-        red[1][wave] = rr;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int w = 0; w < SPMV_WAVES; ++w) {
-            s0 += red[0][w];
-            s1 += red[1][w];
-        }
-        partial[lb] = s0;
-        partial[gridDim.x + lb] = s1;
-    }
-}
-void launch_residual_init(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
-                          const double* b, const double* x, double* r, double* partial,
-                          hipStream_t s) {
-    residual_init_kernel<<<(unsigned)spmv_blocks(n), SPMV_WAVES * WAVE, 0, s>>>(n, rp, ci, val, b, x,
-                                                                                r, partial);
     GIAMG_HIP(hipGetLastError());
 }
 

@@ -32,6 +32,16 @@ Handle::~Handle() {
     if (ev1) (void)hipEventDestroy(ev1);
 }
 
+void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
+    std::vector<int64_t> blocks;
+    make_row_blocks(rp.data(), d.nrows, blocks, d.lanes);
+    d.nblk = (int64_t)blocks.size() - 1;
+    d.rblk.alloc(blocks.size());
+    GIAMG_HIP(hipMemcpyAsync(d.rblk.get(), blocks.data(), blocks.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
+}
+
 void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
     d.nrows = h.nrows;
     d.ncols = h.ncols;
@@ -46,7 +56,7 @@ void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
         GIAMG_HIP(hipMemcpyAsync(d.val.get(), h.val.data(), d.nnz * sizeof(double), hipMemcpyHostToDevice, s));
     }
     if (make32) make_fp32_values(d, s);
-    GIAMG_HIP(hipStreamSynchronize(s));
+    setup_row_blocks(d, h.rp, s);
 }
 
 void download_csr(const DevCSR& d, HostCSR& h, hipStream_t s) {
@@ -93,6 +103,7 @@ double power_estimate(Handle& H, Level& L) {
     for (int it = 0; it < H.opts.power_iters; ++it) {
         SpmvArgs<double> a;
         a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = L.A.val.get(); a.n = n;
+        a.rblk = L.A.rblk.get(); a.nblk = L.A.nblk; a.lanes = L.A.lanes;
         a.v = v.get(); a.y = w.get(); a.dinv = L.dinv.get();
         launch_spmv(SPMV_DINV, a, H.stream);
         const double ww = std::sqrt(device_dot(H, n, w.get(), w.get()));
@@ -242,9 +253,12 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     }
     H.setup_ms[4] = ms_since(t0);
     // work buffers
-    int64_t maxn = 1;
-    for (auto& L : H.levels) maxn = std::max(maxn, L.n);
-    H.partial_cap = std::max<int64_t>(2 * spmv_blocks(maxn), 2 * vec_blocks(maxn)) + 16;
+    int64_t maxn = 1, maxblk = 1;
+    for (auto& L : H.levels) {
+        maxn = std::max(maxn, L.n);
+        maxblk = std::max({maxblk, L.A.nblk, L.P.nblk, L.R.nblk});
+    }
+    H.partial_cap = std::max<int64_t>(2 * maxblk, 2 * vec_blocks(maxn)) + 16;
     H.partial.alloc(H.partial_cap);
     H.scal.alloc(S_COUNT);
     GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), H.stream));
@@ -319,6 +333,7 @@ SpmvArgs<T> args_A(const Level& L) {
     a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = LV<T>::A(L); a.n = L.n;
     a.dinv = LV<T>::dinv(L);
     a.nnz = L.A.nnz; a.ncols = L.A.ncols;
+    a.rblk = L.A.rblk.get(); a.nblk = L.A.nblk; a.lanes = L.A.lanes;
     return a;
 }
 
@@ -447,6 +462,7 @@ void restrict_to(Handle& H, Level& L, const T* r, T* fc) {
     SpmvArgs<T> a;
     a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
     a.nnz = L.R.nnz; a.ncols = L.R.ncols;
+    a.rblk = L.R.rblk.get(); a.nblk = L.R.nblk; a.lanes = L.R.lanes;
     a.v = r; a.y = fc;
     run_spmv(H, SPMV_PLAIN, a);
 }
@@ -456,6 +472,7 @@ void prolong_add(Handle& H, Level& L, const T* ec, T* x) {
     SpmvArgs<T> a;
     a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
     a.nnz = L.P.nnz; a.ncols = L.P.ncols;
+    a.rblk = L.P.rblk.get(); a.nblk = L.P.nblk; a.lanes = L.P.lanes;
     a.v = ec; a.y = x;
     run_spmv(H, SPMV_ADD, a);
 }
@@ -506,15 +523,21 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     const Level& L0 = H.levels[0];
     const bool flexible = H.opts.precision == GIAMG_PREC_MIXED;
     hipStream_t s = H.stream;
-    const int64_t gs = spmv_blocks(n), gv = vec_blocks(n);
+    const int64_t gs = L0.A.nblk, gv = vec_blocks(n);
+    auto rinit = [&](double* out) {
+        SpmvArgs<double> a;
+        a.rp = L0.A.rp.get(); a.ci = L0.A.ci.get(); a.val = L0.A.val.get(); a.n = n;
+        a.rblk = L0.A.rblk.get(); a.nblk = L0.A.nblk; a.lanes = L0.A.lanes;
+        a.v = x; a.f = b; a.y = out; a.partial = H.partial.get();
+        launch_spmv(SPMV_RINIT, a, s);
+    };
     const double nnz0 = (double)L0.A.nnz;
     const double spmv0 = 12.0 * nnz0 + 8.0 * (n + 1) + 8.0 * n;   // CSR + gathered vector
     H.bytes = 0.0;
     GIAMG_HIP(hipEventRecord(H.ev0, s));
     GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), s));
     H.bytes += spmv0 + 16.0 * n;
-    launch_residual_init(n, L0.A.rp.get(), L0.A.ci.get(), L0.A.val.get(), b, x, H.r.get(),
-                         H.partial.get(), s);
+    rinit(H.r.get());
     launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
     fetch_scalars(H);
     const double bnorm = std::sqrt(H.host_scal[S_BB]);
@@ -530,18 +553,18 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             precondition(H, H.r.get(), H.z.get());
             H.bytes += 32.0 * n;
             launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
-            launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s);
-            launch_pcg_beta(H.scal.get(), flexible, true, s);
+            launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
+                          H.scal.get());
             launch_copy<double>(n, H.z.get(), H.p.get(), s);
             status = GIAMG_ENOTCONV;
             for (int k = 1; k <= H.opts.maxit; ++k) {
                 SpmvArgs<double> a;
                 a.rp = L0.A.rp.get(); a.ci = L0.A.ci.get(); a.val = L0.A.val.get(); a.n = n;
+                a.rblk = L0.A.rblk.get(); a.nblk = L0.A.nblk; a.lanes = L0.A.lanes;
                 a.v = H.p.get(); a.y = H.q.get(); a.partial = H.partial.get();
                 H.bytes += spmv0 + 8.0 * n + (flexible ? 56.0 : 48.0) * n;
                 launch_spmv(SPMV_DOT, a, s);
-                launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, s);
-                launch_pcg_alpha(H.scal.get(), s);
+                launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, s, FIN_ALPHA, H.scal.get());
                 launch_pcg_update(n, x, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
                                   H.q.get(), H.scal.get(), H.partial.get(), s);
                 launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, s);
@@ -564,13 +587,14 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 if (flexible) {
                     H.bytes += 24.0 * n;
                     launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), s);
-                    launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, s);
+                    launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, s, FIN_BETA_FLEX,
+                                  H.scal.get());
                 } else {
                     H.bytes += 16.0 * n;
                     launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
-                    launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s);
+                    launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA,
+                                  H.scal.get());
                 }
-                launch_pcg_beta(H.scal.get(), flexible, false, s);
                 H.bytes += 24.0 * n;
                 launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), s);
             }
@@ -579,8 +603,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     GIAMG_HIP(hipEventRecord(H.ev1, s));
     const double bytes = H.bytes;
     // true residual at exit (outside the timed region)
-    launch_residual_init(n, L0.A.rp.get(), L0.A.ci.get(), L0.A.val.get(), b, x, H.tmp.get(),
-                         H.partial.get(), s);
+    rinit(H.tmp.get());
     launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
     fetch_scalars(H);
     if (info) {
@@ -622,12 +645,14 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
         Level& C = H.levels[l + 1];
         a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
         a.nnz = L.R.nnz; a.ncols = L.R.ncols;
+        a.rblk = L.R.rblk.get(); a.nblk = L.R.nblk; a.lanes = L.R.lanes;
         a.v = LV<T>::t(L); a.y = LV<T>::f(C);
     } else if (kernel == GIAMG_KERNEL_PROLONG) {
         Level& C = H.levels[l + 1];
         mode = SPMV_ADD;
         a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
         a.nnz = L.P.nnz; a.ncols = L.P.ncols;
+        a.rblk = L.P.rblk.get(); a.nblk = L.P.nblk; a.lanes = L.P.lanes;
         a.v = LV<T>::x(C); a.y = LV<T>::t(L);
     } else {
         throw Error(GIAMG_EINVAL, "unknown kernel");

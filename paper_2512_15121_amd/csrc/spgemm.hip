@@ -166,6 +166,7 @@ void spgemm(const DevCSR& A, const DevCSR& B, DevCSR& C, hipStream_t s) {
     if (n == 0) {
         C.nnz = 0;
         GIAMG_HIP(hipMemsetAsync(C.rp.get(), 0, sizeof(int64_t), s));
+        GIAMG_HIP(hipStreamSynchronize(s));
         return;
     }
     DevBuf<int32_t> counts(n);
@@ -192,6 +193,7 @@ void spgemm(const DevCSR& A, const DevCSR& B, DevCSR& C, hipStream_t s) {
     C.val.alloc(C.nnz);
     if (C.nnz == 0) {
         GIAMG_HIP(hipStreamSynchronize(s));
+        setup_row_blocks(C, hrp, s);
         return;
     }
     sg_fill_kernel<<<(unsigned)n, SG_WAVE, 0, s>>>(n, A.rp.get(), A.ci.get(), B.rp.get(), B.ci.get(),
@@ -211,6 +213,7 @@ void spgemm(const DevCSR& A, const DevCSR& B, DevCSR& C, hipStream_t s) {
     }
     GIAMG_HIP(hipGetLastError());
     GIAMG_HIP(hipStreamSynchronize(s));
+    setup_row_blocks(C, hrp, s);
 }
 
 }  // namespace giamg
