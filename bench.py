@@ -14,6 +14,7 @@ Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup,
 --workload {cfg2,cfg3}, --no-cpu-baseline, --no-mixed.
 """
 import argparse
+import numpy as np
 import hashlib
 import json
 import os
@@ -108,6 +109,51 @@ def cpu_baseline(mesh, b, lam, w, gpu_iters):
                       f"BLAS limited to 1 thread; oracle setup {setup_s:.1f} s not timed"}
 
 
+def batched_leg(torch, Solver, Options, k=64, reps=3):
+    """Pressure-Poisson-like batch: lambda = 0, pure Neumann with node 0
+    pinned, 20^3 perturbed mesh (seed 4), p = 3, 64 right-hand sides N(0,1)
+    (seed 14) shifted to mean zero; FP32 V-cycle in FP64 flexible CG, block
+    products, graph replay.  Compared with 64 single solves."""
+    import synth
+    mesh = synth.hex_mesh(20, 3, perturb=0.1, seed=4)
+    B = synth.pinned_normal_batch(mesh.n_nodes, k, 14)
+    s = Solver(mesh.coords, mesh.l2g, 3, 0.0, Options(bc="pin", precision="mixed"))
+    Bt = torch.from_numpy(B).to("cuda:0")
+    X = torch.zeros_like(Bt)
+    s.solve_batch(Bt, X, tol=1e-10)          # tunes tiles, captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        X.zero_()
+        _, infos = s.solve_batch(Bt, X, tol=1e-10)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    cols = [torch.from_numpy(np.ascontiguousarray(B[:, j])).to("cuda:0") for j in range(k)]
+    x1 = torch.zeros_like(cols[0])
+    s.solve(cols[0], x1, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters_single = []
+    for j in range(k):
+        x1.zero_()
+        _, inf = s.solve(cols[j], x1, tol=1e-10)
+        iters_single.append(inf.iters)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    out = {"workload": "20^3 p=3 pure Neumann + pin, lambda=0, 64 RHS, mixed",
+           "nodes": mesh.n_nodes, "rhs": k,
+           "rhs_solves_per_s": round(k / t_batch, 2),
+           "single_solves_per_s": round(k / t_single, 2),
+           "speedup_vs_single": round(t_single / t_batch, 2),
+           "iters_max": max(i.iters for i in infos),
+           "iters_single_max": max(iters_single),
+           "worst_true_relres": max(i.true_relres for i in infos),
+           "gbs": round(infos[0].bytes / t_batch / 1e9, 1)}
+    s.close()
+    log(f"batched: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +162,7 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -175,6 +222,9 @@ def main():
         extra["mixed"]["cheb_step_fp32_gbs"] = round(k32_b / (k32_ms * 1e-3) / 1e9, 1)
         log(f"mixed: {args.steps / el_m:.2f} solves/s, {inf_m[-1].iters} iterations")
         sm.close()
+
+    if not args.no_batched:
+        extra["batched"] = batched_leg(torch, Solver, Options)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1,13 +1,810 @@
 // Batched solves: k right-hand sides against one hierarchy.
+//
+// Block vectors are row-major [n][k]: the entry of right-hand side j at row i
+// sits at i*k + j, so one nonzero a_ic multiplies a contiguous run X[c][0:k]
+// and every CSR entry read from HBM is reused k times.  The V-cycle
+// (Algorithm 1) runs as block sparse-times-dense products (SpMM); each column
+// keeps its own CG scalars and stops on its own (masked updates).  All
+// per-column decisions happen on the device, so one CG iteration is captured
+// once in a hipGraph and replayed; the host reads the number of active
+// columns after each chunk of replays.
+//
+// Reproducibility: the value of column j depends only on column j's data,
+// never on k or on the tile shape the tuner picks: row sums run over the
+// nonzeros in CSR order and the column dot products use a fixed row
+// partition.  A right-hand side gives the same bits alone or in a batch.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <memory>
 
 #include "kernels.h"
 
 namespace giamg {
 
-int solve_batch(Handle& H, const double* B, double* X, int32_t k, double tol, giamg_info* infos) {
-    (void)H; (void)B; (void)X; (void)k; (void)tol; (void)infos;
-    throw Error(GIAMG_ENOTSUP, "batched solve not available yet");
+namespace {
+
+constexpr int BW = 64;              // wavefront width
+constexpr int DOT_ROWS = 256;       // rows per column-dot block (fixed)
+constexpr int MAX_K = 1024;
+constexpr int CHUNK = 4;            // graph replays between host checks
+
+template <typename T>
+struct SpmmArgs {
+    const int64_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const T* val = nullptr;
+    int64_t n = 0;
+    int k = 1;
+    const T* v = nullptr;      // gathered block [ncols][k]
+    T* y = nullptr;
+    const T* f = nullptr;
+    const T* dinv = nullptr;   // per row
+    T* r = nullptr;
+    T* x = nullptr;
+    T c1 = 0, c2 = 0, inv_theta = 0, omega = 0;
+    int flags = 0;
+    const int* run = nullptr;  // skip all work when *run == 0
+};
+
+// One wavefront covers RPW = 64 / KT rows; KT lanes per row take KT columns.
+template <typename T, int MODE, int KT, int WPB>
+__global__ void __launch_bounds__(WPB* BW) spmm_kernel(SpmmArgs<T> a) {
+    if (a.run && *a.run == 0) return;
+    constexpr int RPW = BW / KT;
+    const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+    const int sub = lane / KT, cl = lane % KT;
+    const int64_t row = ((int64_t)blockIdx.x * WPB + wave) * RPW + sub;
+    const int64_t col = (int64_t)blockIdx.y * KT + cl;
+    if (row >= a.n || col >= a.k) return;
+    const int64_t k = a.k;
+    const int64_t s = a.rp[row], e = a.rp[row + 1];
+    T acc = 0;
+    int64_t j = s;
+    for (; j + 3 < e; j += 4) {
+        const int32_t c0 = a.ci[j], c1 = a.ci[j + 1], c2 = a.ci[j + 2], c3 = a.ci[j + 3];
+        const T a0 = a.val[j], a1 = a.val[j + 1], a2 = a.val[j + 2], a3 = a.val[j + 3];
+        const T x0 = a.v[c0 * k + col], x1 = a.v[c1 * k + col];
+        const T x2 = a.v[c2 * k + col], x3 = a.v[c3 * k + col];
+        acc += a0 * x0;
+        acc += a1 * x1;
+        acc += a2 * x2;
+        acc += a3 * x3;
+    }
+    for (; j < e; ++j) acc += a.val[j] * a.v[a.ci[j] * k + col];
+    const int64_t idx = row * k + col;
+    if constexpr (MODE == SPMV_PLAIN) {
+        a.y[idx] = acc;
+    } else if constexpr (MODE == SPMV_RESID) {
+        a.y[idx] = a.f[idx] - acc;
+    } else if constexpr (MODE == SPMV_ADD) {
+        a.y[idx] += acc;
+    } else if constexpr (MODE == SPMV_CHEB_INIT) {
+        const T res = a.dinv[row] * (a.f[idx] - acc);
+        a.r[idx] = res;
+        a.y[idx] = res * a.inv_theta;
+    } else if constexpr (MODE == SPMV_CHEB_STEP) {
+        const T rr = a.r[idx] - a.dinv[row] * acc;
+        const T dold = a.v[idx];
+        const T dn = a.c1 * dold + a.c2 * rr;
+        a.r[idx] = rr;
+        a.y[idx] = dn;
+        const T inc = (a.flags & CHEB_LAST) ? dold + dn : dold;
+        a.x[idx] = ((a.flags & CHEB_ASSIGN) ? T(0) : a.x[idx]) + inc;
+    } else if constexpr (MODE == SPMV_JACOBI) {
+        a.y[idx] = a.v[idx] + a.omega * a.dinv[row] * (a.f[idx] - acc);
+    }
+}
+
+// Tile shapes the tuner chooses from.
+struct Tile { int kt, wpb; };
+const Tile kTiles[] = {{64, 4}, {64, 8}, {64, 2}, {32, 4}, {32, 8}, {16, 4}, {16, 8}, {8, 8}};
+
+template <typename T, int MODE>
+void launch_spmm_tile(const SpmmArgs<T>& a, Tile t, hipStream_t s) {
+    const int rpw = BW / t.kt;
+    const int64_t rows_per_block = (int64_t)rpw * t.wpb;
+    const dim3 grid((unsigned)((a.n + rows_per_block - 1) / rows_per_block),
+                    (unsigned)((a.k + t.kt - 1) / t.kt));
+    const dim3 block(t.wpb * BW);
+#define GIAMG_TILE(KT, WPB)                                                         \
+    if (t.kt == KT && t.wpb == WPB) {                                               \
+        spmm_kernel<T, MODE, KT, WPB><<<grid, block, 0, s>>>(a);                    \
+        return;                                                                     \
+    }
+    GIAMG_TILE(64, 4) GIAMG_TILE(64, 8) GIAMG_TILE(64, 2) GIAMG_TILE(32, 4)
+    GIAMG_TILE(32, 8) GIAMG_TILE(16, 4) GIAMG_TILE(16, 8) GIAMG_TILE(8, 8)
+#undef GIAMG_TILE
+    throw Error(GIAMG_EINVAL, "unknown tile");
+}
+
+template <typename T>
+void launch_spmm_any(int mode, const SpmmArgs<T>& a, Tile t, hipStream_t s) {
+    if (a.n <= 0) return;
+    switch (mode) {
+        case SPMV_PLAIN: launch_spmm_tile<T, SPMV_PLAIN>(a, t, s); break;
+        case SPMV_RESID: launch_spmm_tile<T, SPMV_RESID>(a, t, s); break;
+        case SPMV_ADD: launch_spmm_tile<T, SPMV_ADD>(a, t, s); break;
+        case SPMV_CHEB_INIT: launch_spmm_tile<T, SPMV_CHEB_INIT>(a, t, s); break;
+        case SPMV_CHEB_STEP: launch_spmm_tile<T, SPMV_CHEB_STEP>(a, t, s); break;
+        case SPMV_JACOBI: launch_spmm_tile<T, SPMV_JACOBI>(a, t, s); break;
+        default: throw Error(GIAMG_EINVAL, "unknown block product mode");
+    }
+    GIAMG_HIP(hipGetLastError());
+}
+
+// ---- row-local block kernels ------------------------------------------------
+template <typename T>
+__global__ void bcheb_init0_kernel(int64_t n, int k, const T* __restrict__ f, const T* __restrict__ dinv,
+                                   T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T inv_theta,
+                                   int write_x, const int* run) {
+    if (run && *run == 0) return;
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T res = dinv[i / k] * f[i];
+        const T dd = res * inv_theta;
+        r[i] = res;
+        d[i] = dd;
+        if (write_x) x[i] = dd;
+    }
+}
+
+template <typename T>
+__global__ void bjacobi0_kernel(int64_t n, int k, const T* __restrict__ f, const T* __restrict__ dinv,
+                                T* __restrict__ x, T omega, const int* run) {
+    if (run && *run == 0) return;
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = omega * dinv[i / k] * f[i];
+}
+
+template <typename Tin, typename Tout>
+__global__ void bconvert_kernel(int64_t total, const Tin* __restrict__ a, Tout* __restrict__ b,
+                                int accumulate, const int* run) {
+    if (run && *run == 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = accumulate ? (Tout)(b[i] + (Tout)a[i]) : (Tout)a[i];
+}
+
+// Y = inv F for the dense coarsest inverse, FP64 accumulation.
+template <typename T>
+__global__ void bcoarse_kernel(int64_t n, int k, const double* __restrict__ inv, const T* __restrict__ f,
+                               T* __restrict__ y, const int* run) {
+    if (run && *run == 0) return;
+    const int64_t row = blockIdx.x;
+    for (int64_t col = threadIdx.x; col < k; col += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) acc += inv[row * n + j] * (double)f[j * k + col];
+        y[row * k + col] = (T)acc;
+    }
+}
+
+static unsigned bgrid(int64_t total) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
+}
+
+// ---- column dot products with a fixed row partition ---------------------------
+// partial[(c*nb + b)] = sum over rows of block b (in order) of a[i][c] * b[i][c]
+__global__ void __launch_bounds__(256) bdot_partial_kernel(int64_t n, int k, const double* __restrict__ a,
+                                                           const double* __restrict__ b,
+                                                           double* __restrict__ partial, int64_t nb,
+                                                           const int* run) {
+    if (run && *run == 0) return;
+    __shared__ double sh[4][BW];
+    const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+    const int64_t col = (int64_t)blockIdx.y * BW + lane;
+    const int64_t r0 = (int64_t)blockIdx.x * DOT_ROWS + wave * (DOT_ROWS / 4);
+    double s = 0.0;
+    if (col < k) {
+        const int64_t r1 = (r0 + DOT_ROWS / 4 < n) ? r0 + DOT_ROWS / 4 : n;
+        for (int64_t i = r0; i < r1; ++i) s += a[i * k + col] * b[i * k + col];
+    }
+    sh[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && col < k)
+        partial[col * nb + blockIdx.x] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
+// out[c * ostride] = fixed-order sum of partial[c*nb + 0..nb)
+__global__ void __launch_bounds__(256) bdot_reduce_kernel(int64_t nb, const double* __restrict__ partial,
+                                                          double* __restrict__ out, const int* run) {
+    if (run && *run == 0) return;
+    __shared__ double sh[256];
+    const int64_t c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += 256) s += partial[c * nb + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+// ---- per-column CG state ------------------------------------------------------
+struct ColState {
+    double bb, rr, rz, pq, alpha, beta, rznew, zrold;
+    int active, iters, status, pad;
+};
+
+__global__ void bcg_start_kernel(int k, ColState* st, double tol, int* run) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState& s = st[c];
+        s.iters = 0;
+        s.status = GIAMG_OK;
+        s.active = 0;
+        if (s.bb > 0.0 && !(sqrt(s.rr) / sqrt(s.bb) < tol)) {
+            s.active = 1;
+            if (!isfinite(s.rr)) { s.active = 0; s.status = GIAMG_EBREAKDOWN; }
+        }
+        if (s.active) atomicOr(&any, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *run = any;
+}
+
+__global__ void bcg_alpha_kernel(int k, ColState* st, const int* run) {
+    if (*run == 0) return;
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState& s = st[c];
+        if (!s.active) { s.alpha = 0.0; continue; }
+        if (!(s.pq > 0.0) || !isfinite(s.pq) || !isfinite(s.rz)) {
+            s.active = 0;
+            s.status = GIAMG_EBREAKDOWN;
+            s.alpha = 0.0;
+        } else {
+            s.alpha = s.rz / s.pq;
+        }
+    }
+}
+
+// x += alpha p; r_old = r; r -= alpha q   (active columns only)
+__global__ void bcg_update_kernel(int64_t n, int k, double* __restrict__ x, double* __restrict__ r,
+                                  double* __restrict__ rold, const double* __restrict__ p,
+                                  const double* __restrict__ q, const ColState* __restrict__ st,
+                                  const int* run) {
+    if (*run == 0) return;
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const ColState& s = st[i % k];
+        if (!s.active) continue;
+        x[i] += s.alpha * p[i];
+        const double ri = r[i];
+        if (rold) rold[i] = ri;
+        r[i] = ri - s.alpha * q[i];
+    }
+}
+
+__global__ void bcg_check_kernel(int k, ColState* st, double tol, int maxit, int* run) {
+    __shared__ int any;
+    if (*run == 0) return;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState& s = st[c];
+        if (s.active) {
+            s.iters += 1;
+            const double rel = sqrt(s.rr) / sqrt(s.bb);
+            if (!isfinite(rel)) {
+                s.active = 0;
+                s.status = GIAMG_EBREAKDOWN;
+            } else if (rel < tol) {
+                s.active = 0;
+                s.status = GIAMG_OK;
+            } else if (s.iters >= maxit) {
+                s.active = 0;
+                s.status = GIAMG_ENOTCONV;
+            }
+        }
+        if (s.active) atomicOr(&any, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *run = any;
+}
+
+__global__ void bcg_beta_kernel(int k, ColState* st, int flexible, const int* run) {
+    if (*run == 0) return;
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState& s = st[c];
+        if (!s.active) continue;
+        const double rzn = s.rznew;
+        s.beta = flexible ? (rzn - s.zrold) / s.rz : rzn / s.rz;
+        if (!isfinite(rzn)) {
+            s.active = 0;
+            s.status = GIAMG_EBREAKDOWN;
+        }
+        s.rz = rzn;
+    }
+}
+
+// p = z + beta p (first: p = z), active columns only
+__global__ void bcg_direction_kernel(int64_t n, int k, const double* __restrict__ z, double* __restrict__ p,
+                                     const ColState* __restrict__ st, int first, const int* run) {
+    if (*run == 0) return;
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const ColState& s = st[i % k];
+        if (!s.active) continue;
+        p[i] = first ? z[i] : z[i] + s.beta * p[i];
+    }
+}
+
+// x = 0 for right-hand sides that are identically zero
+__global__ void bzero_cols_kernel(int64_t n, int k, double* __restrict__ x, const ColState* __restrict__ st) {
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (st[i % k].bb == 0.0) x[i] = 0.0;
+}
+
+__global__ void bfill_state_kernel(int k, ColState* st) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState z{};
+        st[c] = z;
+    }
+}
+
+// copy a field of the column dots into the state: which = 0 bb, 1 rr, 2 rznew, 3 zrold, 4 pq
+__global__ void bstore_kernel(int k, const double* __restrict__ v, ColState* st, int which,
+                              const int* run) {
+    if (run && *run == 0) return;
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double* f = which == 0 ? &st[c].bb : which == 1 ? &st[c].rr : which == 2 ? &st[c].rznew
+                    : which == 3 ? &st[c].zrold : &st[c].pq;
+        *f = v[c];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// per-handle batch workspace
+// ---------------------------------------------------------------------------
+struct BatchLevel {
+    DevBuf<double> f, x, r, d0, d1, t;
+    DevBuf<float> f32, x32, r32, d032, d132, t32;
+};
+
+struct BatchState {
+    int k = 0;
+    bool mixed = false;
+    std::vector<BatchLevel> lv;
+    DevBuf<double> R, Z, P, Q, Rold;
+    DevBuf<double> partial, dots;
+    DevBuf<ColState> st;
+    DevBuf<int> run;
+    std::map<std::string, Tile> tiles;   // tuned tile per operator and precision
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const double* graph_b = nullptr;
+    double* graph_x = nullptr;
+    double graph_tol = -1.0;
+    double bytes_iter = 0.0;
+    hipStream_t stream = nullptr;     // capturable stream ordered after the caller's
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    ~BatchState() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (stream) (void)hipStreamDestroy(stream);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+    }
+};
+
+void BatchDeleter::operator()(BatchState* b) const { delete b; }
+
+namespace {
+
+template <typename T> struct BL;
+template <> struct BL<double> {
+    static double* f(BatchLevel& b) { return b.f.get(); }
+    static double* x(BatchLevel& b) { return b.x.get(); }
+    static double* r(BatchLevel& b) { return b.r.get(); }
+    static double* d0(BatchLevel& b) { return b.d0.get(); }
+    static double* d1(BatchLevel& b) { return b.d1.get(); }
+    static double* t(BatchLevel& b) { return b.t.get(); }
+    static const double* A(const Level& L) { return L.A.val.get(); }
+    static const double* P(const Level& L) { return L.P.val.get(); }
+    static const double* R(const Level& L) { return L.R.val.get(); }
+    static const double* dinv(const Level& L) { return L.dinv.get(); }
+};
+template <> struct BL<float> {
+    static float* f(BatchLevel& b) { return b.f32.get(); }
+    static float* x(BatchLevel& b) { return b.x32.get(); }
+    static float* r(BatchLevel& b) { return b.r32.get(); }
+    static float* d0(BatchLevel& b) { return b.d032.get(); }
+    static float* d1(BatchLevel& b) { return b.d132.get(); }
+    static float* t(BatchLevel& b) { return b.t32.get(); }
+    static const float* A(const Level& L) { return L.A.val32.get(); }
+    static const float* P(const Level& L) { return L.P.val32.get(); }
+    static const float* R(const Level& L) { return L.R.val32.get(); }
+    static const float* dinv(const Level& L) { return L.dinv32.get(); }
+};
+
+template <typename T>
+SpmmArgs<T> bargs(const DevCSR& M, const T* val, int k, const int* run) {
+    SpmmArgs<T> a;
+    a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows; a.k = k; a.run = run;
+    return a;
+}
+
+struct BatchCtx {
+    Handle& H;
+    BatchState& B;
+    int k;
+    const int* run;
+    bool count_bytes;
+    hipStream_t s() const { return B.stream; }
+};
+
+double spmm_bytes(const DevCSR& M, int k, double vb, double rowvecs) {
+    return (vb + 4.0) * M.nnz + 8.0 * (M.nrows + 1) + vb * (double)M.ncols * k +
+           rowvecs * vb * (double)M.nrows * k;
+}
+
+// tile lookup (tuned on first use, outside any capture)
+template <typename T>
+Tile tile_for(BatchCtx& c, const DevCSR& M, const std::string& key);
+
+template <typename T>
+void spmm(BatchCtx& c, int mode, const DevCSR& M, SpmmArgs<T> a, const std::string& key,
+          double rowvecs) {
+    const Tile t = tile_for<T>(c, M, key);
+    if (c.count_bytes) c.H.bytes += spmm_bytes(M, c.k, sizeof(T), rowvecs);
+    launch_spmm_any<T>(mode, a, t, c.s());
+}
+
+template <typename T>
+Tile tile_for(BatchCtx& c, const DevCSR& M, const std::string& key) {
+    const std::string full = key + (sizeof(T) == 4 ? "/f32" : "/f64");
+    auto it = c.B.tiles.find(full);
+    if (it != c.B.tiles.end()) return it->second;
+    // tune: time a plain product of this operator for every tile shape
+    DevBuf<T> xin((size_t)std::max<int64_t>(M.ncols, 1) * c.k), yout((size_t)std::max<int64_t>(M.nrows, 1) * c.k);
+    GIAMG_HIP(hipMemsetAsync(xin.get(), 0, xin.n * sizeof(T), c.s()));
+    const T* val = nullptr;
+    if constexpr (sizeof(T) == 4) val = M.val32.get(); else val = M.val.get();
+    SpmmArgs<T> a;
+    a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows; a.k = c.k;
+    a.v = xin.get(); a.y = yout.get();
+    Tile best = kTiles[0];
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    GIAMG_HIP(hipEventCreate(&e0));
+    GIAMG_HIP(hipEventCreate(&e1));
+    for (const Tile& t : kTiles) {
+        if (t.kt > 2 * c.k && t.kt > 8) continue;   // mostly idle lanes
+        launch_spmm_any<T>(SPMV_PLAIN, a, t, c.s());
+        GIAMG_HIP(hipEventRecord(e0, c.s()));
+        for (int i = 0; i < 3; ++i) launch_spmm_any<T>(SPMV_PLAIN, a, t, c.s());
+        GIAMG_HIP(hipEventRecord(e1, c.s()));
+        GIAMG_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        GIAMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.B.tiles[full] = best;
+    return best;
+}
+
+template <typename T>
+void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start) {
+    Handle& H = c.H;
+    Level& L = H.levels[l];
+    BatchLevel& W = c.B.lv[l];
+    const int k = c.k;
+    const int deg = H.opts.degree;
+    const std::string key = "A" + std::to_string(l);
+    const int64_t total = L.n * (int64_t)k;
+    if (H.opts.smoother == GIAMG_SMOOTHER_JACOBI) {
+        const T w = (T)H.opts.omega;
+        T* buf[2] = {x, BL<T>::d0(W)};
+        int cur = 0, start = 0;
+        if (zero_start) {
+            if (c.count_bytes) H.bytes += 3.0 * sizeof(T) * total;
+            bjacobi0_kernel<T><<<bgrid(total), 256, 0, c.s()>>>(L.n, k, f, BL<T>::dinv(L), x, w, c.run);
+            start = 1;
+        }
+        for (int s = start; s < deg; ++s) {
+            SpmmArgs<T> a = bargs<T>(L.A, BL<T>::A(L), k, c.run);
+            a.v = buf[cur]; a.y = buf[1 - cur]; a.f = f; a.dinv = BL<T>::dinv(L); a.omega = w;
+            spmm<T>(c, SPMV_JACOBI, L.A, a, key, 3);
+            cur = 1 - cur;
+        }
+        if (cur == 1) {
+            if (c.count_bytes) H.bytes += 2.0 * sizeof(T) * total;
+            bconvert_kernel<T, T><<<bgrid(total), 256, 0, c.s()>>>(total, buf[1], x, 0, c.run);
+        }
+        return;
+    }
+    const double lo = H.opts.cheb_lo * L.lam_hat, hi = H.opts.cheb_hi * L.lam_hat;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    T* r = BL<T>::r(W);
+    T* d[2] = {BL<T>::d0(W), BL<T>::d1(W)};
+    if (zero_start) {
+        if (c.count_bytes) H.bytes += (deg == 1 ? 5.0 : 4.0) * sizeof(T) * total;
+        bcheb_init0_kernel<T><<<bgrid(total), 256, 0, c.s()>>>(L.n, k, f, BL<T>::dinv(L), r, d[0], x,
+                                                                (T)(1.0 / theta), deg == 1, c.run);
+    } else {
+        SpmmArgs<T> a = bargs<T>(L.A, BL<T>::A(L), k, c.run);
+        a.v = x; a.f = f; a.r = r; a.y = d[0]; a.dinv = BL<T>::dinv(L); a.inv_theta = (T)(1.0 / theta);
+        spmm<T>(c, SPMV_CHEB_INIT, L.A, a, key, 4);
+        if (deg == 1) {
+            if (c.count_bytes) H.bytes += 3.0 * sizeof(T) * total;
+            bconvert_kernel<T, T><<<bgrid(total), 256, 0, c.s()>>>(total, d[0], x, 1, c.run);
+        }
+    }
+    double rho = 1.0 / sigma;
+    for (int j = 1; j < deg; ++j) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        SpmmArgs<T> a = bargs<T>(L.A, BL<T>::A(L), k, c.run);
+        a.v = d[(j - 1) & 1]; a.y = d[j & 1]; a.r = r; a.x = x; a.dinv = BL<T>::dinv(L);
+        a.c1 = (T)(rn * rho); a.c2 = (T)(2.0 * rn / delta);
+        a.flags = (j == deg - 1 ? CHEB_LAST : 0) | ((zero_start && j == 1) ? CHEB_ASSIGN : 0);
+        spmm<T>(c, SPMV_CHEB_STEP, L.A, a, key, (zero_start && j == 1) ? 5 : 6);
+        rho = rn;
+    }
+}
+
+template <typename T>
+void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
+    Handle& H = c.H;
+    Level& L = H.levels[l];
+    const int k = c.k;
+    if (l + 1 == H.levels.size()) {
+        if (c.count_bytes) H.bytes += 8.0 * H.nc * H.nc + 2.0 * sizeof(T) * H.nc * k;
+        if (H.nc > 0) bcoarse_kernel<T><<<(unsigned)H.nc, 64, 0, c.s()>>>(H.nc, k, H.coarse_inv.get(), f, x, c.run);
+        return;
+    }
+    BatchLevel& W = c.B.lv[l];
+    BatchLevel& WC = c.B.lv[l + 1];
+    const std::string sl = std::to_string(l);
+    bsmooth<T>(c, l, f, x, true);
+    {
+        SpmmArgs<T> a = bargs<T>(L.A, BL<T>::A(L), k, c.run);
+        a.v = x; a.f = f; a.y = BL<T>::t(W);
+        spmm<T>(c, SPMV_RESID, L.A, a, "A" + sl, 2);
+    }
+    {
+        SpmmArgs<T> a = bargs<T>(L.R, BL<T>::R(L), k, c.run);
+        a.v = BL<T>::t(W); a.y = BL<T>::f(WC);
+        spmm<T>(c, SPMV_PLAIN, L.R, a, "R" + sl, 1);
+    }
+    bvcycle<T>(c, l + 1, BL<T>::f(WC), BL<T>::x(WC));
+    {
+        SpmmArgs<T> a = bargs<T>(L.P, BL<T>::P(L), k, c.run);
+        a.v = BL<T>::x(WC); a.y = x;
+        spmm<T>(c, SPMV_ADD, L.P, a, "P" + sl, 2);
+    }
+    bsmooth<T>(c, l, f, x, false);
+}
+
+void bprecondition(BatchCtx& c, const double* r, double* z) {
+    const int64_t total = c.H.n_nodes * (int64_t)c.k;
+    if (c.B.mixed) {
+        BatchLevel& W = c.B.lv[0];
+        if (c.count_bytes) c.H.bytes += 24.0 * total;
+        bconvert_kernel<double, float><<<bgrid(total), 256, 0, c.s()>>>(total, r, W.f32.get(), 0, c.run);
+        bvcycle<float>(c, 0, W.f32.get(), W.x32.get());
+        bconvert_kernel<float, double><<<bgrid(total), 256, 0, c.s()>>>(total, W.x32.get(), z, 0, c.run);
+    } else {
+        bvcycle<double>(c, 0, r, z);
+    }
+}
+
+// column dots a.b into the state field `which`
+void bdots(BatchCtx& c, const double* a, const double* b, int which) {
+    const int64_t n = c.H.n_nodes;
+    const int64_t nb = (n + DOT_ROWS - 1) / DOT_ROWS;
+    if (c.count_bytes) c.H.bytes += 16.0 * n * c.k;
+    bdot_partial_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
+        n, c.k, a, b, c.B.partial.get(), nb, c.run);
+    bdot_reduce_kernel<<<(unsigned)c.k, 256, 0, c.s()>>>(nb, c.B.partial.get(), c.B.dots.get(), c.run);
+    bstore_kernel<<<1, 256, 0, c.s()>>>(c.k, c.B.dots.get(), c.B.st.get(), which, c.run);
+}
+
+void bproduct_A0(BatchCtx& c, int mode, const double* v, const double* f, double* y, double rowvecs) {
+    Level& L0 = c.H.levels[0];
+    SpmmArgs<double> a = bargs<double>(L0.A, L0.A.val.get(), c.k, c.run);
+    a.v = v; a.f = f; a.y = y;
+    spmm<double>(c, mode, L0.A, a, "A0", rowvecs);
+}
+
+// one CG iteration on the device (captured into the graph)
+void iteration(BatchCtx& c, double* X, double tol) {
+    Handle& H = c.H;
+    BatchState& B = c.B;
+    const int64_t total = H.n_nodes * (int64_t)c.k;
+    const int maxit = H.opts.maxit;
+    const unsigned cb = (unsigned)std::min(c.k, MAX_K);
+    bproduct_A0(c, SPMV_PLAIN, B.P.get(), nullptr, B.Q.get(), 1);
+    bdots(c, B.P.get(), B.Q.get(), 4);
+    bcg_alpha_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), c.run);
+    if (c.count_bytes) H.bytes += (B.mixed ? 56.0 : 48.0) * total;
+    bcg_update_kernel<<<bgrid(total), 256, 0, c.s()>>>(H.n_nodes, c.k, X, B.R.get(),
+                                                       B.mixed ? B.Rold.get() : nullptr, B.P.get(),
+                                                       B.Q.get(), B.st.get(), c.run);
+    bdots(c, B.R.get(), B.R.get(), 1);
+    bcg_check_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), tol, maxit, B.run.get());
+    bprecondition(c, B.R.get(), B.Z.get());
+    bdots(c, B.R.get(), B.Z.get(), 2);
+    if (B.mixed) bdots(c, B.Rold.get(), B.Z.get(), 3);
+    bcg_beta_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), B.mixed ? 1 : 0, c.run);
+    if (c.count_bytes) H.bytes += 24.0 * total;
+    bcg_direction_kernel<<<bgrid(total), 256, 0, c.s()>>>(H.n_nodes, c.k, B.Z.get(), B.P.get(), B.st.get(), 0,
+                                                          c.run);
+    GIAMG_HIP(hipGetLastError());
+}
+
+void ensure_state(Handle& H, int k) {
+    if (H.batch && H.batch->k == k) return;
+    H.batch.reset();
+    std::unique_ptr<BatchState> B(new BatchState());
+    B->k = k;
+    B->mixed = H.opts.precision == GIAMG_PREC_MIXED;
+    for (auto& L : H.levels) {
+        BatchLevel W;
+        const size_t m = (size_t)std::max<int64_t>(L.n, 1) * k;
+        if (B->mixed) {
+            W.f32.alloc(m); W.x32.alloc(m); W.r32.alloc(m); W.d032.alloc(m); W.d132.alloc(m); W.t32.alloc(m);
+        } else {
+            W.f.alloc(m); W.x.alloc(m); W.r.alloc(m); W.d0.alloc(m); W.d1.alloc(m); W.t.alloc(m);
+        }
+        B->lv.push_back(std::move(W));
+    }
+    const size_t tot = (size_t)H.n_nodes * k;
+    B->R.alloc(tot); B->Z.alloc(tot); B->P.alloc(tot); B->Q.alloc(tot);
+    if (B->mixed) B->Rold.alloc(tot);
+    const int64_t nb = (H.n_nodes + DOT_ROWS - 1) / DOT_ROWS;
+    B->partial.alloc((size_t)nb * k);
+    B->dots.alloc(k);
+    B->st.alloc(k);
+    B->run.alloc(1);
+    // the caller's stream may be the legacy default stream, which cannot be
+    // captured: batched work runs on a stream of its own, ordered by events
+    GIAMG_HIP(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
+    GIAMG_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    GIAMG_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    H.batch.reset(B.release());
+}
+
+}  // namespace
+
+int solve_batch(Handle& H, const double* Bm, double* X, int32_t k, double tol, giamg_info* infos) {
+    GIAMG_REQUIRE(k <= MAX_K, "at most 1024 right-hand sides per call");
+    ensure_state(H, k);
+    BatchState& B = *H.batch;
+    hipStream_t s = B.stream;
+    GIAMG_HIP(hipEventRecord(B.ev_in, H.stream));
+    GIAMG_HIP(hipStreamWaitEvent(s, B.ev_in, 0));
+    const int64_t total = H.n_nodes * (int64_t)k;
+    const unsigned cb = (unsigned)std::min(k, MAX_K);
+    BatchCtx c{H, B, k, B.run.get(), true};
+    H.bytes = 0.0;
+    // tune every operator before anything is captured
+    {
+        BatchCtx t{H, B, k, nullptr, false};
+        for (size_t l = 0; l < H.levels.size(); ++l) {
+            Level& L = H.levels[l];
+            const std::string sl = std::to_string(l);
+            tile_for<double>(t, L.A, "A" + sl);
+            if (B.mixed && l + 1 < H.levels.size()) {
+                tile_for<float>(t, L.A, "A" + sl);
+                tile_for<float>(t, L.R, "R" + sl);
+                tile_for<float>(t, L.P, "P" + sl);
+            } else if (l + 1 < H.levels.size()) {
+                tile_for<double>(t, L.R, "R" + sl);
+                tile_for<double>(t, L.P, "P" + sl);
+            }
+        }
+    }
+    hipEvent_t t0, t1;
+    GIAMG_HIP(hipEventCreate(&t0));
+    GIAMG_HIP(hipEventCreate(&t1));
+    GIAMG_HIP(hipEventRecord(t0, s));
+    // start: r = b - A x, norms, activity, z = V(r), rz, p = z
+    GIAMG_HIP(hipMemsetAsync(B.run.get(), 0xff, sizeof(int), s));   // run everything
+    bfill_state_kernel<<<1, cb, 0, s>>>(k, B.st.get());
+    bproduct_A0(c, SPMV_RESID, X, Bm, B.R.get(), 2);
+    bdots(c, Bm, Bm, 0);
+    bdots(c, B.R.get(), B.R.get(), 1);
+    bcg_start_kernel<<<1, cb, 0, s>>>(k, B.st.get(), tol, B.run.get());
+    bzero_cols_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, X, B.st.get());
+    bprecondition(c, B.R.get(), B.Z.get());
+    bdots(c, B.R.get(), B.Z.get(), 2);
+    // rz = rznew for the first direction (its beta is not used: p = z)
+    bcg_beta_kernel<<<1, cb, 0, s>>>(k, B.st.get(), 0, B.run.get());
+    bcg_direction_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, B.Z.get(), B.P.get(), B.st.get(), 1,
+                                                      B.run.get());
+    GIAMG_HIP(hipGetLastError());
+    const double bytes_start = H.bytes;
+    // capture one iteration (pointers are fixed for this k and these b, x)
+    if (!B.exec || B.graph_b != Bm || B.graph_x != X || B.graph_tol != tol) {
+        if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
+        if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
+        GIAMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            iteration(c, X, tol);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        GIAMG_HIP(hipStreamEndCapture(s, &B.graph));
+        GIAMG_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+        B.graph_b = Bm;
+        B.graph_x = X;
+        B.graph_tol = tol;
+        B.bytes_iter = H.bytes - bytes_start;
+    }
+    const double bytes_iter = B.bytes_iter;
+    int host_run = 1;
+    int launched = 0;
+    while (launched < H.opts.maxit) {
+        GIAMG_HIP(hipMemcpyAsync(&host_run, B.run.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+        GIAMG_HIP(hipStreamSynchronize(s));
+        if (!host_run) break;
+        const int n = std::min(CHUNK, H.opts.maxit - launched);
+        for (int i = 0; i < n; ++i) GIAMG_HIP(hipGraphLaunch(B.exec, s));
+        launched += n;
+    }
+    GIAMG_HIP(hipEventRecord(t1, s));
+    std::vector<ColState> hs(k);
+    GIAMG_HIP(hipMemcpyAsync(hs.data(), B.st.get(), k * sizeof(ColState), hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    GIAMG_HIP(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    // true residuals (outside the timed region)
+    GIAMG_HIP(hipMemsetAsync(B.run.get(), 0xff, sizeof(int), s));
+    BatchCtx nc{H, B, k, nullptr, false};
+    bproduct_A0(nc, SPMV_RESID, X, Bm, B.Q.get(), 2);
+    bdots(nc, B.Q.get(), B.Q.get(), 1);
+    std::vector<ColState> ht(k);
+    GIAMG_HIP(hipMemcpyAsync(ht.data(), B.st.get(), k * sizeof(ColState), hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipEventRecord(B.ev_out, s));
+    GIAMG_HIP(hipStreamWaitEvent(H.stream, B.ev_out, 0));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    int worst = GIAMG_OK;
+    int max_iters = 0;
+    for (int j = 0; j < k; ++j) {
+        max_iters = std::max(max_iters, hs[j].iters);
+        const int st = hs[j].status;
+        if (st < 0) worst = std::min(worst, st);
+        else if (worst >= 0) worst = std::max(worst, st);
+        if (infos) {
+            giamg_info& in = infos[j];
+            in.iters = hs[j].iters;
+            in.status = st;
+            in.relres = hs[j].bb > 0 ? std::sqrt(hs[j].rr) / std::sqrt(hs[j].bb) : 0.0;
+            in.true_relres = hs[j].bb > 0 ? std::sqrt(ht[j].rr) / std::sqrt(hs[j].bb) : 0.0;
+            in.solve_ms = ms;
+            in.bytes = 0.0;
+        }
+    }
+    if (infos) {
+        // whole-batch bytes: start + the replays that ran with active columns
+        const double bytes = bytes_start + bytes_iter * max_iters;
+        for (int j = 0; j < k; ++j) infos[j].bytes = bytes;
+    }
+    (void)launched;
+    return worst;
 }
 
 }  // namespace giamg

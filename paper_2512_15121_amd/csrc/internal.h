@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -94,6 +95,10 @@ struct DevCSR {
 void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
 
 // ---- the hierarchy ----------------------------------------------------------
+struct BatchState;                 // batched-solve workspace (batch.hip)
+struct BatchDeleter {
+    void operator()(BatchState* b) const;
+};
 struct Level {
     int kind = GIAMG_LEVEL_P;
     int order = 1;
@@ -131,7 +136,7 @@ struct Handle {
     double* host_scal = nullptr;      // pinned host mirror
     int64_t partial_cap = 0;
     // batched state
-    int32_t batch_k = 0;
+    std::unique_ptr<BatchState, BatchDeleter> batch;
     double bytes = 0.0;               // algorithmic bytes of launched kernels
     double setup_ms[7] = {0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
