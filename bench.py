@@ -11,7 +11,8 @@ CG from x = 0 to the tolerance); the hierarchy is built once before timing
 (its setup time, including the device Galerkin products, is reported apart).
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup,
---workload {cfg2,cfg3}, --no-cpu-baseline, --no-mixed.
+--workload {cfg2,cfg3}, --no-cpu-baseline, --no-mixed, --no-batched,
+--serving {small,full,off}.
 """
 import argparse
 import numpy as np
@@ -154,6 +155,95 @@ def batched_leg(torch, Solver, Options, k=64, reps=3):
     return out
 
 
+def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4), slots=8,
+                chunk=2, seed=5):
+    """Serving trace: requests for Helmholtz problems on n^3 perturbed meshes,
+    n and p uniform in the given ranges, one mesh seed and one lambda
+    (log-uniform [0.1, 100]) per (n, p) key, right-hand sides N(0, 1); mixed
+    GIAMG-PCG to 1e-10.  A warm-up pass builds every hierarchy; then a
+    closed-loop pass (all requests submitted at once) gives the saturation
+    throughput S, and an open-loop pass with Poisson arrivals at 0.7 S gives
+    p50 / p99 latency (submission to solution in host memory)."""
+    import threading
+    import synth
+    rng = np.random.Generator(np.random.PCG64(seed))
+    srv = Server(hbm_budget=int(100e9), slots=slots, chunk=chunk, tol=1e-10)
+    problems = {}
+    trace = []
+    for i in range(n_req):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        p = int(rng.integers(p_range[0], p_range[1] + 1))
+        if (n, p) not in problems:
+            mesh = synth.hex_mesh(n, p, perturb=0.1, seed=1000 + 10 * n + p)
+            lam = synth.loguniform_lambda(2000 + 10 * n + p)
+            pid = srv.add_problem(mesh.coords, mesh.l2g, p, lam, Options(precision="mixed"))
+            problems[(n, p)] = (pid, mesh.n_nodes)
+        pid, nn = problems[(n, p)]
+        trace.append((pid, synth.normal_rhs(nn, 50000 + i)))
+
+    def run(arrivals):
+        lat = [0.0] * len(trace)
+        status = [0] * len(trace)
+        rids = [None] * len(trace)
+        ready = [threading.Event() for _ in trace]
+
+        def waiter():
+            for i in range(len(trace)):
+                ready[i].wait()
+                if rids[i] is None:        # submission stopped early
+                    status[i] = -1
+                    continue
+                try:
+                    _, info, l = srv.wait(rids[i])
+                    lat[i] = l
+                    status[i] = info.status
+                except Exception as e:      # recorded, reported as a failed request
+                    status[i] = getattr(e, "code", -1)
+                    log(f"serving: request {i} failed: {e}")
+        th = threading.Thread(target=waiter, daemon=True)
+        th.start()
+        t0 = time.perf_counter()
+        try:
+            for i, (pid, b) in enumerate(trace):
+                if arrivals is not None:
+                    delay = arrivals[i] - (time.perf_counter() - t0)
+                    if delay > 0:
+                        time.sleep(delay)
+                rids[i] = srv.submit(pid, b)
+                ready[i].set()
+        finally:
+            for e in ready:                # release the waiter whatever happened
+                e.set()
+            th.join()
+        return time.perf_counter() - t0, np.array(lat), status
+
+    try:
+        t_warm, _, _ = run(None)                # warm-up: every hierarchy set up once
+        log(f"serving: warm-up pass {t_warm:.2f} s ({len(problems)} hierarchies)")
+        t_closed, lat_closed, st_closed = run(None)
+        sat = len(trace) / t_closed
+        log(f"serving: closed loop {sat:.1f} solves/s")
+        gaps = rng.exponential(1.0 / (0.7 * sat), size=len(trace))
+        t_open, lat_open, st_open = run(np.cumsum(gaps))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    out = {"workload": f"{n_req} requests, n in {list(n_range)}, p in {list(p_range)}, "
+                       f"{len(problems)} hierarchies, mixed, {slots} slots per hierarchy",
+           "saturation_solves_per_s": round(sat, 2),
+           "open_loop_rate": round(0.7 * sat, 2),
+           "open_loop_solves_per_s": round(len(trace) / t_open, 2),
+           "p50_ms": round(float(np.percentile(lat_open, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat_open, 99)), 3),
+           "closed_p50_ms": round(float(np.percentile(lat_closed, 50)), 3),
+           "closed_p99_ms": round(float(np.percentile(lat_closed, 99)), 3),
+           "all_ok": all(s_ == 0 for s_ in st_closed + st_open),
+           "setups": stats["setups"], "cache_hits": stats["cache_hits"],
+           "peak_bytes": stats["peak_bytes"]}
+    log(f"serving: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +253,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serving", default="small", choices=["small", "full", "off"])
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only launch a 1 GiB copy (3x) and the fine Chebyshev step (5x), "
+                         "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -175,6 +269,18 @@ def main():
 
     dev = torch.device("cuda:0")
     mesh, b, lam, w = problem(args.workload)
+    if args.pmc_probe:
+        src = torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        solver = Solver(mesh.coords, mesh.l2g, w["p"], lam, Options())
+        ms, by = solver.time_kernel("cheb_step", level=0, reps=5)
+        solver.close()
+        log(f"pmc probe: copy 3 x {src.numel() * 8} B; cheb_step 6 launches "
+            f"({by:.0f} algorithmic bytes, {ms * 1e3:.1f} us each)")
+        return
     log(f"workload {args.workload}: n={w['n']} p={w['p']} nodes={mesh.n_nodes} lambda={lam:.6g}")
     t0 = time.perf_counter()
     solver = Solver(mesh.coords, mesh.l2g, w["p"], lam, Options())
@@ -225,6 +331,17 @@ def main():
 
     if not args.no_batched:
         extra["batched"] = batched_leg(torch, Solver, Options)
+    if args.serving != "off":
+        from paper_2512_15121_amd import Server
+        try:
+            if args.serving == "full":
+                extra["serving"] = serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24),
+                                               p_range=(2, 6))
+            else:
+                extra["serving"] = serving_leg(torch, Server, Options)
+        except Exception as e:
+            extra["serving"] = {"error": str(e)}
+            log(f"serving leg failed: {e}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -279,6 +279,66 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
 int giamg_time_kernel(giamg_handle h, int32_t kernel, int32_t level, int32_t reps,
                       double* ms, double* bytes);
 
+
+/* ---- continuous batching ------------------------------------------------
+ * A session holds `slots` right-hand sides of one handle, each with its own
+ * CG state (the block products of giamg_solve_batch; one CG iteration is a
+ * captured HIP graph).  Columns join (admit) and leave (retire) between
+ * steps without disturbing the others: a right-hand side gives the same
+ * bits whatever else shares the session.  Work runs on a stream of the
+ * session's own, ordered after the handle's stream at creation. */
+typedef struct giamg_session_s* giamg_session;
+
+int  giamg_session_create(giamg_handle h, int32_t slots, double tol, giamg_session* out);
+/* Start `count` columns: b[i] (device, n_nodes doubles) into slot slots[i],
+ * zero initial guess.  Asynchronous. */
+int  giamg_session_admit(giamg_session s, int32_t count, const int32_t* slots,
+                         const double* const* b);
+/* Enqueue `iters` CG iterations of every running column.  Asynchronous. */
+int  giamg_session_step(giamg_session s, int32_t iters);
+/* Synchronise; running[j] = 1 while slot j iterates; infos (may be NULL)
+ * get each slot's iterations, status and recursive relative residual. */
+int  giamg_session_poll(giamg_session s, int32_t* running, giamg_info* infos);
+/* Copy slot's solution into x (device, n_nodes doubles) and free the slot. */
+int  giamg_session_retire(giamg_session s, int32_t slot, double* x);
+void giamg_session_free(giamg_session s);
+
+/* ---- serving -------------------------------------------------------------
+ * A request loop on a background thread: requests for registered problems
+ * are continuously batched into sessions (one per resident hierarchy, each
+ * on its own stream, so different hierarchies overlap on the device);
+ * hierarchies stay cached on the device and are set up on a worker thread
+ * when the HBM budget allows, evicting idle ones least recently used first.
+ * Latency runs from giamg_server_submit to the solution being in x. */
+typedef struct giamg_server_s* giamg_server;
+
+typedef struct giamg_server_opts {
+    int64_t hbm_budget;   /* bytes of device memory for hierarchies and slots */
+    int32_t slots;        /* concurrent right-hand sides per hierarchy */
+    int32_t chunk;        /* CG iterations between admission points */
+    double  tol;          /* relative residual target of every request */
+} giamg_server_opts;
+
+typedef struct giamg_server_stats {
+    int64_t submitted, completed, setups, evictions, cache_hits;
+    int64_t peak_bytes, resident_bytes;
+    int32_t groups_resident, pad;
+} giamg_server_statistics;
+
+int  giamg_server_create(const giamg_server_opts* opts, giamg_server* out);
+/* Register a problem (arguments as giamg_setup; host arrays are copied). */
+int  giamg_server_add_problem(giamg_server s, const double* coords, int64_t n_nodes,
+                              const int32_t* l2g, int64_t n_elem, int32_t p, double lambda,
+                              const giamg_opts* opts, int32_t* problem);
+/* Submit b (host, copied) for `problem`; x (host, n_nodes doubles) receives
+ * the solution and must stay valid until giamg_server_wait returns. */
+int  giamg_server_submit(giamg_server s, int32_t problem, const double* b, double* x,
+                         int64_t* request);
+/* Block until the request finishes; returns its status. */
+int  giamg_server_wait(giamg_server s, int64_t request, giamg_info* info, double* latency_ms);
+int  giamg_server_stats(giamg_server s, giamg_server_statistics* out);
+void giamg_server_free(giamg_server s);
+
 /* Thread-local message of the last failing call on this thread. */
 const char* giamg_last_error(void);
 

@@ -231,26 +231,51 @@ __global__ void __launch_bounds__(256) bdot_reduce_kernel(int64_t nb, const doub
 // ---- per-column CG state ------------------------------------------------------
 struct ColState {
     double bb, rr, rz, pq, alpha, beta, rznew, zrold;
-    int active, iters, status, pad;
+    int active, iters, status, init;   // init: column being (re)started
 };
 
+// Starting columns: decide activity from ||b|| and ||r0||; run = any active.
 __global__ void bcg_start_kernel(int k, ColState* st, double tol, int* run) {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
         ColState& s = st[c];
-        s.iters = 0;
-        s.status = GIAMG_OK;
-        s.active = 0;
-        if (s.bb > 0.0 && !(sqrt(s.rr) / sqrt(s.bb) < tol)) {
-            s.active = 1;
-            if (!isfinite(s.rr)) { s.active = 0; s.status = GIAMG_EBREAKDOWN; }
+        if (s.init) {
+            s.iters = 0;
+            s.status = GIAMG_OK;
+            s.active = 0;
+            if (s.bb > 0.0 && !(sqrt(s.rr) / sqrt(s.bb) < tol)) {
+                s.active = 1;
+                if (!isfinite(s.rr)) { s.active = 0; s.status = GIAMG_EBREAKDOWN; }
+            }
         }
         if (s.active) atomicOr(&any, 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) *run = any;
+}
+
+// Finish starting columns: rz = (r, z), clear the flag.
+__global__ void bcg_start_finish_kernel(int k, ColState* st) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState& s = st[c];
+        if (!s.init) continue;
+        if (s.active) {
+            s.rz = s.rznew;
+            if (!isfinite(s.rz)) { s.active = 0; s.status = GIAMG_EBREAKDOWN; }
+        }
+        s.init = 0;
+    }
+}
+
+// dst = src on starting columns
+__global__ void bcopy_init_kernel(int64_t n, int k, const double* __restrict__ src, double* __restrict__ dst,
+                                  const ColState* __restrict__ st) {
+    const int64_t total = n * k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (st[i % k].init) dst[i] = src[i];
 }
 
 __global__ void bcg_alpha_kernel(int k, ColState* st, const int* run) {
@@ -336,7 +361,7 @@ __global__ void bcg_direction_kernel(int64_t n, int k, const double* __restrict_
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const ColState& s = st[i % k];
-        if (!s.active) continue;
+        if (!s.active || (first && !s.init)) continue;
         p[i] = first ? z[i] : z[i] + s.beta * p[i];
     }
 }
@@ -346,21 +371,34 @@ __global__ void bzero_cols_kernel(int64_t n, int k, double* __restrict__ x, cons
     const int64_t total = n * k;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x)
-        if (st[i % k].bb == 0.0) x[i] = 0.0;
+        if (st[i % k].init && st[i % k].bb == 0.0) x[i] = 0.0;
 }
 
 __global__ void bfill_state_kernel(int k, ColState* st) {
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
         ColState z{};
+        z.init = 1;
+        st[c] = z;
+    }
+}
+
+// (re)start the listed slots: zero their state, mark them starting
+__global__ void bmark_init_kernel(int k, ColState* st, const int* slots, int ns) {
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+        const int c = slots[i];
+        if (c < 0 || c >= k) continue;
+        ColState z{};
+        z.init = 1;
         st[c] = z;
     }
 }
 
 // copy a field of the column dots into the state: which = 0 bb, 1 rr, 2 rznew, 3 zrold, 4 pq
 __global__ void bstore_kernel(int k, const double* __restrict__ v, ColState* st, int which,
-                              const int* run) {
+                              int only_init, const int* run) {
     if (run && *run == 0) return;
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        if (only_init && !st[c].init) continue;
         double* f = which == 0 ? &st[c].bb : which == 1 ? &st[c].rr : which == 2 ? &st[c].rznew
                     : which == 3 ? &st[c].zrold : &st[c].pq;
         *f = v[c];
@@ -404,6 +442,11 @@ struct BatchState {
 };
 
 void BatchDeleter::operator()(BatchState* b) const { delete b; }
+
+std::mutex& capture_mutex() {
+    static std::mutex m;
+    return m;
+}
 
 namespace {
 
@@ -606,15 +649,15 @@ void bprecondition(BatchCtx& c, const double* r, double* z) {
     }
 }
 
-// column dots a.b into the state field `which`
-void bdots(BatchCtx& c, const double* a, const double* b, int which) {
+// column dots a.b into the state field `which` (only starting columns if only_init)
+void bdots(BatchCtx& c, const double* a, const double* b, int which, int only_init = 0) {
     const int64_t n = c.H.n_nodes;
     const int64_t nb = (n + DOT_ROWS - 1) / DOT_ROWS;
     if (c.count_bytes) c.H.bytes += 16.0 * n * c.k;
     bdot_partial_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
         n, c.k, a, b, c.B.partial.get(), nb, c.run);
     bdot_reduce_kernel<<<(unsigned)c.k, 256, 0, c.s()>>>(nb, c.B.partial.get(), c.B.dots.get(), c.run);
-    bstore_kernel<<<1, 256, 0, c.s()>>>(c.k, c.B.dots.get(), c.B.st.get(), which, c.run);
+    bstore_kernel<<<1, 256, 0, c.s()>>>(c.k, c.B.dots.get(), c.B.st.get(), which, only_init, c.run);
 }
 
 void bproduct_A0(BatchCtx& c, int mode, const double* v, const double* f, double* y, double rowvecs) {
@@ -650,9 +693,7 @@ void iteration(BatchCtx& c, double* X, double tol) {
     GIAMG_HIP(hipGetLastError());
 }
 
-void ensure_state(Handle& H, int k) {
-    if (H.batch && H.batch->k == k) return;
-    H.batch.reset();
+std::unique_ptr<BatchState> make_state(Handle& H, int k) {
     std::unique_ptr<BatchState> B(new BatchState());
     B->k = k;
     B->mixed = H.opts.precision == GIAMG_PREC_MIXED;
@@ -679,7 +720,55 @@ void ensure_state(Handle& H, int k) {
     GIAMG_HIP(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
     GIAMG_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     GIAMG_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
-    H.batch.reset(B.release());
+    return B;
+}
+
+void ensure_state(Handle& H, int k) {
+    if (H.batch && H.batch->k == k) return;
+    H.batch.reset();
+    H.batch.reset(make_state(H, k).release());
+}
+
+// Start the columns flagged `init` without touching the others (their
+// recursive residuals and directions stay as they are).
+void start_columns(BatchCtx& c, const double* Bm, double* X, double tol) {
+    Handle& H = c.H;
+    BatchState& B = c.B;
+    hipStream_t s = c.s();
+    const int k = c.k;
+    const int64_t total = H.n_nodes * (int64_t)k;
+    const unsigned cb = (unsigned)std::min(k, MAX_K);
+    GIAMG_HIP(hipMemsetAsync(B.run.get(), 0xff, sizeof(int), s));
+    bproduct_A0(c, SPMV_RESID, X, Bm, B.Q.get(), 2);
+    bcopy_init_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, B.Q.get(), B.R.get(), B.st.get());
+    bdots(c, Bm, Bm, 0, 1);
+    bdots(c, B.R.get(), B.R.get(), 1, 1);
+    bcg_start_kernel<<<1, cb, 0, s>>>(k, B.st.get(), tol, B.run.get());
+    bzero_cols_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, X, B.st.get());
+    bprecondition(c, B.R.get(), B.Z.get());
+    bdots(c, B.R.get(), B.Z.get(), 2, 1);
+    bcg_direction_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, B.Z.get(), B.P.get(), B.st.get(), 1,
+                                                      B.run.get());
+    bcg_start_finish_kernel<<<1, cb, 0, s>>>(k, B.st.get());
+    GIAMG_HIP(hipGetLastError());
+}
+
+void tune_all(Handle& H, BatchState& B, int k) {
+    BatchCtx t{H, B, k, nullptr, false};
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+        Level& L = H.levels[l];
+        const std::string sl = std::to_string(l);
+        tile_for<double>(t, L.A, "A" + sl);
+        if (l + 1 == H.levels.size()) continue;
+        if (B.mixed) {
+            tile_for<float>(t, L.A, "A" + sl);
+            tile_for<float>(t, L.R, "R" + sl);
+            tile_for<float>(t, L.P, "P" + sl);
+        } else {
+            tile_for<double>(t, L.R, "R" + sl);
+            tile_for<double>(t, L.P, "P" + sl);
+        }
+    }
 }
 
 }  // namespace
@@ -691,52 +780,26 @@ int solve_batch(Handle& H, const double* Bm, double* X, int32_t k, double tol, g
     hipStream_t s = B.stream;
     GIAMG_HIP(hipEventRecord(B.ev_in, H.stream));
     GIAMG_HIP(hipStreamWaitEvent(s, B.ev_in, 0));
-    const int64_t total = H.n_nodes * (int64_t)k;
     const unsigned cb = (unsigned)std::min(k, MAX_K);
     BatchCtx c{H, B, k, B.run.get(), true};
     H.bytes = 0.0;
     // tune every operator before anything is captured
-    {
-        BatchCtx t{H, B, k, nullptr, false};
-        for (size_t l = 0; l < H.levels.size(); ++l) {
-            Level& L = H.levels[l];
-            const std::string sl = std::to_string(l);
-            tile_for<double>(t, L.A, "A" + sl);
-            if (B.mixed && l + 1 < H.levels.size()) {
-                tile_for<float>(t, L.A, "A" + sl);
-                tile_for<float>(t, L.R, "R" + sl);
-                tile_for<float>(t, L.P, "P" + sl);
-            } else if (l + 1 < H.levels.size()) {
-                tile_for<double>(t, L.R, "R" + sl);
-                tile_for<double>(t, L.P, "P" + sl);
-            }
-        }
-    }
+    tune_all(H, B, k);
     hipEvent_t t0, t1;
     GIAMG_HIP(hipEventCreate(&t0));
     GIAMG_HIP(hipEventCreate(&t1));
     GIAMG_HIP(hipEventRecord(t0, s));
-    // start: r = b - A x, norms, activity, z = V(r), rz, p = z
+    // start every column: r = b - A x, norms, activity, z = V(r), rz, p = z
     GIAMG_HIP(hipMemsetAsync(B.run.get(), 0xff, sizeof(int), s));   // run everything
     bfill_state_kernel<<<1, cb, 0, s>>>(k, B.st.get());
-    bproduct_A0(c, SPMV_RESID, X, Bm, B.R.get(), 2);
-    bdots(c, Bm, Bm, 0);
-    bdots(c, B.R.get(), B.R.get(), 1);
-    bcg_start_kernel<<<1, cb, 0, s>>>(k, B.st.get(), tol, B.run.get());
-    bzero_cols_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, X, B.st.get());
-    bprecondition(c, B.R.get(), B.Z.get());
-    bdots(c, B.R.get(), B.Z.get(), 2);
-    // rz = rznew for the first direction (its beta is not used: p = z)
-    bcg_beta_kernel<<<1, cb, 0, s>>>(k, B.st.get(), 0, B.run.get());
-    bcg_direction_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, B.Z.get(), B.P.get(), B.st.get(), 1,
-                                                      B.run.get());
-    GIAMG_HIP(hipGetLastError());
+    start_columns(c, Bm, X, tol);
     const double bytes_start = H.bytes;
     // capture one iteration (pointers are fixed for this k and these b, x)
     if (!B.exec || B.graph_b != Bm || B.graph_x != X || B.graph_tol != tol) {
         if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
         if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
-        GIAMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        GIAMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
         try {
             iteration(c, X, tol);
         } catch (...) {
@@ -805,6 +868,188 @@ int solve_batch(Handle& H, const double* Bm, double* X, int32_t k, double tol, g
     }
     (void)launched;
     return worst;
+}
+
+
+// ---------------------------------------------------------------------------
+// continuous-batching sessions: slots join and leave between iterations
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void bclear_state_kernel(int k, ColState* st) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ColState z{};
+        st[c] = z;
+    }
+}
+
+// column `slot` of the block X [n][k] <- b [n]; x column <- 0
+__global__ void bscatter_kernel(int64_t n, int k, int slot, const double* __restrict__ b,
+                                double* __restrict__ Bm, double* __restrict__ X) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        Bm[i * k + slot] = b[i];
+        X[i * k + slot] = 0.0;
+    }
+}
+
+__global__ void bgather_kernel(int64_t n, int k, int slot, const double* __restrict__ X, double* __restrict__ x) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = X[i * k + slot];
+}
+
+__global__ void bfree_slot_kernel(int k, ColState* st, int slot) {
+    if (threadIdx.x == 0 && slot >= 0 && slot < k) {
+        ColState z{};
+        st[slot] = z;
+    }
+}
+
+}  // namespace
+
+struct Session {
+    Handle* H = nullptr;
+    std::unique_ptr<BatchState> B;
+    int k = 0;
+    double tol = 0.0;
+    DevBuf<double> Bm, X;
+    DevBuf<int> slots;
+    hipEvent_t done = nullptr;
+    ~Session() {
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+
+Session* session_create(Handle& H, int k, double tol) {
+    GIAMG_REQUIRE(k >= 1 && k <= MAX_K, "slots must be in [1, 1024]");
+    std::unique_ptr<Session> S(new Session());
+    S->H = &H;
+    S->k = k;
+    S->tol = tol;
+    S->B = make_state(H, k);
+    BatchState& B = *S->B;
+    hipStream_t s = B.stream;
+    GIAMG_HIP(hipEventRecord(B.ev_in, H.stream));
+    GIAMG_HIP(hipStreamWaitEvent(s, B.ev_in, 0));
+    const size_t tot = (size_t)H.n_nodes * k;
+    S->Bm.alloc(tot);
+    S->X.alloc(tot);
+    S->slots.alloc(k);
+    GIAMG_HIP(hipMemsetAsync(S->Bm.get(), 0, tot * sizeof(double), s));
+    GIAMG_HIP(hipMemsetAsync(S->X.get(), 0, tot * sizeof(double), s));
+    for (DevBuf<double>* v : {&B.R, &B.Z, &B.P, &B.Q})
+        GIAMG_HIP(hipMemsetAsync(v->get(), 0, tot * sizeof(double), s));
+    bclear_state_kernel<<<1, 256, 0, s>>>(k, B.st.get());
+    GIAMG_HIP(hipMemsetAsync(B.run.get(), 0, sizeof(int), s));
+    tune_all(H, B, k);
+    BatchCtx c{H, B, k, B.run.get(), false};
+    {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        GIAMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        try {
+            iteration(c, S->X.get(), tol);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        GIAMG_HIP(hipStreamEndCapture(s, &B.graph));
+    }
+    GIAMG_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    GIAMG_HIP(hipEventCreateWithFlags(&S->done, hipEventDisableTiming));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    return S.release();
+}
+
+void session_destroy(Session* S) {
+    if (!S) return;
+    if (S->B) (void)hipStreamSynchronize(S->B->stream);
+    delete S;
+}
+
+// Copy each b (device, n entries) into its slot and start those columns.
+void session_admit(Session* S, const int* slot, const double* const* b, int count) {
+    BatchState& B = *S->B;
+    Handle& H = *S->H;
+    hipStream_t s = B.stream;
+    GIAMG_REQUIRE(count >= 1 && count <= S->k, "bad admission count");
+    std::vector<int> sl(slot, slot + count);
+    // the right-hand sides were written on the caller's stream
+    GIAMG_HIP(hipEventRecord(B.ev_in, H.stream));
+    GIAMG_HIP(hipStreamWaitEvent(s, B.ev_in, 0));
+    for (int i = 0; i < count; ++i) {
+        GIAMG_REQUIRE(sl[i] >= 0 && sl[i] < S->k, "slot out of range");
+        bscatter_kernel<<<bgrid(H.n_nodes), 256, 0, s>>>(H.n_nodes, S->k, sl[i], b[i], S->Bm.get(), S->X.get());
+    }
+    GIAMG_HIP(hipMemcpyAsync(S->slots.get(), sl.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
+    bmark_init_kernel<<<1, 256, 0, s>>>(S->k, B.st.get(), S->slots.get(), count);
+    BatchCtx c{H, B, S->k, B.run.get(), false};
+    start_columns(c, S->Bm.get(), S->X.get(), S->tol);
+    GIAMG_HIP(hipEventRecord(S->done, s));
+}
+
+// Enqueue `iters` CG iterations for every running slot (asynchronous).
+void session_step(Session* S, int iters) {
+    for (int i = 0; i < iters; ++i) GIAMG_HIP(hipGraphLaunch(S->B->exec, S->B->stream));
+    GIAMG_HIP(hipEventRecord(S->done, S->B->stream));
+}
+
+bool session_ready(Session* S) {
+    const hipError_t e = hipEventQuery(S->done);
+    if (e == hipSuccess) return true;
+    if (e == hipErrorNotReady) return false;
+    GIAMG_HIP(e);
+    return false;
+}
+
+// Slot states: 1 running, 0 otherwise (free or finished: the caller tracks
+// occupancy); infos describe every slot.
+void session_poll(Session* S, int* state, giamg_info* infos) {
+    BatchState& B = *S->B;
+    std::vector<ColState> hs(S->k);
+    GIAMG_HIP(hipMemcpyAsync(hs.data(), B.st.get(), S->k * sizeof(ColState), hipMemcpyDeviceToHost, B.stream));
+    GIAMG_HIP(hipStreamSynchronize(B.stream));
+    for (int j = 0; j < S->k; ++j) {
+        const ColState& c = hs[j];
+        state[j] = (c.active || c.init) ? 1 : 0;
+        if (infos) {
+            infos[j].iters = c.iters;
+            infos[j].status = c.status;
+            infos[j].relres = c.bb > 0 ? std::sqrt(c.rr) / std::sqrt(c.bb) : 0.0;
+            infos[j].true_relres = -1.0;
+            infos[j].solve_ms = 0.0;
+            infos[j].bytes = 0.0;
+        }
+    }
+}
+
+// Copy the slot's solution to x (device, n entries) and free the slot.
+void session_retire(Session* S, int slot, double* x) {
+    GIAMG_REQUIRE(slot >= 0 && slot < S->k, "slot out of range");
+    BatchState& B = *S->B;
+    Handle& H = *S->H;
+    // x may still be in use on the caller's stream
+    GIAMG_HIP(hipEventRecord(B.ev_in, H.stream));
+    GIAMG_HIP(hipStreamWaitEvent(B.stream, B.ev_in, 0));
+    bgather_kernel<<<bgrid(H.n_nodes), 256, 0, B.stream>>>(H.n_nodes, S->k, slot, S->X.get(), x);
+    bfree_slot_kernel<<<1, 64, 0, B.stream>>>(S->k, B.st.get(), slot);
+    GIAMG_HIP(hipGetLastError());
+    GIAMG_HIP(hipStreamSynchronize(B.stream));
+}
+
+hipStream_t session_stream(Session* S) { return S->B->stream; }
+
+int64_t session_device_bytes(const Session* S) {
+    const BatchState& B = *S->B;
+    int64_t b = 0;
+    for (const auto& l : B.lv)
+        b += (int64_t)(l.f.n + l.x.n + l.r.n + l.d0.n + l.d1.n + l.t.n) * 8 +
+             (int64_t)(l.f32.n + l.x32.n + l.r32.n + l.d032.n + l.d132.n + l.t32.n) * 4;
+    b += (int64_t)(B.R.n + B.Z.n + B.P.n + B.Q.n + B.Rold.n + B.partial.n) * 8;
+    b += (int64_t)(S->Bm.n + S->X.n) * 8;
+    return b;
 }
 
 }  // namespace giamg

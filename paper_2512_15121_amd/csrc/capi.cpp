@@ -21,10 +21,24 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info);
 int solve_batch(Handle& H, const double* B, double* X, int32_t k, double tol, giamg_info* infos);
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out);
 void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes);
+struct Session;
+Session* session_create(Handle& H, int k, double tol);
+void session_destroy(Session* S);
+void session_admit(Session* S, const int* slot, const double* const* b, int count);
+void session_step(Session* S, int iters);
+void session_poll(Session* S, int* state, giamg_info* infos);
+void session_retire(Session* S, int slot, double* x);
+}  // namespace giamg
+
+namespace giamg {
+std::string& last_error() {
+    thread_local std::string msg;
+    return msg;
+}
 }  // namespace giamg
 
 namespace {
-thread_local std::string g_last_error;
+#define g_last_error (::giamg::last_error())
 
 template <typename F>
 int guarded(F&& f) {
@@ -384,6 +398,66 @@ int giamg_time_kernel(giamg_handle h, int32_t kernel, int32_t level, int32_t rep
         giamg::time_kernel(h->h, kernel, level, reps, ms, bytes);
         return GIAMG_OK;
     });
+}
+
+struct giamg_session_s {
+    giamg::Session* s = nullptr;
+    giamg_s* owner = nullptr;
+};
+
+int giamg_session_create(giamg_handle h, int32_t slots, double tol, giamg_session* out) {
+    return guarded([&]() -> int {
+        bind_device(h);
+        GIAMG_REQUIRE(out != nullptr, "out is null");
+        GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
+        giamg::Session* S = giamg::session_create(h->h, slots, tol);
+        *out = new giamg_session_s{S, h};
+        return GIAMG_OK;
+    });
+}
+
+int giamg_session_admit(giamg_session s, int32_t count, const int32_t* slots, const double* const* b) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(s && slots && b, "null argument");
+        bind_device(s->owner);
+        for (int i = 0; i < count; ++i) GIAMG_REQUIRE(b[i] != nullptr, "null right-hand side");
+        giamg::session_admit(s->s, slots, b, count);
+        return GIAMG_OK;
+    });
+}
+
+int giamg_session_step(giamg_session s, int32_t iters) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(s && iters >= 0, "bad argument");
+        bind_device(s->owner);
+        giamg::session_step(s->s, iters);
+        return GIAMG_OK;
+    });
+}
+
+int giamg_session_poll(giamg_session s, int32_t* running, giamg_info* infos) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(s && running, "null argument");
+        bind_device(s->owner);
+        giamg::session_poll(s->s, running, infos);
+        return GIAMG_OK;
+    });
+}
+
+int giamg_session_retire(giamg_session s, int32_t slot, double* x) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(s && x, "null argument");
+        bind_device(s->owner);
+        giamg::session_retire(s->s, slot, x);
+        return GIAMG_OK;
+    });
+}
+
+void giamg_session_free(giamg_session s) {
+    if (!s) return;
+    (void)hipSetDevice(s->owner->device);
+    giamg::session_destroy(s->s);
+    delete s;
 }
 
 const char* giamg_last_error(void) { return g_last_error.c_str(); }

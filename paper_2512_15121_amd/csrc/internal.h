@@ -7,6 +7,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -172,6 +173,9 @@ HostCSR transpose(const HostCSR& M);
 bool spd_inverse(const std::vector<double>& A, int64_t n, std::vector<double>& inv);
 
 uint64_t splitmix64(uint64_t seed, uint64_t i);
+// Held while a HIP graph is captured, and by threads of the library that
+// could otherwise issue synchronising calls during another thread's capture.
+std::mutex& capture_mutex();
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)>& fn);
 
 // ---- device helpers (kernels_*.hip) ----------------------------------------

@@ -296,6 +296,22 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     H.setup_ms[6] = ms_since(t_all);
 }
 
+int64_t handle_device_bytes(const Handle& H) {
+    auto csr = [](const DevCSR& m) {
+        return (int64_t)(m.rp.n + m.rblk.n) * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 +
+               (int64_t)m.val32.n * 4;
+    };
+    int64_t b = 0;
+    for (const Level& L : H.levels) {
+        b += csr(L.A) + csr(L.P) + csr(L.R);
+        b += (int64_t)(L.dinv.n + L.f.n + L.x.n + L.r.n + L.d0.n + L.d1.n + L.t.n) * 8;
+        b += (int64_t)(L.dinv32.n + L.f32.n + L.x32.n + L.r32.n + L.d032.n + L.d132.n + L.t32.n) * 4;
+    }
+    b += (int64_t)H.coarse_inv.n * 8;
+    b += (int64_t)(H.x.n + H.r.n + H.z.n + H.p.n + H.q.n + H.rold.n + H.tmp.n + H.partial.n) * 8;
+    return b;
+}
+
 // ---------------------------------------------------------------------------
 // V-cycle
 // ---------------------------------------------------------------------------

@@ -47,6 +47,19 @@ class _Info(ctypes.Structure):
                 ("solve_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("setups", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("cache_hits", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_int64), ("groups_resident", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
 class _LevelDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("coarsest", ctypes.c_int32), ("pad", ctypes.c_int32),
@@ -118,6 +131,18 @@ _SIGNATURES = {
     "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, P, P, ctypes.POINTER(P)]),
     "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, P, P, ctypes.POINTER(P)]),
     "giamg_time_kernel": (I32, [P, I32, I32, I32, P, P]),
+    "giamg_session_create": (I32, [P, I32, F64, ctypes.POINTER(P)]),
+    "giamg_session_admit": (I32, [P, I32, P, P]),
+    "giamg_session_step": (I32, [P, I32]),
+    "giamg_session_poll": (I32, [P, P, P]),
+    "giamg_session_retire": (I32, [P, I32, P]),
+    "giamg_session_free": (None, [P]),
+    "giamg_server_create": (I32, [P, ctypes.POINTER(P)]),
+    "giamg_server_add_problem": (I32, [P, P, I64, P, I64, I32, F64, ctypes.POINTER(_Opts), P]),
+    "giamg_server_submit": (I32, [P, I32, P, P, P]),
+    "giamg_server_wait": (I32, [P, I64, P, P]),
+    "giamg_server_stats": (I32, [P, P]),
+    "giamg_server_free": (None, [P]),
 }
 KERNEL = {"cheb_step": 0, "spmv": 1, "restrict": 2, "prolong": 3}
 
@@ -339,3 +364,110 @@ def host_aggregate(rp, ci, val, seed=0):
     _check(library().giamg_host_aggregate(_ptr(rp), _ptr(ci), _ptr(val), n, seed, _ptr(agg),
                                           ctypes.byref(na), ctypes.byref(h)))
     return agg, na.value, _take_hcsr(h)
+
+
+# ---- continuous batching ---------------------------------------------------
+def _info(i):
+    return SolveInfo(i.iters, i.status, i.relres, i.true_relres, i.solve_ms, i.bytes)
+
+
+class Session:
+    """Slots of one solver that right-hand sides join and leave between steps."""
+
+    def __init__(self, solver: Solver, slots: int, tol: float = 1e-10):
+        self.lib = library()
+        self.solver = solver
+        self.slots = slots
+        self._s = ctypes.c_void_p()
+        _check(self.lib.giamg_session_create(solver._h, slots, float(tol), ctypes.byref(self._s)))
+        self._keep = {}
+
+    def admit(self, slots, bs):
+        arr = (ctypes.c_int32 * len(slots))(*slots)
+        ptrs = (ctypes.c_void_p * len(bs))(*[b.data_ptr() for b in bs])
+        for s_, b in zip(slots, bs):
+            self._keep[s_] = b          # the kernels read b asynchronously
+        _check(self.lib.giamg_session_admit(self._s, len(slots), arr, ptrs))
+
+    def step(self, iters):
+        _check(self.lib.giamg_session_step(self._s, iters))
+
+    def poll(self):
+        running = np.zeros(self.slots, dtype=np.int32)
+        infos = (_Info * self.slots)()
+        _check(self.lib.giamg_session_poll(self._s, _ptr(running), infos))
+        return running.astype(bool), [_info(i) for i in infos]
+
+    def retire(self, slot, out):
+        _check(self.lib.giamg_session_retire(self._s, slot, _dev(out)))
+        self._keep.pop(slot, None)
+        return out
+
+    def close(self):
+        if self._s:
+            self.lib.giamg_session_free(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop with continuous batching, device hierarchy cache and HBM
+    budget (runs on a background thread inside the library)."""
+
+    def __init__(self, hbm_budget, slots=8, chunk=2, tol=1e-10):
+        self.lib = library()
+        o = _ServerOpts(int(hbm_budget), int(slots), int(chunk), float(tol))
+        self._s = ctypes.c_void_p()
+        _check(self.lib.giamg_server_create(ctypes.byref(o), ctypes.byref(self._s)))
+        self._sizes = []
+        self._out = {}
+
+    def add_problem(self, coords, l2g, p, lam, opts: Options = None):
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+        pid = ctypes.c_int32()
+        co = (opts or Options())._c()
+        _check(self.lib.giamg_server_add_problem(self._s, _ptr(coords), coords.shape[0], _ptr(l2g),
+                                                 l2g.shape[0], int(p), float(lam), ctypes.byref(co),
+                                                 ctypes.byref(pid)))
+        self._sizes.append(coords.shape[0])
+        return pid.value
+
+    def submit(self, problem, b):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        assert b.size == self._sizes[problem]
+        x = np.zeros_like(b)
+        rid = ctypes.c_int64()
+        _check(self.lib.giamg_server_submit(self._s, problem, _ptr(b), _ptr(x), ctypes.byref(rid)))
+        self._out[rid.value] = x
+        return rid.value
+
+    def wait(self, request):
+        info = _Info()
+        lat = ctypes.c_double()
+        rc = self.lib.giamg_server_wait(self._s, request, ctypes.byref(info), ctypes.byref(lat))
+        x = self._out.pop(request)
+        if rc < 0:
+            raise GiamgError(rc, library().giamg_last_error().decode())
+        return x, _info(info), lat.value
+
+    def stats(self):
+        st = _ServerStats()
+        _check(self.lib.giamg_server_stats(self._s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_ if f != "pad"}
+
+    def close(self):
+        if self._s:
+            self.lib.giamg_server_free(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
