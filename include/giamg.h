@@ -154,6 +154,9 @@ int giamg_solve_batch(giamg_handle h, const double* B, double* X, int32_t k,
 #define GIAMG_MAT_A          0
 #define GIAMG_MAT_P          1   /* prolongation to the next coarser level */
 #define GIAMG_MAT_R          2   /* restriction R = P^T */
+#define GIAMG_MAT_AP         3   /* A P, the left factor of the Galerkin product (rows of
+                                    this level, columns of the next); the post-smoother
+                                    uses it for its first residual after the correction */
 
 typedef struct giamg_level_desc {
     int32_t kind;        /* GIAMG_LEVEL_* */
@@ -163,6 +166,7 @@ typedef struct giamg_level_desc {
     int64_t rows;        /* rows of A on this level */
     int64_t nnz_A, nnz_P, nnz_R;   /* P/R are 0 on the coarsest level */
     double  lam_hat;     /* lambda_max(D^-1 A) estimate (0 on the coarsest level) */
+    int64_t nnz_AP;      /* 0 on the coarsest level */
 } giamg_level_desc;
 
 int giamg_num_levels(giamg_handle h);

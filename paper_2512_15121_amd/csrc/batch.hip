@@ -461,6 +461,7 @@ template <> struct BL<double> {
     static const double* A(const Level& L) { return L.A.val.get(); }
     static const double* P(const Level& L) { return L.P.val.get(); }
     static const double* R(const Level& L) { return L.R.val.get(); }
+    static const double* AP(const Level& L) { return L.AP.val.get(); }
     static const double* dinv(const Level& L) { return L.dinv.get(); }
 };
 template <> struct BL<float> {
@@ -473,6 +474,7 @@ template <> struct BL<float> {
     static const float* A(const Level& L) { return L.A.val32.get(); }
     static const float* P(const Level& L) { return L.P.val32.get(); }
     static const float* R(const Level& L) { return L.R.val32.get(); }
+    static const float* AP(const Level& L) { return L.AP.val32.get(); }
     static const float* dinv(const Level& L) { return L.dinv32.get(); }
 };
 
@@ -544,8 +546,11 @@ Tile tile_for(BatchCtx& c, const DevCSR& M, const std::string& key) {
     return best;
 }
 
+// Post-smoothing after the coarse correction x = x' + P e takes the residual
+// t = f - A x' and e: its first product is t - (A P) e.
 template <typename T>
-void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start) {
+void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start, const T* t = nullptr,
+             const T* e = nullptr) {
     Handle& H = c.H;
     Level& L = H.levels[l];
     BatchLevel& W = c.B.lv[l];
@@ -583,9 +588,12 @@ void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start) {
         bcheb_init0_kernel<T><<<bgrid(total), 256, 0, c.s()>>>(L.n, k, f, BL<T>::dinv(L), r, d[0], x,
                                                                 (T)(1.0 / theta), deg == 1, c.run);
     } else {
-        SpmmArgs<T> a = bargs<T>(L.A, BL<T>::A(L), k, c.run);
-        a.v = x; a.f = f; a.r = r; a.y = d[0]; a.dinv = BL<T>::dinv(L); a.inv_theta = (T)(1.0 / theta);
-        spmm<T>(c, SPMV_CHEB_INIT, L.A, a, key, 4);
+        const bool ap = e != nullptr;
+        const DevCSR& M = ap ? L.AP : L.A;
+        SpmmArgs<T> a = bargs<T>(M, ap ? BL<T>::AP(L) : BL<T>::A(L), k, c.run);
+        a.v = ap ? e : x; a.f = ap ? t : f; a.r = r; a.y = d[0]; a.dinv = BL<T>::dinv(L);
+        a.inv_theta = (T)(1.0 / theta);
+        spmm<T>(c, SPMV_CHEB_INIT, M, a, ap ? "AP" + std::to_string(l) : key, 4);
         if (deg == 1) {
             if (c.count_bytes) H.bytes += 3.0 * sizeof(T) * total;
             bconvert_kernel<T, T><<<bgrid(total), 256, 0, c.s()>>>(total, d[0], x, 1, c.run);
@@ -633,7 +641,7 @@ void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
         a.v = BL<T>::x(WC); a.y = x;
         spmm<T>(c, SPMV_ADD, L.P, a, "P" + sl, 2);
     }
-    bsmooth<T>(c, l, f, x, false);
+    bsmooth<T>(c, l, f, x, false, BL<T>::t(W), BL<T>::x(WC));
 }
 
 void bprecondition(BatchCtx& c, const double* r, double* z) {
@@ -760,13 +768,16 @@ void tune_all(Handle& H, BatchState& B, int k) {
         const std::string sl = std::to_string(l);
         tile_for<double>(t, L.A, "A" + sl);
         if (l + 1 == H.levels.size()) continue;
+        const bool ap = H.opts.smoother == GIAMG_SMOOTHER_CHEBYSHEV;
         if (B.mixed) {
             tile_for<float>(t, L.A, "A" + sl);
             tile_for<float>(t, L.R, "R" + sl);
             tile_for<float>(t, L.P, "P" + sl);
+            if (ap) tile_for<float>(t, L.AP, "AP" + sl);
         } else {
             tile_for<double>(t, L.R, "R" + sl);
             tile_for<double>(t, L.P, "P" + sl);
+            if (ap) tile_for<double>(t, L.AP, "AP" + sl);
         }
     }
 }

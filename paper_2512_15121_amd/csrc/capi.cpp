@@ -194,6 +194,7 @@ int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out) {
         out->nnz_P = L.P.nnz;
         out->nnz_R = L.R.nnz;
         out->lam_hat = L.lam_hat;
+        out->nnz_AP = L.AP.nnz;
         return GIAMG_OK;
     });
 }
@@ -207,7 +208,8 @@ int giamg_level_csr(giamg_handle h, int32_t level, int32_t which, int64_t* row_p
         const giamg::DevCSR* M = which == GIAMG_MAT_A ? &L.A
                                  : which == GIAMG_MAT_P ? &L.P
                                  : which == GIAMG_MAT_R ? &L.R
-                                                        : nullptr;
+                                 : which == GIAMG_MAT_AP ? &L.AP
+                                                         : nullptr;
         GIAMG_REQUIRE(M != nullptr, "unknown matrix");
         GIAMG_REQUIRE(M->nrows > 0 || which == GIAMG_MAT_A, "matrix absent on this level");
         hipStream_t s = h->h.stream;

@@ -105,6 +105,8 @@ struct Level {
     int order = 1;
     int64_t n = 0;
     DevCSR A, P, R;                // P, R empty on the coarsest level
+    DevCSR AP;                     // A P (rows of this level, columns of the next), kept
+                                   // from the Galerkin product for the post-smoothing residual
     DevBuf<double> dinv;
     DevBuf<float> dinv32;
     double lam_hat = 0.0;

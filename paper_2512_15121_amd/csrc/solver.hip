@@ -190,14 +190,13 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         upload_csr(P, F.P, H.stream, mixed);
         upload_csr(R, F.R, H.stream, mixed);
         t0 = clock_t_::now();
-        DevCSR AP;
-        spgemm(F.A, F.P, AP, H.stream);
+        spgemm(F.A, F.P, F.AP, H.stream);
         Level C;
         C.kind = GIAMG_LEVEL_P;
         C.order = q;
         C.n = nc;
         C.l2g = std::move(l2g_next);
-        spgemm(F.R, AP, C.A, H.stream);
+        spgemm(F.R, F.AP, C.A, H.stream);
         H.setup_ms[3] += ms_since(t0);
         H.levels.push_back(std::move(C));
         free_mask.assign(nc, 1);
@@ -221,13 +220,12 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         upload_csr(P, F.P, H.stream, mixed);
         upload_csr(R, F.R, H.stream, mixed);
         t0 = clock_t_::now();
-        DevCSR AP;
-        spgemm(F.A, F.P, AP, H.stream);
+        spgemm(F.A, F.P, F.AP, H.stream);
         Level C;
         C.kind = GIAMG_LEVEL_H;
         C.order = 1;
         C.n = nagg;
-        spgemm(F.R, AP, C.A, H.stream);
+        spgemm(F.R, F.AP, C.A, H.stream);
         H.setup_ms[3] += ms_since(t0);
         H.levels.push_back(std::move(C));
     }
@@ -256,7 +254,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     int64_t maxn = 1, maxblk = 1;
     for (auto& L : H.levels) {
         maxn = std::max(maxn, L.n);
-        maxblk = std::max({maxblk, L.A.nblk, L.P.nblk, L.R.nblk});
+        maxblk = std::max({maxblk, L.A.nblk, L.P.nblk, L.R.nblk, L.AP.nblk});
     }
     H.partial_cap = std::max<int64_t>(2 * maxblk, 2 * vec_blocks(maxn)) + 16;
     H.partial.alloc(H.partial_cap);
@@ -270,6 +268,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         alloc_level_vectors(L, mixed);
         if (mixed) make_fp32_values(L.A, H.stream);
         if (l + 1 == H.levels.size()) break;
+        if (mixed) make_fp32_values(L.AP, H.stream);
         L.dinv.alloc(L.n);
         DevBuf<int> bad(1);
         GIAMG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), H.stream));
@@ -303,7 +302,7 @@ int64_t handle_device_bytes(const Handle& H) {
     };
     int64_t b = 0;
     for (const Level& L : H.levels) {
-        b += csr(L.A) + csr(L.P) + csr(L.R);
+        b += csr(L.A) + csr(L.P) + csr(L.R) + csr(L.AP);
         b += (int64_t)(L.dinv.n + L.f.n + L.x.n + L.r.n + L.d0.n + L.d1.n + L.t.n) * 8;
         b += (int64_t)(L.dinv32.n + L.f32.n + L.x32.n + L.r32.n + L.d032.n + L.d132.n + L.t32.n) * 4;
     }
@@ -322,6 +321,7 @@ template <> struct LV<double> {
     static const double* A(const Level& L) { return L.A.val.get(); }
     static const double* P(const Level& L) { return L.P.val.get(); }
     static const double* R(const Level& L) { return L.R.val.get(); }
+    static const double* AP(const Level& L) { return L.AP.val.get(); }
     static const double* dinv(const Level& L) { return L.dinv.get(); }
     static double* f(Level& L) { return L.f.get(); }
     static double* x(Level& L) { return L.x.get(); }
@@ -334,6 +334,7 @@ template <> struct LV<float> {
     static const float* A(const Level& L) { return L.A.val32.get(); }
     static const float* P(const Level& L) { return L.P.val32.get(); }
     static const float* R(const Level& L) { return L.R.val32.get(); }
+    static const float* AP(const Level& L) { return L.AP.val32.get(); }
     static const float* dinv(const Level& L) { return L.dinv32.get(); }
     static float* f(Level& L) { return L.f32.get(); }
     static float* x(Level& L) { return L.x32.get(); }
@@ -344,12 +345,18 @@ template <> struct LV<float> {
 };
 
 template <typename T>
-SpmvArgs<T> args_A(const Level& L) {
+SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     SpmvArgs<T> a;
-    a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = LV<T>::A(L); a.n = L.n;
+    a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows;
+    a.nnz = M.nnz; a.ncols = M.ncols;
+    a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
+    return a;
+}
+
+template <typename T>
+SpmvArgs<T> args_A(const Level& L) {
+    SpmvArgs<T> a = args_of<T>(L.A, LV<T>::A(L));
     a.dinv = LV<T>::dinv(L);
-    a.nnz = L.A.nnz; a.ncols = L.A.ncols;
-    a.rblk = L.A.rblk.get(); a.nblk = L.A.nblk; a.lanes = L.A.lanes;
     return a;
 }
 
@@ -407,8 +414,13 @@ ChebCoef cheb_coef(const Handle& H, const Level& L) {
 // The update of x by d_j is deferred into the next product's epilogue (the
 // product gathers d, never x), so no kernel reads and writes x at once.
 // zero_start: pre-smoothing from x = 0 (x is not read).
+// Post-smoothing after a coarse correction x = x' + P e may pass the residual
+// t = f - A x' from before the correction and the coarse vector e: then
+// f - A x = t - (A P) e, a product with A P, whose rows are several times
+// shorter than those of A on the p-levels.
 template <typename T>
-void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
+void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start,
+                      const T* t = nullptr, const T* e = nullptr) {
     const int k = H.opts.degree;
     const ChebCoef c = cheb_coef(H, L);
     T* r = LV<T>::r(L);
@@ -416,6 +428,15 @@ void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
     if (zero_start) {
         H.bytes += (k == 1 ? 5.0 : 4.0) * sizeof(T) * L.n;
         launch_cheb_init0<T>(L.n, f, LV<T>::dinv(L), r, d[0], x, (T)c.inv_theta, k == 1, H.stream);
+    } else if (e != nullptr) {
+        SpmvArgs<T> a = args_of<T>(L.AP, LV<T>::AP(L));
+        a.dinv = LV<T>::dinv(L);
+        a.v = e; a.f = t; a.r = r; a.y = d[0]; a.inv_theta = (T)c.inv_theta;
+        run_spmv(H, SPMV_CHEB_INIT, a);
+        if (k == 1) {
+            H.bytes += 3.0 * sizeof(T) * L.n;
+            launch_add<T>(L.n, d[0], x, H.stream);
+        }
     } else {
         SpmvArgs<T> a = args_A<T>(L);
         a.v = x; a.f = f; a.r = r; a.y = d[0]; a.inv_theta = (T)c.inv_theta;
@@ -459,9 +480,10 @@ void smooth_jacobi(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
 }
 
 template <typename T>
-void smooth(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
+void smooth(Handle& H, Level& L, const T* f, T* x, bool zero_start, const T* t = nullptr,
+            const T* e = nullptr) {
     if (H.opts.smoother == GIAMG_SMOOTHER_CHEBYSHEV)
-        smooth_chebyshev<T>(H, L, f, x, zero_start);
+        smooth_chebyshev<T>(H, L, f, x, zero_start, t, e);
     else
         smooth_jacobi<T>(H, L, f, x, zero_start);
 }
@@ -475,20 +497,14 @@ void residual(Handle& H, Level& L, const T* f, const T* x, T* out) {
 
 template <typename T>
 void restrict_to(Handle& H, Level& L, const T* r, T* fc) {
-    SpmvArgs<T> a;
-    a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
-    a.nnz = L.R.nnz; a.ncols = L.R.ncols;
-    a.rblk = L.R.rblk.get(); a.nblk = L.R.nblk; a.lanes = L.R.lanes;
+    SpmvArgs<T> a = args_of<T>(L.R, LV<T>::R(L));
     a.v = r; a.y = fc;
     run_spmv(H, SPMV_PLAIN, a);
 }
 
 template <typename T>
 void prolong_add(Handle& H, Level& L, const T* ec, T* x) {
-    SpmvArgs<T> a;
-    a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
-    a.nnz = L.P.nnz; a.ncols = L.P.ncols;
-    a.rblk = L.P.rblk.get(); a.nblk = L.P.nblk; a.lanes = L.P.lanes;
+    SpmvArgs<T> a = args_of<T>(L.P, LV<T>::P(L));
     a.v = ec; a.y = x;
     run_spmv(H, SPMV_ADD, a);
 }
@@ -508,7 +524,7 @@ void vcycle(Handle& H, size_t l, const T* f, T* x) {
     restrict_to<T>(H, L, LV<T>::t(L), LV<T>::f(C));
     vcycle<T>(H, l + 1, LV<T>::f(C), LV<T>::x(C));
     prolong_add<T>(H, L, LV<T>::x(C), x);
-    smooth<T>(H, L, f, x, false);
+    smooth<T>(H, L, f, x, false, LV<T>::t(L), LV<T>::x(C));
 }
 
 void precondition(Handle& H, const double* r, double* z) {

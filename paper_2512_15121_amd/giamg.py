@@ -19,7 +19,7 @@ SMOOTHER = {"chebyshev": 0, "jacobi": 1}
 BC = {"dirichlet": 0, "pin": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 LEVEL_KIND = {0: "p", 1: "h"}
-MAT = {"A": 0, "P": 1, "R": 2}
+MAT = {"A": 0, "P": 1, "R": 2, "AP": 3}
 OP = {"spmv": 0, "residual": 1, "restrict": 2, "prolong_add": 3, "presmooth": 4,
       "postsmooth": 5, "coarse": 6, "vcycle": 7}
 OP_FP32 = 256
@@ -65,7 +65,7 @@ class _LevelDesc(ctypes.Structure):
                 ("coarsest", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("nnz_A", ctypes.c_int64),
                 ("nnz_P", ctypes.c_int64), ("nnz_R", ctypes.c_int64),
-                ("lam_hat", ctypes.c_double)]
+                ("lam_hat", ctypes.c_double), ("nnz_AP", ctypes.c_int64)]
 
 
 @dataclass
@@ -247,7 +247,7 @@ class Solver:
         _check(self.lib.giamg_level_describe(self._h, l, ctypes.byref(d)))
         return {"kind": LEVEL_KIND[d.kind], "order": d.order, "coarsest": bool(d.coarsest),
                 "rows": d.rows, "nnz_A": d.nnz_A, "nnz_P": d.nnz_P, "nnz_R": d.nnz_R,
-                "lam_hat": d.lam_hat}
+                "nnz_AP": d.nnz_AP, "lam_hat": d.lam_hat}
 
     def level_csr(self, l, which="A"):
         d = self.level(l)
@@ -255,6 +255,8 @@ class Solver:
             nr, nnz = d["rows"], d["nnz_A"]
         elif which == "P":
             nr, nnz = d["rows"], d["nnz_P"]
+        elif which == "AP":
+            nr, nnz = d["rows"], d["nnz_AP"]
         else:
             nr, nnz = self.level(l + 1)["rows"], d["nnz_R"]
         rp = np.zeros(nr + 1, dtype=np.int64)

@@ -55,3 +55,35 @@ def test_errors_without_device_work():
     assert rc == giamg.EINVAL and b"range" in lib.giamg_last_error()
     assert not h.value
     lib.giamg_free(None)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror has the C struct's size and field offsets, as gcc
+    lays out include/giamg.h."""
+    import shutil
+    import subprocess
+    from paper_2512_15121_amd import giamg
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    mirrors = {"giamg_opts": giamg._Opts, "giamg_info": giamg._Info,
+               "giamg_level_desc": giamg._LevelDesc, "giamg_server_opts": giamg._ServerOpts,
+               "giamg_server_statistics": giamg._ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "giamg.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in mirrors.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, f"{cname}.{field}"

@@ -2,8 +2,9 @@
 
 Bars (derivations in DESIGN.md, "Tolerances"):
 * integer work bit-exact: constrained mask, every level's CSR structure of
-  A, P and R, next-level element maps, aggregates;
-* assembled/Galerkin values: max |a - a_o| <= 1e-12 max |a_o| per level;
+  A, P, R and A P, next-level element maps, aggregates;
+* assembled/Galerkin values: max |a - a_o| <= 1e-12 max |a_o| per level
+  (for A P: 1e-12 max (|A| |P|), as its entries cancel);
 * lambda_max estimate: relative 1e-6;
 * one product: |y - y_o|_i <= 64 eps (|A| |x|)_i;
 * smoothing, V-cycle: ||y - y_o|| <= 1e-11 ||y_o||;
@@ -17,7 +18,7 @@ import pytest
 import scipy.sparse as sp
 
 import synth
-from oracle import hierarchy, krylov, cycle, smoothers, assembly
+from oracle import hierarchy, krylov, cycle, smoothers, assembly, galerkin
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +90,13 @@ def test_hierarchy_bitexact_structure_and_values(torch_dev, name):
                 rp, ci, val = s.level_csr(l, which)
                 assert np.array_equal(rp, M.indptr) and np.array_equal(ci, M.indices), f"{which}{l}"
                 assert np.max(np.abs(val - M.data)) <= 1e-12 * np.max(np.abs(M.data)), f"{which}{l}"
+            # A P, the left factor of the Galerkin product, kept for post-smoothing
+            AP = galerkin.values_on_pattern(galerkin.symbolic_product(lv.A, lv.P), lv.A @ lv.P)
+            rp, ci, val = s.level_csr(l, "AP")
+            assert d["nnz_AP"] == AP.nnz
+            assert np.array_equal(rp, AP.indptr) and np.array_equal(ci, AP.indices), f"AP{l}"
+            scale = (abs(lv.A) @ abs(lv.P)).max()
+            assert np.max(np.abs(val - AP.data)) <= 1e-12 * scale, f"AP{l}"
             assert abs(d["lam_hat"] - lv.lam_hat) <= 1e-6 * lv.lam_hat
             if lv.agg is not None:
                 assert np.array_equal(s.level_aggregates(l), lv.agg)
