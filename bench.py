@@ -11,7 +11,7 @@ CG from x = 0 to the tolerance); the hierarchy is built once before timing
 (its setup time, including the device Galerkin products, is reported apart).
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup,
---workload {cfg2,cfg3}, --no-cpu-baseline, --no-mixed, --no-batched,
+--workload {helmholtz16_p4,helmholtz32_p4}, --no-cpu-baseline, --no-mixed, --no-batched,
 --serving {small,full,off}.
 """
 import argparse
@@ -28,8 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     # name: (n, p, lambda or None for log-uniform draw, mesh seed, rhs seed, lambda seed)
-    "cfg2": dict(n=16, p=4, lam=10.0, mesh_seed=2, rhs_seed=12, lam_seed=None),
-    "cfg3": dict(n=32, p=4, lam=None, mesh_seed=3, rhs_seed=23, lam_seed=13),
+    "helmholtz16_p4": dict(n=16, p=4, lam=10.0, mesh_seed=2, rhs_seed=12, lam_seed=None),
+    "helmholtz32_p4": dict(n=32, p=4, lam=None, mesh_seed=3, rhs_seed=23, lam_seed=13),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cheb_step.json")
 KERNEL_SOURCES = ["paper_2512_15121_amd/csrc/kernels.hip", "paper_2512_15121_amd/csrc/kernels.h"]
@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="helmholtz16_p4", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")

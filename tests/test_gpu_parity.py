@@ -36,7 +36,7 @@ def torch_dev():
 
 CASES = {
     # name: (n, p, lam, smoother, perturb, coarse_max, bc)
-    "cfg1_4x4x4_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet"),
+    "manufactured_4cube_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet"),
     "p4_6cube_cheb_sa": (6, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet"),
     "p6_4cube_cheb": (4, 6, 0.5, "chebyshev", 0.1, 2000, "dirichlet"),
     "p5_7cube_ragged": (7, 5, 3.0, "chebyshev", 0.1, 300, "dirichlet"),
@@ -105,7 +105,7 @@ def test_hierarchy_bitexact_structure_and_values(torch_dev, name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "p3_pin_neumann", "cfg1_4x4x4_p2_jacobi"])
+@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "p3_pin_neumann", "manufactured_4cube_p2_jacobi"])
 def test_each_vcycle_step(torch_dev, name):
     torch, dev = torch_dev
     m, H = _case(name)
@@ -183,9 +183,9 @@ def test_fp64_solve_parity(torch_dev, name):
     s2.close()
 
 
-def test_cfg1_manufactured_rhs_and_load_vector(torch_dev):
+def test_manufactured_rhs_and_load_vector(torch_dev):
     torch, dev = torch_dev
-    name = "cfg1_4x4x4_p2_jacobi"
+    name = "manufactured_4cube_p2_jacobi"
     m, H = _case(name)
     s = _solver(name)
     xq = s.quadrature_points()
@@ -229,7 +229,7 @@ def test_mixed_precision_solve(torch_dev):
 def test_edge_cases(torch_dev):
     torch, dev = torch_dev
     from paper_2512_15121_amd import Solver, Options, giamg
-    name = "cfg1_4x4x4_p2_jacobi"
+    name = "manufactured_4cube_p2_jacobi"
     m, H = _case(name)
     s = _solver(name)
     n = m.n_nodes

@@ -118,7 +118,7 @@ def _struct(M):
     return sp.csr_matrix((np.ones(M.nnz), M.indices, M.indptr), shape=M.shape).toarray() > 0
 
 
-def test_hierarchy_sizes_cfg_shape():
+def test_hierarchy_sizes_p2_12cube():
     # a p = 2 problem on 12^3 elements reaches h-levels (p1 level > 2000 rows)
     m = synth.hex_mesh(12, 2, perturb=0.1, seed=2)
     H = hierarchy.build(m.coords, m.l2g, 2, 10.0,

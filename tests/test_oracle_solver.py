@@ -128,7 +128,7 @@ def test_pcg_against_dense_and_textbook():
     assert krylov.giamg_pcg(H, b, x0=x).iters == 0
 
 
-def test_cfg1_converges_order_robust():
+def test_manufactured_4cube_converges_order_robust():
     iters = []
     for p in (2, 3, 4):
         m = synth.hex_mesh(4, p)
