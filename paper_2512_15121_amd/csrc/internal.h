@@ -91,6 +91,12 @@ struct DevCSR {
     DevBuf<int64_t> rblk;   // row blocks of the streaming product kernel
     int64_t nblk = 0;
     int lanes = 64;
+    // Staged gathers: per row block, the distinct columns its nonzeros touch,
+    // as runs of consecutive columns that the product loads into LDS first.
+    DevBuf<int32_t> run_ptr;  // [nblk + 1] offsets into runs; a block with 0 runs gathers directly
+    DevBuf<int32_t> runs;     // [2 * nruns] (first column, LDS slot | length << 16)
+    DevBuf<uint16_t> slot;    // [nnz] LDS slot of each nonzero's column within its block
+    int64_t nruns = 0, nnz_staged = 0;
 };
 // Build the row blocks of d from a host copy of its row pointers.
 void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);

@@ -44,7 +44,11 @@ struct SpmvArgs {
     const int64_t* rblk = nullptr;   // row-block boundaries (nblk + 1 entries)
     int64_t nblk = 0;
     int lanes = 64;                  // lanes that reduce one row
+    const int32_t* run_ptr = nullptr;   // staged gathers (DevCSR); null: every block gathers directly
+    const int32_t* runs = nullptr;
+    const uint16_t* slot = nullptr;
     int64_t nnz = 0, ncols = 0;      // host-side byte accounting only
+    int64_t nnz_staged = 0, nruns = 0;
 };
 
 template <typename T>
@@ -52,6 +56,12 @@ void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s);
 // Greedy row blocking of a CSR operator: consecutive rows while their
 // nonzeros fit SPMV_CAP; the reduction width follows the mean row length.
 void make_row_blocks(const int64_t* rp, int64_t n, std::vector<int64_t>& blocks, int& lanes);
+// Staged-gather tables of d (run_ptr, runs, slot) from its device CSR and
+// row blocks; rp is the host copy of the row pointers.  Blocks whose columns
+// span more than STAGE_SPAN or form more than SPMV_THREADS runs, and
+// long-row blocks, keep direct gathers.
+constexpr int64_t STAGE_SPAN = 262144;
+void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
 
 // row-local kernels
 template <typename T>

@@ -152,14 +152,23 @@ __device__ __forceinline__ void block_sum2(double* red, int tid, double a, doubl
 // Streaming CSR product.  A block owns a run of at most SPMV_THREADS whole
 // rows whose nonzeros (at most SPMV_CAP = 8 per thread) are contiguous:
 //  0. thread t prefetches the row-local operands of row r0 + t;
-//  1. every thread issues its eight column/value loads at once (coalesced,
-//     non-temporal), gathers the vector and stages the products in LDS;
+//  1. every thread issues its eight value loads and eight column loads at
+//     once (coalesced, non-temporal) and forms the products in LDS.  With
+//     staged gathers the block first copies the vector entries it needs
+//     into LDS: the distinct columns of its nonzeros form runs of
+//     consecutive ids, a wave copies one run (at most 64 entries) per load,
+//     and the run table is read before the values arrive, so the copies
+//     overlap the value stream; the nonzeros then carry 16-bit LDS slots in
+//     place of column ids.  Without staging each nonzero gathers straight
+//     from memory once its column id has arrived.
 //  2. groups of L lanes sum the rows from LDS in a fixed order;
 //  3. thread t finishes row r0 + t (coalesced row-local stores).
-// A row longer than SPMV_CAP has a block of its own, summed straight from
-// memory by the whole block.
+// Both forms multiply the same operands and sum in the same order, so they
+// give bitwise identical results.  A row longer than SPMV_CAP has a block of
+// its own, summed straight from memory by the whole block.
 template <typename T, int MODE, int L>
-__global__ void __launch_bounds__(SPMV_THREADS) spmv_stream_kernel(SpmvArgs<T> a) {
+__global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+spmv_stream_kernel(SpmvArgs<T> a) {
     constexpr int PER = SPMV_CAP / SPMV_THREADS;
     __shared__ T prod[SPMV_CAP];
     __shared__ T rowsum[SPMV_THREADS];
@@ -200,25 +209,82 @@ __global__ void __launch_bounds__(SPMV_THREADS) spmv_stream_kernel(SpmvArgs<T> a
     }
     const int nrows = (int)(r1 - r0);
     const int n = (int)cnt;
+    const int nruns = a.run_ptr ? a.run_ptr[lb + 1] - a.run_ptr[lb] : 0;
     // 0. row-local operands of this thread's row
     RowIn<T> in{};
     const bool own = tid < nrows;
     if (own) epilogue_load<T, MODE>(a, r0 + tid, in);
-    // 1. stream the nonzeros: all loads first, then the gathers
-    int32_t c[PER];
-    T av[PER];
+    if (nruns > 0) {
+        // 1s. staged: run table, then values and slots, then the vector runs
+        const int lane = tid % WAVE, w = tid / WAVE;
+        constexpr int NW = SPMV_THREADS / WAVE;
+        const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + a.run_ptr[lb];
+        constexpr int SB = 8;   // runs copied per batch (loads in flight); fits 64 registers
+        // runs w, w + NW, ... of this wave; a staged block has at most
+        // STAGE_MAX_RUNS = NW * WAVE runs, so one descriptor per lane
+        const int mine = nruns > w ? (nruns - w + NW - 1) / NW : 0;
+        int2 dsc = make_int2(0, 0);
+        if (lane < mine) dsc = runs[w + NW * lane];
+        const uint16_t* __restrict__ sl = a.slot + base;
+        int c[PER];
+        T av[PER];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int idx = tid + k * SPMV_THREADS;
-        if (idx < n) {
-            c[k] = ldnt(ci + idx);
-            av[k] = ldnt(val + idx);
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + k * SPMV_THREADS;
+            if (idx < n) {
+                c[k] = (int)ldnt(sl + idx);
+                av[k] = ldnt(val + idx);
+            }
         }
-    }
+        for (int i0 = 0; i0 < mine; i0 += SB) {
+            T tmp[SB];
+            int dst[SB];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int idx = tid + k * SPMV_THREADS;
-        if (idx < n) prod[idx] = av[k] * v[c[k]];
+            for (int j = 0; j < SB; ++j) {
+                dst[j] = -1;
+                if (i0 + j < mine) {
+                    const int col = __builtin_amdgcn_readlane(dsc.x, i0 + j);
+                    const int ol = __builtin_amdgcn_readlane(dsc.y, i0 + j);
+                    if (lane < (ol >> 16)) {
+                        tmp[j] = v[col + lane];
+                        dst[j] = (ol & 0xffff) + lane;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < SB; ++j)
+                if (dst[j] >= 0) prod[dst[j]] = tmp[j];
+        }
+        __syncthreads();
+        T pr[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + k * SPMV_THREADS;
+            if (idx < n) pr[k] = av[k] * prod[c[k]];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + k * SPMV_THREADS;
+            if (idx < n) prod[idx] = pr[k];
+        }
+    } else {
+        // 1d. direct: all loads first, then the gathers
+        int32_t c[PER];
+        T av[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + k * SPMV_THREADS;
+            if (idx < n) {
+                c[k] = ldnt(ci + idx);
+                av[k] = ldnt(val + idx);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + k * SPMV_THREADS;
+            if (idx < n) prod[idx] = av[k] * v[c[k]];
+        }
     }
     __syncthreads();
     // 2. row sums, L lanes per row
@@ -240,6 +306,182 @@ __global__ void __launch_bounds__(SPMV_THREADS) spmv_stream_kernel(SpmvArgs<T> a
             if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = red[SPMV_THREADS];
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Staged-gather tables (setup).  Per row block: a bitmap of the columns its
+// nonzeros touch (64-bit words over [cmin, cmax]); a run is a maximal set of
+// consecutive set bits inside one word, so it holds at most 64 columns; the
+// LDS slot of a column is its rank among the set bits.  Pass 1 counts the
+// runs of each block, pass 2 writes the runs and the slot of every nonzero.
+// Blocks with more than STAGE_MAX_RUNS runs (scattered columns) are left to
+// direct gathers, as are blocks spanning more than STAGE_SPAN columns.
+// ---------------------------------------------------------------------------
+constexpr int STAGE_THREADS = 512;
+constexpr int STAGE_WORDS = (int)(STAGE_SPAN / 64);
+constexpr int STAGE_MAX_RUNS = SPMV_THREADS;   // one run descriptor per lane of the block
+static_assert(STAGE_MAX_RUNS == (SPMV_THREADS / WAVE) * WAVE, "descriptor lanes");
+constexpr int STAGE_WPT = STAGE_WORDS / STAGE_THREADS;
+static_assert(STAGE_WORDS % STAGE_THREADS == 0, "bitmap words per thread");
+
+// Exclusive prefix over the block of one int per thread; sum in total.
+__device__ int stage_exscan(int v, int* sc, int tid, int& total) {
+    sc[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < STAGE_THREADS; o <<= 1) {
+        const int t = tid >= o ? sc[tid - o] : 0;
+        __syncthreads();
+        sc[tid] += t;
+        __syncthreads();
+    }
+    total = sc[STAGE_THREADS - 1];
+    const int incl = sc[tid];
+    __syncthreads();
+    return incl - v;
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(STAGE_THREADS) stage_kernel(const int64_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ ci,
+                                                             const int64_t* __restrict__ rblk,
+                                                             int32_t* counts, const int32_t* run_ptr,
+                                                             int32_t* runs, uint16_t* slot) {
+    __shared__ unsigned long long bm[STAGE_WORDS];
+    __shared__ uint16_t rank_pre[STAGE_WORDS];
+    __shared__ uint16_t run_pre[STAGE_WORDS];
+    __shared__ int sc[STAGE_THREADS];
+    __shared__ int wmin[STAGE_THREADS / WAVE], wmax[STAGE_THREADS / WAVE];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t r0 = rblk[b], r1 = rblk[b + 1];
+    const int64_t base = rp[r0];
+    const int64_t cnt = rp[r1] - base;
+    if (cnt == 0 || cnt > SPMV_CAP) {
+        if (!FILL && tid == 0) counts[b] = 0;
+        return;
+    }
+    const int n = (int)cnt;
+    const int32_t* c = ci + base;
+    int mn = 0x7fffffff, mx = -1;
+    for (int i = tid; i < n; i += STAGE_THREADS) {
+        const int v = c[i];
+        mn = min(mn, v);
+        mx = max(mx, v);
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, WAVE));
+        mx = max(mx, __shfl_xor(mx, o, WAVE));
+    }
+    if (tid % WAVE == 0) {
+        wmin[tid / WAVE] = mn;
+        wmax[tid / WAVE] = mx;
+    }
+    __syncthreads();
+    mn = wmin[0];
+    mx = wmax[0];
+    for (int i = 1; i < STAGE_THREADS / WAVE; ++i) {
+        mn = min(mn, wmin[i]);
+        mx = max(mx, wmax[i]);
+    }
+    if ((int64_t)mx - mn + 1 > STAGE_SPAN) {       // same decision in every thread
+        if (!FILL && tid == 0) counts[b] = 0;
+        return;
+    }
+    const int nw = (int)(((int64_t)mx - mn + 64) >> 6);
+    for (int w = tid; w < nw; w += STAGE_THREADS) bm[w] = 0ull;
+    __syncthreads();
+    for (int i = tid; i < n; i += STAGE_THREADS) {
+        const int o = c[i] - mn;
+        atomicOr(&bm[o >> 6], 1ull << (o & 63));
+    }
+    __syncthreads();
+    const int w0 = tid * STAGE_WPT, w1 = min(nw, w0 + STAGE_WPT);
+    int pc = 0, rc = 0;
+    for (int w = w0; w < w1; ++w) {
+        const unsigned long long x = bm[w];
+        pc += __popcll(x);
+        rc += __popcll(x & ~(x << 1));
+    }
+    int tot_runs = 0, tot_cols = 0;
+    int rex = stage_exscan(rc, sc, tid, tot_runs);
+    if (!FILL) {
+        if (tid == 0) counts[b] = tot_runs <= STAGE_MAX_RUNS ? tot_runs : 0;
+        return;
+    }
+    if (tot_runs > STAGE_MAX_RUNS) return;   // scattered columns: direct gathers
+    int uex = stage_exscan(pc, sc, tid, tot_cols);
+    for (int w = w0; w < w1; ++w) {
+        const unsigned long long x = bm[w];
+        rank_pre[w] = (uint16_t)uex;
+        run_pre[w] = (uint16_t)rex;
+        uex += __popcll(x);
+        rex += __popcll(x & ~(x << 1));
+    }
+    __syncthreads();
+    int32_t* out = runs + 2 * (int64_t)run_ptr[b];
+    for (int w = w0; w < w1; ++w) {
+        const unsigned long long x = bm[w];
+        unsigned long long st = x & ~(x << 1);
+        int ri = run_pre[w];
+        while (st) {
+            const int pos = __ffsll((long long)st) - 1;
+            const unsigned long long rest = ~(x >> pos);
+            const int len = rest ? __ffsll((long long)rest) - 1 : 64 - pos;
+            const int rank = rank_pre[w] + __popcll(x & ((1ull << pos) - 1ull));
+            out[2 * ri] = mn + w * 64 + pos;
+            out[2 * ri + 1] = rank | (len << 16);
+            ++ri;
+            st &= st - 1ull;
+        }
+    }
+    for (int i = tid; i < n; i += STAGE_THREADS) {
+        const int o = c[i] - mn;
+        const int w = o >> 6, pos = o & 63;
+        slot[base + i] = (uint16_t)(rank_pre[w] + __popcll(bm[w] & ((1ull << pos) - 1ull)));
+    }
+}
+
+void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
+    d.run_ptr.release();
+    d.runs.release();
+    d.slot.release();
+    d.nruns = 0;
+    d.nnz_staged = 0;
+    if (d.nblk <= 0 || d.nnz <= 0) return;
+    GIAMG_REQUIRE(d.nblk < (int64_t(1) << 31), "too many row blocks");
+    DevBuf<int32_t> counts(d.nblk);
+    stage_kernel<false><<<(unsigned)d.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), d.rblk.get(),
+                                                                  counts.get(), nullptr, nullptr, nullptr);
+    GIAMG_HIP(hipGetLastError());
+    std::vector<int32_t> hc(d.nblk);
+    std::vector<int64_t> hb(d.nblk + 1);
+    GIAMG_HIP(hipMemcpyAsync(hc.data(), counts.get(), d.nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipMemcpyAsync(hb.data(), d.rblk.get(), (d.nblk + 1) * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> ptr(d.nblk + 1, 0);
+    int64_t total = 0, staged = 0;
+    for (int64_t b = 0; b < d.nblk; ++b) {
+        ptr[b] = (int32_t)total;
+        total += hc[b];
+        if (hc[b] > 0) staged += rp[hb[b + 1]] - rp[hb[b]];
+        if (total >= (int64_t(1) << 31)) return;   // tables too large: direct gathers throughout
+    }
+    ptr[d.nblk] = (int32_t)total;
+    if (total == 0) return;
+    d.run_ptr.alloc(d.nblk + 1);
+    d.runs.alloc(2 * total);
+    d.slot.alloc(d.nnz);
+    GIAMG_HIP(hipMemcpyAsync(d.run_ptr.get(), ptr.data(), ptr.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s));
+    stage_kernel<true><<<(unsigned)d.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), d.rblk.get(),
+                                                                 nullptr, d.run_ptr.get(), d.runs.get(),
+                                                                 d.slot.get());
+    GIAMG_HIP(hipGetLastError());
+    GIAMG_HIP(hipStreamSynchronize(s));
+    d.nruns = total;
+    d.nnz_staged = staged;
 }
 
 template <typename T, int MODE>

@@ -40,6 +40,7 @@ void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) 
     GIAMG_HIP(hipMemcpyAsync(d.rblk.get(), blocks.data(), blocks.size() * sizeof(int64_t),
                              hipMemcpyHostToDevice, s));
     GIAMG_HIP(hipStreamSynchronize(s));
+    build_staging(d, rp, s);
 }
 
 void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
@@ -74,6 +75,18 @@ void download_csr(const DevCSR& d, HostCSR& h, hipStream_t s) {
     GIAMG_HIP(hipStreamSynchronize(s));
 }
 
+// Product arguments over one CSR operator (values in the precision of T).
+template <typename T>
+SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
+    SpmvArgs<T> a;
+    a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows;
+    a.nnz = M.nnz; a.ncols = M.ncols;
+    a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
+    a.run_ptr = M.run_ptr.get(); a.runs = M.runs.get(); a.slot = M.slot.get();
+    a.nnz_staged = M.nnz_staged; a.nruns = M.nruns;
+    return a;
+}
+
 void make_fp32_values(DevCSR& d, hipStream_t s) {
     d.val32.alloc(d.nnz);
     launch_convert<double, float>(d.nnz, d.val.get(), d.val32.get(), s);
@@ -101,9 +114,7 @@ double power_estimate(Handle& H, Level& L) {
     launch_power_start(n, v.get(), H.stream);
     double lam = 0.0;
     for (int it = 0; it < H.opts.power_iters; ++it) {
-        SpmvArgs<double> a;
-        a.rp = L.A.rp.get(); a.ci = L.A.ci.get(); a.val = L.A.val.get(); a.n = n;
-        a.rblk = L.A.rblk.get(); a.nblk = L.A.nblk; a.lanes = L.A.lanes;
+        SpmvArgs<double> a = args_of<double>(L.A, L.A.val.get());
         a.v = v.get(); a.y = w.get(); a.dinv = L.dinv.get();
         launch_spmv(SPMV_DINV, a, H.stream);
         const double ww = std::sqrt(device_dot(H, n, w.get(), w.get()));
@@ -289,6 +300,15 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     const int64_t nn = std::max<int64_t>(n, 1);
     H.x.alloc(nn); H.r.alloc(nn); H.z.alloc(nn); H.p.alloc(nn); H.q.alloc(nn); H.rold.alloc(nn);
     H.tmp.alloc(nn);
+    if (o.direct_gathers) {
+        for (auto& L : H.levels)
+            for (DevCSR* M : {&L.A, &L.P, &L.R, &L.AP}) {
+                M->run_ptr.release();
+                M->runs.release();
+                M->slot.release();
+                M->nruns = M->nnz_staged = 0;
+            }
+    }
     if (!H.ev0) GIAMG_HIP(hipEventCreate(&H.ev0));
     if (!H.ev1) GIAMG_HIP(hipEventCreate(&H.ev1));
     GIAMG_HIP(hipStreamSynchronize(H.stream));
@@ -298,7 +318,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
 int64_t handle_device_bytes(const Handle& H) {
     auto csr = [](const DevCSR& m) {
         return (int64_t)(m.rp.n + m.rblk.n) * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 +
-               (int64_t)m.val32.n * 4;
+               (int64_t)m.val32.n * 4 + (int64_t)(m.run_ptr.n + m.runs.n) * 4 + (int64_t)m.slot.n * 2;
     };
     int64_t b = 0;
     for (const Level& L : H.levels) {
@@ -345,22 +365,14 @@ template <> struct LV<float> {
 };
 
 template <typename T>
-SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
-    SpmvArgs<T> a;
-    a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows;
-    a.nnz = M.nnz; a.ncols = M.ncols;
-    a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
-    return a;
-}
-
-template <typename T>
 SpmvArgs<T> args_A(const Level& L) {
     SpmvArgs<T> a = args_of<T>(L.A, LV<T>::A(L));
     a.dinv = LV<T>::dinv(L);
     return a;
 }
 
-// Algorithmic HBM bytes of one product launch: the CSR arrays, the gathered
+// Algorithmic HBM bytes of one product launch: values, column ids (16-bit
+// slots plus the run tables in staged blocks), row pointers, the gathered
 // vector once, and the row-local vectors its epilogue reads and writes.
 template <typename T>
 double spmv_bytes(int mode, const SpmvArgs<T>& a) {
@@ -376,7 +388,9 @@ double spmv_bytes(int mode, const SpmvArgs<T>& a) {
         case SPMV_DOT: rows = 1; break;               // y
         case SPMV_DINV: rows = 2; break;              // dinv, y
     }
-    return (vb + 4.0) * a.nnz + 8.0 * (a.n + 1) + vb * a.ncols + rows * vb * a.n;
+    const double staged = a.run_ptr ? 2.0 * a.nnz_staged + 8.0 * a.nruns + 4.0 * (a.nblk + 1) : 0.0;
+    return vb * a.nnz + 4.0 * (a.nnz - a.nnz_staged) + staged + 8.0 * (a.n + 1) + vb * a.ncols +
+           rows * vb * a.n;
 }
 
 template <typename T>
@@ -557,18 +571,13 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     hipStream_t s = H.stream;
     const int64_t gs = L0.A.nblk, gv = vec_blocks(n);
     auto rinit = [&](double* out) {
-        SpmvArgs<double> a;
-        a.rp = L0.A.rp.get(); a.ci = L0.A.ci.get(); a.val = L0.A.val.get(); a.n = n;
-        a.rblk = L0.A.rblk.get(); a.nblk = L0.A.nblk; a.lanes = L0.A.lanes;
+        SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
         a.v = x; a.f = b; a.y = out; a.partial = H.partial.get();
-        launch_spmv(SPMV_RINIT, a, s);
+        run_spmv(H, SPMV_RINIT, a);
     };
-    const double nnz0 = (double)L0.A.nnz;
-    const double spmv0 = 12.0 * nnz0 + 8.0 * (n + 1) + 8.0 * n;   // CSR + gathered vector
     H.bytes = 0.0;
     GIAMG_HIP(hipEventRecord(H.ev0, s));
     GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), s));
-    H.bytes += spmv0 + 16.0 * n;
     rinit(H.r.get());
     launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
     fetch_scalars(H);
@@ -590,12 +599,10 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             launch_copy<double>(n, H.z.get(), H.p.get(), s);
             status = GIAMG_ENOTCONV;
             for (int k = 1; k <= H.opts.maxit; ++k) {
-                SpmvArgs<double> a;
-                a.rp = L0.A.rp.get(); a.ci = L0.A.ci.get(); a.val = L0.A.val.get(); a.n = n;
-                a.rblk = L0.A.rblk.get(); a.nblk = L0.A.nblk; a.lanes = L0.A.lanes;
+                SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
                 a.v = H.p.get(); a.y = H.q.get(); a.partial = H.partial.get();
-                H.bytes += spmv0 + 8.0 * n + (flexible ? 56.0 : 48.0) * n;
-                launch_spmv(SPMV_DOT, a, s);
+                H.bytes += (flexible ? 56.0 : 48.0) * n;
+                run_spmv(H, SPMV_DOT, a);
                 launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, s, FIN_ALPHA, H.scal.get());
                 launch_pcg_update(n, x, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
                                   H.q.get(), H.scal.get(), H.partial.get(), s);
@@ -675,16 +682,12 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
         }
     } else if (kernel == GIAMG_KERNEL_RESTRICT) {
         Level& C = H.levels[l + 1];
-        a.rp = L.R.rp.get(); a.ci = L.R.ci.get(); a.val = LV<T>::R(L); a.n = L.R.nrows;
-        a.nnz = L.R.nnz; a.ncols = L.R.ncols;
-        a.rblk = L.R.rblk.get(); a.nblk = L.R.nblk; a.lanes = L.R.lanes;
+        a = args_of<T>(L.R, LV<T>::R(L));
         a.v = LV<T>::t(L); a.y = LV<T>::f(C);
     } else if (kernel == GIAMG_KERNEL_PROLONG) {
         Level& C = H.levels[l + 1];
         mode = SPMV_ADD;
-        a.rp = L.P.rp.get(); a.ci = L.P.ci.get(); a.val = LV<T>::P(L); a.n = L.P.nrows;
-        a.nnz = L.P.nnz; a.ncols = L.P.ncols;
-        a.rblk = L.P.rblk.get(); a.nblk = L.P.nblk; a.lanes = L.P.lanes;
+        a = args_of<T>(L.P, LV<T>::P(L));
         a.v = LV<T>::x(C); a.y = LV<T>::t(L);
     } else {
         throw Error(GIAMG_EINVAL, "unknown kernel");

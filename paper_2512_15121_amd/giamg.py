@@ -38,7 +38,8 @@ class _Opts(ctypes.Structure):
                 ("pin_node", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("agg_seed", ctypes.c_uint64),
                 ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
-                ("cheb_hi", ctypes.c_double)]
+                ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -65,7 +66,8 @@ class _LevelDesc(ctypes.Structure):
                 ("coarsest", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("nnz_A", ctypes.c_int64),
                 ("nnz_P", ctypes.c_int64), ("nnz_R", ctypes.c_int64),
-                ("lam_hat", ctypes.c_double), ("nnz_AP", ctypes.c_int64)]
+                ("lam_hat", ctypes.c_double), ("nnz_AP", ctypes.c_int64),
+                ("staged_nnz_A", ctypes.c_int64), ("runs_A", ctypes.c_int64)]
 
 
 @dataclass
@@ -83,9 +85,11 @@ class Options:
     power_iters: int = 20
     cheb_lo: float = 0.1
     cheb_hi: float = 1.1
+    direct_gathers: bool = False
 
     def _c(self) -> _Opts:
         d = asdict(self)
+        d["direct_gathers"] = int(d["direct_gathers"])
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]
@@ -247,7 +251,8 @@ class Solver:
         _check(self.lib.giamg_level_describe(self._h, l, ctypes.byref(d)))
         return {"kind": LEVEL_KIND[d.kind], "order": d.order, "coarsest": bool(d.coarsest),
                 "rows": d.rows, "nnz_A": d.nnz_A, "nnz_P": d.nnz_P, "nnz_R": d.nnz_R,
-                "nnz_AP": d.nnz_AP, "lam_hat": d.lam_hat}
+                "nnz_AP": d.nnz_AP, "lam_hat": d.lam_hat, "staged_nnz_A": d.staged_nnz_A,
+                "runs_A": d.runs_A}
 
     def level_csr(self, l, which="A"):
         d = self.level(l)

@@ -105,6 +105,63 @@ def test_hierarchy_bitexact_structure_and_values(torch_dev, name):
     s.close()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_staged_gathers_bitwise_equal_direct(torch_dev, name):
+    """Products with each row block's columns staged in LDS multiply the same
+    operands and sum in the same order as direct gathers: every operator
+    product, the V-cycle and the whole solve agree bit for bit."""
+    torch, dev = torch_dev
+    s1 = _solver(name)
+    s2 = _solver(name, direct_gathers=True)
+    d0 = s1.level(0)
+    assert d0["staged_nnz_A"] > 0.9 * d0["nnz_A"] and d0["runs_A"] > 0
+    assert s2.level(0)["staged_nnz_A"] == 0 and s2.level(0)["runs_A"] == 0
+    rng = np.random.default_rng(7)
+    nl = s1.num_levels()
+    for l in range(nl):
+        n = s1.level(l)["rows"]
+        x = _to(torch, dev, rng.standard_normal(n))
+        o1 = torch.zeros(n, dtype=torch.float64, device=dev)
+        o2 = torch.zeros_like(o1)
+        s1.apply("spmv", l, x, out=o1)
+        s2.apply("spmv", l, x, out=o2)
+        assert torch.equal(o1, o2), f"spmv {l}"
+        if l + 1 == nl:
+            continue
+        nc = s1.level(l + 1)["rows"]
+        c1 = torch.zeros(nc, dtype=torch.float64, device=dev)
+        c2 = torch.zeros_like(c1)
+        s1.apply("restrict", l, x, out=c1)
+        s2.apply("restrict", l, x, out=c2)
+        assert torch.equal(c1, c2), f"restrict {l}"
+        y1, y2 = x.clone(), x.clone()
+        s1.apply("prolong_add", l, c1, out=y1)
+        s2.apply("prolong_add", l, c1, out=y2)
+        assert torch.equal(y1, y2), f"prolong {l}"
+        s1.apply("vcycle", l, x, out=o1)
+        s2.apply("vcycle", l, x, out=o2)
+        assert torch.equal(o1, o2), f"vcycle {l}"
+    b = _to(torch, dev, rng.standard_normal(d0["rows"]))
+    x1, i1 = s1.solve(b, tol=1e-10)
+    x2, i2 = s2.solve(b, tol=1e-10)
+    assert i1.iters == i2.iters and i1.relres == i2.relres and torch.equal(x1, x2)
+    s1.close()
+    s2.close()
+
+
+def test_staged_gathers_mixed_bitwise_equal_direct(torch_dev):
+    torch, dev = torch_dev
+    name = "p4_6cube_cheb_sa"
+    s1 = _solver(name, precision="mixed")
+    s2 = _solver(name, precision="mixed", direct_gathers=True)
+    b = _to(torch, dev, np.random.default_rng(8).standard_normal(s1.level(0)["rows"]))
+    x1, i1 = s1.solve(b, tol=1e-10)
+    x2, i2 = s2.solve(b, tol=1e-10)
+    assert i1.status == 0 and i1.iters == i2.iters and torch.equal(x1, x2)
+    s1.close()
+    s2.close()
+
+
 @pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "p3_pin_neumann", "manufactured_4cube_p2_jacobi"])
 def test_each_vcycle_step(torch_dev, name):
     torch, dev = torch_dev
