@@ -90,7 +90,7 @@ struct DevCSR {
     DevBuf<float> val32;
     DevBuf<int64_t> rblk;   // row blocks of the streaming product kernel
     int64_t nblk = 0;
-    int lanes = 64;
+    int lanes = 16;
     // Staged gathers: per row block, the distinct columns its nonzeros touch,
     // as runs of consecutive columns that the product loads into LDS first.
     DevBuf<int32_t> run_ptr;  // [nblk + 1] offsets into runs; a block with 0 runs gathers directly

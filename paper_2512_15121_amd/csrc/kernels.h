@@ -43,7 +43,7 @@ struct SpmvArgs {
     int flags = 0;
     const int64_t* rblk = nullptr;   // row-block boundaries (nblk + 1 entries)
     int64_t nblk = 0;
-    int lanes = 64;                  // lanes that reduce one row
+    int lanes = 16;                  // lanes that reduce one row (16, 4 or 1)
     const int32_t* run_ptr = nullptr;   // staged gathers (DevCSR); null: every block gathers directly
     const int32_t* runs = nullptr;
     const uint16_t* slot = nullptr;

@@ -149,6 +149,105 @@ __device__ __forceinline__ void block_sum2(double* red, int tid, double a, doubl
     }
 }
 
+// Forms of step 1 of the streaming product (below).  Loads that depend on
+// earlier loads are unconditional, from clamped (always valid) indices, and
+// only their stores are guarded: guards there split the code into blocks
+// that the compiler separates with waits for every load in flight.
+
+// Staged: run table first, then values and slots, then the vector runs
+// (copied into prod), then the products (into prod).  nruns > 0.
+template <typename T>
+__device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int64_t lb, int64_t base, int n,
+                                               int nruns, T* prod) {
+    constexpr int PER = SPMV_CAP / SPMV_THREADS;
+    constexpr int NW = SPMV_THREADS / WAVE;
+    constexpr int SB = 8;   // runs copied per batch (loads in flight); fits 64 registers
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const T* __restrict__ v = a.v;
+    const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + a.run_ptr[lb];
+    // runs w, w + NW, ... of this wave; a staged block has at most
+    // STAGE_MAX_RUNS = NW * WAVE runs, so one descriptor per lane
+    const int mine = nruns > w ? (nruns - w + NW - 1) / NW : 0;
+    const int2 dsc = runs[min(w + NW * lane, nruns - 1)];
+    const uint16_t* __restrict__ sl = a.slot + base;
+    const T* __restrict__ val = a.val + base;
+    int c[PER];
+    T av[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        // Guarded (lanes past the block's nonzeros issue nothing): measured
+        // faster here than clamped loads, and these guards add no waits
+        // between the loads.  Unsigned offsets keep scalar-base addressing.
+        const unsigned idx = (unsigned)(tid + k * SPMV_THREADS);
+        if (idx < (unsigned)n) {
+            c[k] = (int)ldnt(sl + idx);
+            av[k] = ldnt(val + idx);
+        } else {
+            c[k] = 0;
+            av[k] = T(0);
+        }
+    }
+    // One batch copies SB runs: SB loads in flight, then the LDS stores.
+    // The first batch is straight-line code that runs even in a wave
+    // without runs (its loads then repeat a valid run and store nothing):
+    // its loads issue while the value stream is in flight, and no loop head
+    // makes the compiler wait for that stream first.
+    auto stage_batch = [&](int i0) {
+        T tmp[SB];
+        int dst[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+            const int i = max(0, min(i0 + j, mine - 1));
+            const T* __restrict__ vr = v + __builtin_amdgcn_readlane(dsc.x, i);   // run start
+            const int ol = __builtin_amdgcn_readlane(dsc.y, i);
+            const int len = ol >> 16;
+            tmp[j] = vr[min((unsigned)lane, (unsigned)(len - 1))];
+            dst[j] = (i0 + j < mine && lane < len) ? (ol & 0xffff) + lane : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+            if (dst[j] >= 0) prod[dst[j]] = tmp[j];
+    };
+    stage_batch(0);
+    for (int i0 = SB; i0 < mine; i0 += SB) stage_batch(i0);
+    __syncthreads();
+    T pr[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) pr[k] = av[k] * prod[c[k]];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = tid + k * SPMV_THREADS;
+        if (idx < n) prod[idx] = pr[k];
+    }
+}
+
+// Direct: column ids and values first, then the gathers.  n > 0.
+template <typename T>
+__device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t base, int n, T* prod) {
+    constexpr int PER = SPMV_CAP / SPMV_THREADS;
+    const int tid = threadIdx.x;
+    const int32_t* __restrict__ ci = a.ci + base;
+    const T* __restrict__ val = a.val + base;
+    const T* __restrict__ v = a.v;
+    int32_t c[PER];
+    T av[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const unsigned idx = min((unsigned)(tid + k * SPMV_THREADS), (unsigned)(n - 1));
+        c[k] = ldnt(ci + idx);
+        av[k] = ldnt(val + idx);
+    }
+    T xv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) xv[k] = v[c[k]];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = tid + k * SPMV_THREADS;
+        if (idx < n) prod[idx] = av[k] * xv[k];
+    }
+}
+
 // Streaming CSR product.  A block owns a run of at most SPMV_THREADS whole
 // rows whose nonzeros (at most SPMV_CAP = 8 per thread) are contiguous:
 //  0. thread t prefetches the row-local operands of row r0 + t;
@@ -164,12 +263,15 @@ __device__ __forceinline__ void block_sum2(double* red, int tid, double a, doubl
 //  2. groups of L lanes sum the rows from LDS in a fixed order;
 //  3. thread t finishes row r0 + t (coalesced row-local stores).
 // Both forms multiply the same operands and sum in the same order, so they
-// give bitwise identical results.  A row longer than SPMV_CAP has a block of
-// its own, summed straight from memory by the whole block.
-template <typename T, int MODE, int L>
+// give bitwise identical results.  STAGE picks the form at compile time:
+// 0 direct everywhere; 1 staged in every block with nonzeros; 2 per block
+// (the run count decides).  Forms 0 and 1 keep the other form's code out of
+// the kernel, so nothing ahead of the value stream waits on loads.  A row
+// longer than SPMV_CAP (forms 0 and 2 only) has a block of its own, summed
+// straight from memory by the whole block.
+template <typename T, int MODE, int L, int STAGE>
 __global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
 spmv_stream_kernel(SpmvArgs<T> a) {
-    constexpr int PER = SPMV_CAP / SPMV_THREADS;
     __shared__ T prod[SPMV_CAP];
     __shared__ T rowsum[SPMV_THREADS];
     double* red = reinterpret_cast<double*>(prod);   // reused once products are consumed
@@ -178,113 +280,55 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     const int64_t r0 = a.rblk[lb], r1 = a.rblk[lb + 1];
     const int64_t base = a.rp[r0];
     const int64_t cnt = a.rp[r1] - base;
-    const int32_t* __restrict__ ci = a.ci + base;
-    const T* __restrict__ val = a.val + base;
-    const T* __restrict__ v = a.v;
     double dot = 0.0, dot2 = 0.0;
-    if (cnt > SPMV_CAP) {
-        // one long row: block-wide strided sum, fixed-order tree
-        RowIn<T> in{};
-        if (tid == 0) epilogue_load<T, MODE>(a, r0, in);
-        T acc0 = 0, acc1 = 0;
-        int64_t i = tid;
-        for (; i + SPMV_THREADS < cnt; i += 2 * SPMV_THREADS) {
-            const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + SPMV_THREADS);
-            const T a0 = ldnt(val + i), a1 = ldnt(val + i + SPMV_THREADS);
-            acc0 += a0 * v[c0];
-            acc1 += a1 * v[c1];
-        }
-        if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
-        block_sum2(red, tid, (double)(acc0 + acc1), 0.0);
-        const T y = (T)red[0];
-        __syncthreads();
-        if (tid == 0) {
-            epilogue_store<T, MODE>(a, r0, y, in, dot, dot2);
-            if constexpr (has_partials<MODE>()) {
-                a.partial[lb] = dot;
-                if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
+    if constexpr (STAGE != 1) {
+        if (cnt > SPMV_CAP) {
+            // one long row: block-wide strided sum, fixed-order tree
+            const int32_t* __restrict__ ci = a.ci + base;
+            const T* __restrict__ val = a.val + base;
+            const T* __restrict__ v = a.v;
+            RowIn<T> in{};
+            if (tid == 0) epilogue_load<T, MODE>(a, r0, in);
+            T acc0 = 0, acc1 = 0;
+            int64_t i = tid;
+            for (; i + SPMV_THREADS < cnt; i += 2 * SPMV_THREADS) {
+                const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + SPMV_THREADS);
+                const T a0 = ldnt(val + i), a1 = ldnt(val + i + SPMV_THREADS);
+                acc0 += a0 * v[c0];
+                acc1 += a1 * v[c1];
             }
+            if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
+            block_sum2(red, tid, (double)(acc0 + acc1), 0.0);
+            const T y = (T)red[0];
+            __syncthreads();
+            if (tid == 0) {
+                epilogue_store<T, MODE>(a, r0, y, in, dot, dot2);
+                if constexpr (has_partials<MODE>()) {
+                    a.partial[lb] = dot;
+                    if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
+                }
+            }
+            return;
         }
-        return;
     }
     const int nrows = (int)(r1 - r0);
     const int n = (int)cnt;
-    const int nruns = a.run_ptr ? a.run_ptr[lb + 1] - a.run_ptr[lb] : 0;
     // 0. row-local operands of this thread's row
     RowIn<T> in{};
     const bool own = tid < nrows;
-    if (own) epilogue_load<T, MODE>(a, r0 + tid, in);
-    if (nruns > 0) {
-        // 1s. staged: run table, then values and slots, then the vector runs
-        const int lane = tid % WAVE, w = tid / WAVE;
-        constexpr int NW = SPMV_THREADS / WAVE;
-        const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + a.run_ptr[lb];
-        constexpr int SB = 8;   // runs copied per batch (loads in flight); fits 64 registers
-        // runs w, w + NW, ... of this wave; a staged block has at most
-        // STAGE_MAX_RUNS = NW * WAVE runs, so one descriptor per lane
-        const int mine = nruns > w ? (nruns - w + NW - 1) / NW : 0;
-        int2 dsc = make_int2(0, 0);
-        if (lane < mine) dsc = runs[w + NW * lane];
-        const uint16_t* __restrict__ sl = a.slot + base;
-        int c[PER];
-        T av[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int idx = tid + k * SPMV_THREADS;
-            if (idx < n) {
-                c[k] = (int)ldnt(sl + idx);
-                av[k] = ldnt(val + idx);
-            }
-        }
-        for (int i0 = 0; i0 < mine; i0 += SB) {
-            T tmp[SB];
-            int dst[SB];
-#pragma unroll
-            for (int j = 0; j < SB; ++j) {
-                dst[j] = -1;
-                if (i0 + j < mine) {
-                    const int col = __builtin_amdgcn_readlane(dsc.x, i0 + j);
-                    const int ol = __builtin_amdgcn_readlane(dsc.y, i0 + j);
-                    if (lane < (ol >> 16)) {
-                        tmp[j] = v[col + lane];
-                        dst[j] = (ol & 0xffff) + lane;
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < SB; ++j)
-                if (dst[j] >= 0) prod[dst[j]] = tmp[j];
-        }
-        __syncthreads();
-        T pr[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int idx = tid + k * SPMV_THREADS;
-            if (idx < n) pr[k] = av[k] * prod[c[k]];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int idx = tid + k * SPMV_THREADS;
-            if (idx < n) prod[idx] = pr[k];
-        }
+    epilogue_load<T, MODE>(a, r0 + min(tid, nrows - 1), in);
+    // 1. products into LDS
+    if constexpr (STAGE == 0) {
+        if (n > 0) direct_products<T>(a, base, n, prod);
+    } else if constexpr (STAGE == 1) {
+        const int nruns = a.run_ptr[lb + 1] - a.run_ptr[lb];   // 0 only for blocks of empty rows
+        if (nruns > 0) stage_products<T>(a, lb, base, n, nruns, prod);
     } else {
-        // 1d. direct: all loads first, then the gathers
-        int32_t c[PER];
-        T av[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int idx = tid + k * SPMV_THREADS;
-            if (idx < n) {
-                c[k] = ldnt(ci + idx);
-                av[k] = ldnt(val + idx);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int idx = tid + k * SPMV_THREADS;
-            if (idx < n) prod[idx] = av[k] * v[c[k]];
-        }
+        const int nruns = a.run_ptr[lb + 1] - a.run_ptr[lb];
+        if (nruns > 0)
+            stage_products<T>(a, lb, base, n, nruns, prod);
+        else if (n > 0)
+            direct_products<T>(a, base, n, prod);
     }
     __syncthreads();
     // 2. row sums, L lanes per row
@@ -484,16 +528,25 @@ void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
     d.nnz_staged = staged;
 }
 
-template <typename T, int MODE>
-void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
+template <typename T, int MODE, int STAGE>
+void launch_spmv_form(const SpmvArgs<T>& a, hipStream_t s) {
     const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
     switch (a.lanes) {
-        case 64: spmv_stream_kernel<T, MODE, 64><<<grid, block, 0, s>>>(a); break;
-        case 16: spmv_stream_kernel<T, MODE, 16><<<grid, block, 0, s>>>(a); break;
-        case 4: spmv_stream_kernel<T, MODE, 4><<<grid, block, 0, s>>>(a); break;
-        case 1: spmv_stream_kernel<T, MODE, 1><<<grid, block, 0, s>>>(a); break;
+        case 16: spmv_stream_kernel<T, MODE, 16, STAGE><<<grid, block, 0, s>>>(a); break;
+        case 4: spmv_stream_kernel<T, MODE, 4, STAGE><<<grid, block, 0, s>>>(a); break;
+        case 1: spmv_stream_kernel<T, MODE, 1, STAGE><<<grid, block, 0, s>>>(a); break;
         default: throw Error(GIAMG_EINVAL, "unsupported reduction width");
     }
+}
+
+template <typename T, int MODE>
+void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
+    if (a.run_ptr == nullptr)
+        launch_spmv_form<T, MODE, 0>(a, s);
+    else if (a.nnz_staged == a.nnz)
+        launch_spmv_form<T, MODE, 1>(a, s);
+    else
+        launch_spmv_form<T, MODE, 2>(a, s);
 }
 
 template <typename T>
