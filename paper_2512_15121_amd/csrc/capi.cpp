@@ -82,7 +82,7 @@ void giamg_default_opts(giamg_opts* o) {
     o->cheb_lo = 0.1;
     o->cheb_hi = 1.1;
     o->direct_gathers = 0;
-    o->reserved = 0;
+    o->graph_launch = 0;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -113,6 +113,7 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
         GIAMG_REQUIRE(o.power_iters >= 1, "power_iters must be >= 1");
         GIAMG_REQUIRE(o.cheb_lo > 0.0 && o.cheb_hi > o.cheb_lo, "need 0 < cheb_lo < cheb_hi");
         GIAMG_REQUIRE(o.direct_gathers == 0 || o.direct_gathers == 1, "direct_gathers must be 0 or 1");
+        GIAMG_REQUIRE(o.graph_launch == 0 || o.graph_launch == 1, "graph_launch must be 0 or 1");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         for (int64_t i = 0; i < n_elem * nl; ++i)
             GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");

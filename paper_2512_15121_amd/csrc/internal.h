@@ -143,6 +143,16 @@ struct Handle {
     DevBuf<double> partial;           // block partial sums
     DevBuf<double> scal;              // device scalars, see Scalars in solve.hip
     double* host_scal = nullptr;      // pinned host mirror
+    DevBuf<int> ctl;                  // CG control block (stop flag, iterations, cap)
+    int* host_ctl = nullptr;          // pinned host mirror
+    int last_iters = 0;               // iterations of the previous solve (chunk size hint)
+    // one CG iteration captured as a graph (on gstream, iterate in x), made
+    // at the first solve; part1/part2: algorithmic bytes of its two halves
+    hipStream_t gstream = nullptr;
+    hipGraph_t it_graph = nullptr;
+    hipGraphExec_t it_exec = nullptr;
+    double it_part1 = 0.0, it_part2 = 0.0;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t partial_cap = 0;
     // batched state
     std::unique_ptr<BatchState, BatchDeleter> batch;

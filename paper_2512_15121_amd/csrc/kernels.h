@@ -44,6 +44,7 @@ struct SpmvArgs {
     const int64_t* rblk = nullptr;   // row-block boundaries (nblk + 1 entries)
     int64_t nblk = 0;
     int lanes = 16;                  // lanes that reduce one row (16, 4 or 1)
+    const int* stop = nullptr;       // device stop flag (null: the thread's StopScope flag)
     const int32_t* run_ptr = nullptr;   // staged gathers (DevCSR); null: every block gathers directly
     const int32_t* runs = nullptr;
     const uint16_t* slot = nullptr;
@@ -85,15 +86,31 @@ void launch_dot_partial(int64_t n, const double* a, const double* b, double* par
 void launch_dot2_partial(int64_t n, const double* a, const double* b, const double* c,
                          double* partial, hipStream_t s);  // a.b and c.b
 // CG scalar finalisations applied after a reduction (see ScalarSlot)
-enum FinishKind : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA_FIRST = 2, FIN_BETA = 3, FIN_BETA_FLEX = 4 };
+enum FinishKind : int {
+    FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA_FIRST = 2, FIN_BETA = 3, FIN_BETA_FLEX = 4, FIN_CONV = 5
+};
 void launch_reduce(int64_t m, const double* partial, int64_t stride, int ncomp, double* out,
-                   hipStream_t s, int fin = 0, double* scal = nullptr);
+                   hipStream_t s, int fin = 0, double* scal = nullptr, int* ctl = nullptr);
 
 // PCG / FCG vector kernels
 // device scalar slots; (S_BB, S_RR) and (S_RZNEW, S_ZROLD) are written as pairs
 enum ScalarSlot : int {
     S_BB = 0, S_RR = 1, S_RZ = 2, S_PQ = 3, S_ALPHA = 4, S_BETA = 5, S_RZNEW = 6, S_ZROLD = 7,
-    S_FLAG = 8, S_TMP = 9, S_COUNT = 16
+    S_FLAG = 8, S_TMP = 9, S_TOL = 10, S_COUNT = 16
+};
+// CG control block (device ints): stop flag, iterations done, iteration cap
+enum CtlSlot : int { C_STOP = 0, C_ITERS = 1, C_MAXIT = 2, C_COUNT = 4 };
+
+// While a StopScope is open, every kernel this thread launches through the
+// wrappers of this header returns at once once *flag is nonzero.
+class StopScope {
+public:
+    explicit StopScope(const int* flag);
+    ~StopScope();
+    StopScope(const StopScope&) = delete;
+    StopScope& operator=(const StopScope&) = delete;
+private:
+    const int* prev_;
 };
 void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const double* p,
                        const double* q, const double* scal, double* partial, hipStream_t s);

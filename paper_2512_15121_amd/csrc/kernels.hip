@@ -26,6 +26,17 @@ constexpr int64_t VEC_MAX_BLOCKS = 2048;
 constexpr int RED_THREADS = 1024;
 constexpr int64_t SPMV_MAX_ROWS = SPMV_THREADS;   // rows per block
 
+// Device stop flag handed to every kernel launched by this thread while a
+// StopScope is open (null otherwise): a kernel whose flag reads nonzero
+// returns at once, so iterations queued past convergence cost one dispatch
+// per kernel and change nothing.
+thread_local const int* g_stop = nullptr;
+
+StopScope::StopScope(const int* flag) : prev_(g_stop) { g_stop = flag; }
+StopScope::~StopScope() { g_stop = prev_; }
+
+__device__ __forceinline__ bool stopped(const int* stop) { return stop != nullptr && *stop != 0; }
+
 // Hardware dispatches block b to XCD (b mod 8).  Logical block ids are
 // reassigned so that each XCD receives one contiguous range.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
@@ -272,6 +283,7 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 template <typename T, int MODE, int L, int STAGE>
 __global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
 spmv_stream_kernel(SpmvArgs<T> a) {
+    if (stopped(a.stop)) return;
     __shared__ T prod[SPMV_CAP];
     __shared__ T rowsum[SPMV_THREADS];
     double* red = reinterpret_cast<double*>(prod);   // reused once products are consumed
@@ -550,7 +562,9 @@ void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s) {
+void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
+    SpmvArgs<T> a = args;
+    if (a.stop == nullptr) a.stop = g_stop;
     if (a.n <= 0 || a.nblk <= 0) return;
     if (a.rblk == nullptr) throw Error(GIAMG_EINVAL, "operator without row blocks");
     switch (mode) {
@@ -581,7 +595,8 @@ static inline unsigned vgrid(int64_t n) {
 template <typename T>
 __global__ void cheb_init0_kernel(int64_t n, const T* __restrict__ f, const T* __restrict__ dinv,
                                   T* __restrict__ r, T* __restrict__ d, T* __restrict__ x,
-                                  T inv_theta, int write_x) {
+                                  T inv_theta, int write_x, const int* stop) {
+    if (stopped(stop)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const T res = dinv[i] * f[i];
@@ -595,7 +610,7 @@ template <typename T>
 void launch_cheb_init0(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, T inv_theta,
                        bool write_x, hipStream_t s) {
     if (n <= 0) return;
-    cheb_init0_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, f, dinv, r, d, x, inv_theta, write_x);
+    cheb_init0_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, f, dinv, r, d, x, inv_theta, write_x, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 template void launch_cheb_init0<double>(int64_t, const double*, const double*, double*, double*,
@@ -605,7 +620,8 @@ template void launch_cheb_init0<float>(int64_t, const float*, const float*, floa
 
 template <typename T>
 __global__ void jacobi0_kernel(int64_t n, const T* __restrict__ f, const T* __restrict__ dinv,
-                               T* __restrict__ x, T omega) {
+                               T* __restrict__ x, T omega, const int* stop) {
+    if (stopped(stop)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         x[i] = omega * dinv[i] * f[i];
@@ -613,7 +629,7 @@ __global__ void jacobi0_kernel(int64_t n, const T* __restrict__ f, const T* __re
 template <typename T>
 void launch_jacobi0(int64_t n, const T* f, const T* dinv, T* x, T omega, hipStream_t s) {
     if (n <= 0) return;
-    jacobi0_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, f, dinv, x, omega);
+    jacobi0_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, f, dinv, x, omega, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 template void launch_jacobi0<double>(int64_t, const double*, const double*, double*, double,
@@ -621,7 +637,8 @@ template void launch_jacobi0<double>(int64_t, const double*, const double*, doub
 template void launch_jacobi0<float>(int64_t, const float*, const float*, float*, float, hipStream_t);
 
 template <typename T>
-__global__ void copy_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ b) {
+__global__ void copy_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ b, const int* stop) {
+    if (stopped(stop)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         b[i] = a[i];
@@ -629,14 +646,15 @@ __global__ void copy_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ 
 template <typename T>
 void launch_copy(int64_t n, const T* a, T* b, hipStream_t s) {
     if (n <= 0) return;
-    copy_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, a, b);
+    copy_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, a, b, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 template void launch_copy<double>(int64_t, const double*, double*, hipStream_t);
 template void launch_copy<float>(int64_t, const float*, float*, hipStream_t);
 
 template <typename T>
-__global__ void add_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ b) {
+__global__ void add_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ b, const int* stop) {
+    if (stopped(stop)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         b[i] += a[i];
@@ -644,14 +662,16 @@ __global__ void add_kernel(int64_t n, const T* __restrict__ a, T* __restrict__ b
 template <typename T>
 void launch_add(int64_t n, const T* a, T* b, hipStream_t s) {
     if (n <= 0) return;
-    add_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, a, b);
+    add_kernel<T><<<vgrid(n), VEC_THREADS, 0, s>>>(n, a, b, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 template void launch_add<double>(int64_t, const double*, double*, hipStream_t);
 template void launch_add<float>(int64_t, const float*, float*, hipStream_t);
 
 template <typename Tin, typename Tout>
-__global__ void convert_kernel(int64_t n, const Tin* __restrict__ a, Tout* __restrict__ b) {
+__global__ void convert_kernel(int64_t n, const Tin* __restrict__ a, Tout* __restrict__ b,
+                               const int* stop) {
+    if (stopped(stop)) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         b[i] = (Tout)a[i];
@@ -659,7 +679,7 @@ __global__ void convert_kernel(int64_t n, const Tin* __restrict__ a, Tout* __res
 template <typename Tin, typename Tout>
 void launch_convert(int64_t n, const Tin* a, Tout* b, hipStream_t s) {
     if (n <= 0) return;
-    convert_kernel<Tin, Tout><<<vgrid(n), VEC_THREADS, 0, s>>>(n, a, b);
+    convert_kernel<Tin, Tout><<<vgrid(n), VEC_THREADS, 0, s>>>(n, a, b, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 template void launch_convert<double, float>(int64_t, const double*, float*, hipStream_t);
@@ -691,7 +711,9 @@ void launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s
 // per row, FP64 accumulation whatever the vector type.
 template <typename T>
 __global__ void __launch_bounds__(256) coarse_kernel(int64_t n, const double* __restrict__ inv,
-                                                     const T* __restrict__ f, T* __restrict__ x) {
+                                                     const T* __restrict__ f, T* __restrict__ x,
+                                                     const int* stop) {
+    if (stopped(stop)) return;
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t row = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (row >= n) return;
@@ -704,7 +726,7 @@ __global__ void __launch_bounds__(256) coarse_kernel(int64_t n, const double* __
 template <typename T>
 void launch_coarse_apply(int64_t n, const double* inv, const T* f, T* x, hipStream_t s) {
     if (n <= 0) return;
-    coarse_kernel<T><<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, inv, f, x);
+    coarse_kernel<T><<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, inv, f, x, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 template void launch_coarse_apply<double>(int64_t, const double*, const double*, double*,
@@ -735,7 +757,9 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __global__ void __launch_bounds__(VEC_THREADS) dot_partial_kernel(int64_t n, const double* __restrict__ a,
                                                                   const double* __restrict__ b,
-                                                                  double* __restrict__ partial) {
+                                                                  double* __restrict__ partial,
+                                                                  const int* stop) {
+    if (stopped(stop)) return;
     __shared__ double sh[VEC_THREADS];
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n;
@@ -746,14 +770,16 @@ __global__ void __launch_bounds__(VEC_THREADS) dot_partial_kernel(int64_t n, con
 }
 void launch_dot_partial(int64_t n, const double* a, const double* b, double* partial,
                         hipStream_t s) {
-    dot_partial_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, partial);
+    dot_partial_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, partial, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 
 __global__ void __launch_bounds__(VEC_THREADS) dot2_partial_kernel(int64_t n, const double* __restrict__ a,
                                                                    const double* __restrict__ b,
                                                                    const double* __restrict__ c,
-                                                                   double* __restrict__ partial) {
+                                                                   double* __restrict__ partial,
+                                                                   const int* stop) {
+    if (stopped(stop)) return;
     __shared__ double sh[VEC_THREADS];
     double s0 = 0.0, s1 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n;
@@ -770,13 +796,34 @@ __global__ void __launch_bounds__(VEC_THREADS) dot2_partial_kernel(int64_t n, co
 }
 void launch_dot2_partial(int64_t n, const double* a, const double* b, const double* c,
                          double* partial, hipStream_t s) {
-    dot2_partial_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, c, partial);
+    dot2_partial_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, c, partial, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 
 // out[c] = sum_{i<m} partial[c*stride + i] for c < ncomp, fixed order; then
 // thread 0 applies the CG scalar update `fin` to the scalar block.
-__device__ void cg_finish(int fin, double* scal) {
+// FIN_CONV closes an iteration: ctl[0] (the stop flag) becomes 2 on a
+// breakdown flagged in it (the iteration is not counted); otherwise ctl[1]
+// counts it and ctl[0] becomes 1 when ||r|| / ||b|| < tol (the operations
+// the host would use), 2 on a non-finite residual, 3 when ctl[1] reaches
+// ctl[2].
+__device__ void cg_finish(int fin, double* scal, int* ctl) {
+    if (fin == FIN_CONV) {
+        if (scal[S_FLAG] != 0.0) {   // breakdown in this iteration: not counted
+            ctl[0] = 2;
+            return;
+        }
+        const int k = ctl[1] + 1;
+        ctl[1] = k;
+        const double relres = sqrt(scal[S_RR]) / sqrt(scal[S_BB]);
+        if (!isfinite(relres))
+            ctl[0] = 2;
+        else if (relres < scal[S_TOL])
+            ctl[0] = 1;
+        else if (k >= ctl[2])
+            ctl[0] = 3;
+        return;
+    }
     if (fin == FIN_ALPHA) {
         const double pq = scal[S_PQ];
         if (!(pq > 0.0) || !isfinite(pq) || !isfinite(scal[S_RZ])) {
@@ -801,7 +848,9 @@ __device__ void cg_finish(int fin, double* scal) {
 __global__ void __launch_bounds__(RED_THREADS) reduce_kernel(int64_t m, const double* __restrict__ partial,
                                                              int64_t stride, int ncomp,
                                                              double* out, int fin,
-                                                             double* scal) {   // out may lie inside scal
+                                                             double* scal,   // out may lie inside scal
+                                                             int* ctl, const int* stop) {
+    if (stopped(stop)) return;
     __shared__ double sh[RED_THREADS];
     for (int c = 0; c < ncomp; ++c) {
         double s = 0.0;
@@ -811,12 +860,13 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_kernel(int64_t m, const do
     }
     if (fin != FIN_NONE && threadIdx.x == 0) {
         __threadfence_block();
-        cg_finish(fin, scal);
+        cg_finish(fin, scal, ctl);
     }
 }
 void launch_reduce(int64_t m, const double* partial, int64_t stride, int ncomp, double* out,
-                   hipStream_t s, int fin, double* scal) {
-    reduce_kernel<<<1, RED_THREADS, 0, s>>>(m, partial, stride, ncomp, out, fin, scal);
+                   hipStream_t s, int fin, double* scal, int* ctl) {
+    if (fin == FIN_CONV && ctl == nullptr) throw Error(GIAMG_EINVAL, "convergence test without control block");
+    reduce_kernel<<<1, RED_THREADS, 0, s>>>(m, partial, stride, ncomp, out, fin, scal, ctl, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 
@@ -829,7 +879,9 @@ __global__ void __launch_bounds__(VEC_THREADS) pcg_update_kernel(int64_t n, doub
                                                                  const double* __restrict__ p,
                                                                  const double* __restrict__ q,
                                                                  const double* __restrict__ scal,
-                                                                 double* __restrict__ partial) {
+                                                                 double* __restrict__ partial,
+                                                                 const int* stop) {
+    if (stopped(stop)) return;
     __shared__ double sh[VEC_THREADS];
     const double alpha = scal[S_ALPHA];
     double s = 0.0;
@@ -847,19 +899,21 @@ __global__ void __launch_bounds__(VEC_THREADS) pcg_update_kernel(int64_t n, doub
 }
 void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const double* p,
                        const double* q, const double* scal, double* partial, hipStream_t s) {
-    pcg_update_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, x, r, rold, p, q, scal, partial);
+    pcg_update_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, x, r, rold, p, q, scal, partial,
+                                                                    g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 
 __global__ void pcg_direction_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ p,
-                                     const double* __restrict__ scal) {
+                                     const double* __restrict__ scal, const int* stop) {
+    if (stopped(stop)) return;
     const double beta = scal[S_BETA];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = z[i] + beta * p[i];
 }
 void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s) {
-    pcg_direction_kernel<<<vgrid(n), VEC_THREADS, 0, s>>>(n, z, p, scal);
+    pcg_direction_kernel<<<vgrid(n), VEC_THREADS, 0, s>>>(n, z, p, scal, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 

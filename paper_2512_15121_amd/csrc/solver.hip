@@ -28,8 +28,14 @@ double ms_since(clock_t_::time_point t0) {
 
 Handle::~Handle() {
     if (host_scal) (void)hipHostFree(host_scal);
+    if (host_ctl) (void)hipHostFree(host_ctl);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (it_exec) (void)hipGraphExecDestroy(it_exec);
+    if (it_graph) (void)hipGraphDestroy(it_graph);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (gstream) (void)hipStreamDestroy(gstream);
 }
 
 void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
@@ -272,6 +278,8 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     H.scal.alloc(S_COUNT);
     GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), H.stream));
     if (!H.host_scal) GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&H.host_scal), S_COUNT * sizeof(double)));
+    H.ctl.alloc(C_COUNT);
+    if (!H.host_ctl) GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&H.host_ctl), C_COUNT * sizeof(int)));
     // smoother data
     t0 = clock_t_::now();
     for (size_t l = 0; l < H.levels.size(); ++l) {
@@ -311,6 +319,9 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     }
     if (!H.ev0) GIAMG_HIP(hipEventCreate(&H.ev0));
     if (!H.ev1) GIAMG_HIP(hipEventCreate(&H.ev1));
+    if (!H.ev_fork) GIAMG_HIP(hipEventCreateWithFlags(&H.ev_fork, hipEventDisableTiming));
+    if (!H.ev_join) GIAMG_HIP(hipEventCreateWithFlags(&H.ev_join, hipEventDisableTiming));
+    if (!H.gstream) GIAMG_HIP(hipStreamCreateWithFlags(&H.gstream, hipStreamNonBlocking));
     GIAMG_HIP(hipStreamSynchronize(H.stream));
     H.setup_ms[6] = ms_since(t_all);
 }
@@ -553,6 +564,14 @@ void precondition(Handle& H, const double* r, double* z) {
     }
 }
 
+// Points the handle's stream at another one for the scope (graph capture).
+struct StreamSwap {
+    Handle& H;
+    hipStream_t saved;
+    StreamSwap(Handle& h, hipStream_t st) : H(h), saved(h.stream) { H.stream = st; }
+    ~StreamSwap() { H.stream = saved; }
+};
+
 void fetch_scalars(Handle& H) {
     GIAMG_HIP(hipMemcpyAsync(H.host_scal, H.scal.get(), S_COUNT * sizeof(double),
                              hipMemcpyDeviceToHost, H.stream));
@@ -590,53 +609,128 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
         launch_fill(n, 0.0, x, s);
     } else {
         relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
-        if (!(relres < tol)) {
+        if (!(relres < tol) && H.opts.maxit > 0) {
+            // device-side convergence test: tolerance and control block
+            H.host_scal[S_TOL] = tol;
+            GIAMG_HIP(hipMemcpyAsync(H.scal.get() + S_TOL, H.host_scal + S_TOL, sizeof(double),
+                                     hipMemcpyHostToDevice, s));
+            H.host_ctl[C_STOP] = 0;
+            H.host_ctl[C_ITERS] = 0;
+            H.host_ctl[C_MAXIT] = H.opts.maxit;
+            H.host_ctl[3] = 0;
+            GIAMG_HIP(hipMemcpyAsync(H.ctl.get(), H.host_ctl, C_COUNT * sizeof(int), hipMemcpyHostToDevice, s));
             precondition(H, H.r.get(), H.z.get());
             H.bytes += 32.0 * n;
             launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
             launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
                           H.scal.get());
             launch_copy<double>(n, H.z.get(), H.p.get(), s);
-            status = GIAMG_ENOTCONV;
-            for (int k = 1; k <= H.opts.maxit; ++k) {
+            // Iterations are queued in chunks without reading anything back:
+            // the reduction that closes an iteration sets the device stop
+            // flag, after which every queued kernel returns at once.  The
+            // host reads the control block between chunks only; the first
+            // chunk is the previous solve's iteration count.  With
+            // graph_launch one iteration is a graph, captured at the first
+            // solve of the handle and replayed on the handle's graph stream.
+            // The iterate lives in the handle's x (copied in and out), so the
+            // graph's pointers never change.
+            const bool graph = H.opts.graph_launch != 0;
+            double* xi = H.x.get();
+            H.bytes += 16.0 * n;
+            launch_copy<double>(n, x, xi, s);
+            auto iteration = [&]() {
+                hipStream_t st = H.stream;
+                const double b0 = H.bytes;
                 SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
                 a.v = H.p.get(); a.y = H.q.get(); a.partial = H.partial.get();
                 H.bytes += (flexible ? 56.0 : 48.0) * n;
                 run_spmv(H, SPMV_DOT, a);
-                launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, s, FIN_ALPHA, H.scal.get());
-                launch_pcg_update(n, x, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
-                                  H.q.get(), H.scal.get(), H.partial.get(), s);
-                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, s);
-                fetch_scalars(H);
-                if (H.host_scal[S_FLAG] != 0.0) {
-                    status = GIAMG_EBREAKDOWN;
-                    break;
-                }
-                iters = k;
-                relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
-                if (!std::isfinite(relres)) {
-                    status = GIAMG_EBREAKDOWN;
-                    break;
-                }
-                if (relres < tol) {
-                    status = GIAMG_OK;
-                    break;
-                }
+                launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, st, FIN_ALPHA, H.scal.get());
+                launch_pcg_update(n, xi, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
+                                  H.q.get(), H.scal.get(), H.partial.get(), st);
+                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, st, FIN_CONV,
+                              H.scal.get(), H.ctl.get());
+                const double b1 = H.bytes;
                 precondition(H, H.r.get(), H.z.get());
                 if (flexible) {
                     H.bytes += 24.0 * n;
-                    launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), s);
-                    launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, s, FIN_BETA_FLEX,
+                    launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), st);
+                    launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, st, FIN_BETA_FLEX,
                                   H.scal.get());
                 } else {
                     H.bytes += 16.0 * n;
-                    launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
-                    launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA,
+                    launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), st);
+                    launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, st, FIN_BETA,
                                   H.scal.get());
                 }
                 H.bytes += 24.0 * n;
-                launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), s);
+                launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), st);
+                H.it_part1 = b1 - b0;
+                H.it_part2 = H.bytes - b1;
+            };
+            hipStream_t its = s;
+            if (graph) {
+                its = H.gstream;
+                if (!H.it_exec) {
+                    const double keep = H.bytes;
+                    StreamSwap swap(H, its);
+                    StopScope scope(H.ctl.get());
+                    std::lock_guard<std::mutex> cap(capture_mutex());
+                    GIAMG_HIP(hipStreamBeginCapture(its, hipStreamCaptureModeRelaxed));
+                    try {
+                        iteration();
+                    } catch (...) {
+                        hipGraph_t g = nullptr;
+                        (void)hipStreamEndCapture(its, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    GIAMG_HIP(hipStreamEndCapture(its, &H.it_graph));
+                    GIAMG_HIP(hipGraphInstantiate(&H.it_exec, H.it_graph, nullptr, nullptr, 0));
+                    H.bytes = keep;
+                }
+                GIAMG_HIP(hipEventRecord(H.ev_fork, s));
+                GIAMG_HIP(hipStreamWaitEvent(its, H.ev_fork, 0));
             }
+            const double bytes0 = H.bytes;
+            int launched = 0;
+            int chunk = H.last_iters > 0 ? H.last_iters : 8;
+            {
+                StopScope scope(H.ctl.get());
+                for (;;) {
+                    const int todo = std::min(chunk, H.opts.maxit - launched);
+                    for (int j = 0; j < todo; ++j) {
+                        if (graph)
+                            GIAMG_HIP(hipGraphLaunch(H.it_exec, its));
+                        else
+                            iteration();
+                    }
+                    launched += todo;
+                    GIAMG_HIP(hipMemcpyAsync(H.host_ctl, H.ctl.get(), C_COUNT * sizeof(int),
+                                             hipMemcpyDeviceToHost, its));
+                    GIAMG_HIP(hipStreamSynchronize(its));
+                    if (H.host_ctl[C_STOP] != 0 || launched >= H.opts.maxit) break;
+                    chunk = 1;
+                }
+            }
+            if (graph) {
+                GIAMG_HIP(hipEventRecord(H.ev_join, its));
+                GIAMG_HIP(hipStreamWaitEvent(s, H.ev_join, 0));
+            }
+            H.bytes = bytes0;
+            const double part1 = H.it_part1, part2 = H.it_part2;
+            launch_copy<double>(n, xi, x, s);
+            iters = H.host_ctl[C_ITERS];
+            const int stop = H.host_ctl[C_STOP];
+            status = stop == 1 ? GIAMG_OK : stop == 2 ? GIAMG_EBREAKDOWN : GIAMG_ENOTCONV;
+            H.last_iters = iters;
+            // bytes of the work that ran: the iteration that stopped skipped its second half
+            const int halves2 = std::max(0, (stop == 2 ? iters : iters - 1));
+            H.bytes = bytes0 + 16.0 * n + part1 * (stop == 2 ? iters + 1 : iters) + part2 * halves2;
+            fetch_scalars(H);
+            relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
+        } else if (!(relres < tol)) {
+            status = GIAMG_ENOTCONV;
         }
     }
     GIAMG_HIP(hipEventRecord(H.ev1, s));

@@ -39,7 +39,7 @@ class _Opts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("agg_seed", ctypes.c_uint64),
                 ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("graph_launch", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -86,10 +86,12 @@ class Options:
     cheb_lo: float = 0.1
     cheb_hi: float = 1.1
     direct_gathers: bool = False
+    graph_launch: bool = False
 
     def _c(self) -> _Opts:
         d = asdict(self)
         d["direct_gathers"] = int(d["direct_gathers"])
+        d["graph_launch"] = int(d["graph_launch"])
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]

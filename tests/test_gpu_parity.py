@@ -332,6 +332,38 @@ def test_edge_cases(torch_dev):
         Solver(m.coords, l2g, 2, 1.0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "manufactured_4cube_p2_jacobi", "p3_pin_neumann"])
+def test_graph_replay_equals_eager(torch_dev, name, precision):
+    """One CG iteration is captured as a graph at the first solve of a
+    handle and replayed.  Replays across several solves, with eager work on
+    the same handle and stream syncs between them, give the same iterates,
+    bit for bit, as launching every kernel from the host."""
+    torch, dev = torch_dev
+    m, _ = _case(name)
+    n = m.n_nodes
+    sg = _solver(name, precision=precision, graph_launch=True)
+    se = _solver(name, precision=precision)
+    tmp = torch.zeros(n, dtype=torch.float64, device=dev)
+    for trial, tol in enumerate([1e-10, 1e-6, 1e-12, 1e-10]):
+        if CASES[name][6] == "pin":
+            b = synth.pinned_normal_batch(n, 1, 30 + trial)[:, 0].copy()
+        else:
+            b = synth.normal_rhs(n, 30 + trial)
+        bt = _to(torch, dev, b)
+        xg, ig = sg.solve(bt, tol=tol)
+        xe, ie = se.solve(bt, tol=tol)
+        assert ig.status == ie.status == 0 and ig.iters == ie.iters, (trial, ig, ie)
+        assert torch.equal(xg, xe), trial
+        assert ig.relres == ie.relres
+        # eager work on the graph handle and the default stream between replays
+        sg.apply("spmv", 0, xg, out=tmp)
+        tmp.mul_(0.5)
+        torch.cuda.synchronize()
+    sg.close()
+    se.close()
+
+
 def test_determinism(torch_dev):
     torch, dev = torch_dev
     name = "p5_7cube_ragged"
@@ -341,4 +373,15 @@ def test_determinism(torch_dev):
     x1, i1 = s.solve(b)
     x2, i2 = s.solve(b)
     assert i1.iters == i2.iters and torch.equal(x1, x2)
+    # Iterations are queued in chunks sized by the previous solve and stop on
+    # a device flag: a handle's history changes neither count nor result.
+    b2 = _to(torch, dev, synth.normal_rhs(m.n_nodes, 4))
+    x3, i3 = s.solve(b2, tol=1e-6)
+    x4, i4 = s.solve(b2, tol=1e-12)
+    for tol, (xr, ir) in ((1e-6, (x3, i3)), (1e-12, (x4, i4))):
+        fresh = _solver(name)
+        xf, inf_ = fresh.solve(b2, tol=tol)
+        assert ir.iters == inf_.iters and ir.status == inf_.status == 0 and torch.equal(xr, xf)
+        fresh.close()
+    assert i3.iters < i1.iters < i4.iters
     s.close()
