@@ -303,7 +303,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic_entry(args.workload),
-                "kernel": "spmv_stream_kernel<double, SPMV_CHEB_STEP, 16> on the fine level",
+                "kernel": "spmv_stream_kernel<double, SPMV_CHEB_STEP, 16, 1> (staged gathers) on the fine level",
                 "bytes_per_launch": k_bytes, "ms_per_launch": round(k_ms, 5)}
     log(f"cheb_step fine: {k_ms*1e3:.1f} us, {achieved:.0f} GB/s")
 

@@ -275,15 +275,16 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
 
 /*
  * giamg_time_kernel -- time one device kernel of a level in the launch
- * configuration the solve uses: `reps` back-to-back launches between two
- * HIP events on the handle's stream (contents of the level's work vectors
+ * configuration the solve uses: `reps` launches on the handle's stream, each
+ * between its own pair of HIP events (contents of the level's work vectors
  * are overwritten).  kernel:
  *   GIAMG_KERNEL_CHEB_STEP  fused Chebyshev step on A_l (FP64; FP32 with GIAMG_OP_FP32)
  *   GIAMG_KERNEL_SPMV       plain y = A_l v
  *   GIAMG_KERNEL_RESTRICT   y = R_l v
  *   GIAMG_KERNEL_PROLONG    x += P_l v
  * ms receives the mean duration of one launch, bytes its algorithmic HBM
- * bytes (CSR arrays, the gathered vector once, row-local vectors).
+ * bytes (values, column ids or 16-bit slots and run tables, row pointers,
+ * the gathered vector once, row-local vectors).
  */
 #define GIAMG_KERNEL_CHEB_STEP 0
 #define GIAMG_KERNEL_SPMV      1

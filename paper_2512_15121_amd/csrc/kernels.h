@@ -45,6 +45,9 @@ struct SpmvArgs {
     int64_t nblk = 0;
     int lanes = 16;                  // lanes that reduce one row (16, 4 or 1)
     const int* stop = nullptr;       // device stop flag (null: the thread's StopScope flag)
+    // host only: events the dispatch itself records at kernel start and end
+    // (timing; null for ordinary launches)
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     const int32_t* run_ptr = nullptr;   // staged gathers (DevCSR); null: every block gathers directly
     const int32_t* runs = nullptr;
     const uint16_t* slot = nullptr;

@@ -12,6 +12,7 @@
 //  * every smoother/CG vector update fused into the product's row epilogue;
 //  * reductions are two-stage and fixed-order (no floating-point atomics), so
 //    results are bitwise reproducible run to run.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -540,13 +541,22 @@ void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
     d.nnz_staged = staged;
 }
 
+template <typename T, int MODE, int L, int STAGE>
+void launch_spmv_kernel(const SpmvArgs<T>& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
+    if (a.ev_start != nullptr)   // timing: the dispatch records the events itself
+        hipExtLaunchKernelGGL(spmv_stream_kernel<T, MODE, L, STAGE>, grid, block, 0, s, a.ev_start,
+                              a.ev_stop, 0, a);
+    else
+        spmv_stream_kernel<T, MODE, L, STAGE><<<grid, block, 0, s>>>(a);
+}
+
 template <typename T, int MODE, int STAGE>
 void launch_spmv_form(const SpmvArgs<T>& a, hipStream_t s) {
-    const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
     switch (a.lanes) {
-        case 16: spmv_stream_kernel<T, MODE, 16, STAGE><<<grid, block, 0, s>>>(a); break;
-        case 4: spmv_stream_kernel<T, MODE, 4, STAGE><<<grid, block, 0, s>>>(a); break;
-        case 1: spmv_stream_kernel<T, MODE, 1, STAGE><<<grid, block, 0, s>>>(a); break;
+        case 16: launch_spmv_kernel<T, MODE, 16, STAGE>(a, s); break;
+        case 4: launch_spmv_kernel<T, MODE, 4, STAGE>(a, s); break;
+        case 1: launch_spmv_kernel<T, MODE, 1, STAGE>(a, s); break;
         default: throw Error(GIAMG_EINVAL, "unsupported reduction width");
     }
 }

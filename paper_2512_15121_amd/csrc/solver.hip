@@ -794,13 +794,31 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
         GIAMG_HIP(hipMemsetAsync(LV<T>::x(C), 0, C.n * sizeof(T), H.stream));
     }
     launch_spmv(mode, a, H.stream);   // warm-up
-    GIAMG_HIP(hipEventRecord(H.ev0, H.stream));
-    for (int i = 0; i < reps; ++i) launch_spmv(mode, a, H.stream);
-    GIAMG_HIP(hipEventRecord(H.ev1, H.stream));
-    GIAMG_HIP(hipEventSynchronize(H.ev1));
-    float t = 0.0f;
-    GIAMG_HIP(hipEventElapsedTime(&t, H.ev0, H.ev1));
-    *ms = (double)t / reps;
+    // one event pair per launch, recorded by the dispatch itself at kernel
+    // start and end: the average is the kernel's own duration
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    double total = 0.0;
+    try {
+        for (auto& e : ev) GIAMG_HIP(hipEventCreate(&e));
+        for (int i = 0; i < reps; ++i) {
+            SpmvArgs<T> at = a;
+            at.ev_start = ev[2 * i];
+            at.ev_stop = ev[2 * i + 1];
+            launch_spmv(mode, at, H.stream);
+        }
+        GIAMG_HIP(hipEventSynchronize(ev.back()));
+        for (int i = 0; i < reps; ++i) {
+            float t = 0.0f;
+            GIAMG_HIP(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            total += t;
+        }
+    } catch (...) {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    *ms = total / reps;
     *bytes = spmv_bytes(mode, a);
 }
 }  // namespace
