@@ -12,7 +12,7 @@ CG from x = 0 to the tolerance); the hierarchy is built once before timing
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup,
 --workload {helmholtz16_p4,helmholtz32_p4}, --no-cpu-baseline, --no-mixed, --no-batched,
---serving {small,full,off}.
+--serving {small,medium,full,off}.
 """
 import argparse
 import numpy as np
@@ -162,8 +162,8 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
     (log-uniform [0.1, 100]) per (n, p) key, right-hand sides N(0, 1); mixed
     GIAMG-PCG to 1e-10.  A warm-up pass builds every hierarchy; then a
     closed-loop pass (all requests submitted at once) gives the saturation
-    throughput S, and an open-loop pass with Poisson arrivals at 0.7 S gives
-    p50 / p99 latency (submission to solution in host memory)."""
+    throughput S, and open-loop passes with Poisson arrivals at 0.7 S and
+    0.4 S give p50 / p99 latency (submission to solution in host memory)."""
     import threading
     import synth
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -225,6 +225,12 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
         log(f"serving: closed loop {sat:.1f} solves/s")
         gaps = rng.exponential(1.0 / (0.7 * sat), size=len(trace))
         t_open, lat_open, st_open = run(np.cumsum(gaps))
+        log(f"serving: open loop at 0.7 S: {len(trace) / t_open:.1f} solves/s")
+        # a lighter load too: with arrivals spread over many hierarchies few
+        # requests share a batch, so the open loop saturates below S
+        gaps4 = rng.exponential(1.0 / (0.4 * sat), size=len(trace))
+        t_open4, lat_open4, st_open4 = run(np.cumsum(gaps4))
+        log(f"serving: open loop at 0.4 S: {len(trace) / t_open4:.1f} solves/s")
         stats = srv.stats()
     finally:
         srv.close()
@@ -237,7 +243,11 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
            "p99_ms": round(float(np.percentile(lat_open, 99)), 3),
            "closed_p50_ms": round(float(np.percentile(lat_closed, 50)), 3),
            "closed_p99_ms": round(float(np.percentile(lat_closed, 99)), 3),
-           "all_ok": all(s_ == 0 for s_ in st_closed + st_open),
+           "open_loop_04": {"rate": round(0.4 * sat, 2),
+                            "solves_per_s": round(len(trace) / t_open4, 2),
+                            "p50_ms": round(float(np.percentile(lat_open4, 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat_open4, 99)), 3)},
+           "all_ok": all(s_ == 0 for s_ in st_closed + st_open + st_open4),
            "setups": stats["setups"], "cache_hits": stats["cache_hits"],
            "peak_bytes": stats["peak_bytes"]}
     log(f"serving: {out}")
@@ -253,7 +263,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serving", default="small", choices=["small", "full", "off"])
+    ap.add_argument("--serving", default="small", choices=["small", "medium", "full", "off"])
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy (3x) and the fine Chebyshev step (5x), "
                          "for hardware-counter runs")
@@ -306,12 +316,27 @@ def main():
                 "kernel": "spmv_stream_kernel<double, SPMV_CHEB_STEP, 16, 1> (staged gathers) on the fine level",
                 "bytes_per_launch": k_bytes, "ms_per_launch": round(k_ms, 5)}
     log(f"cheb_step fine: {k_ms*1e3:.1f} us, {achieved:.0f} GB/s")
+    # a plain 1 GiB device copy in the same run: the bandwidth a streaming
+    # kernel reaches here (read + write bytes over its time)
+    src = torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    extra_copy = {"copy_1gib_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    log(f"1 GiB copy: {copy_gbs:.0f} GB/s; Chebyshev step at {achieved / copy_gbs:.2f} of it")
 
     extra = {"iterations": iters, "true_relres": true_rel,
              "solve_gbs": round(bytes_per_solve / (ms_per_step * 1e-3) / 1e9, 1),
              "solve_bytes": bytes_per_solve,
              "setup_s": round(setup_s, 3), "setup_ms": solver.setup_times(),
-             "levels": levels}
+             "levels": levels, **extra_copy}
     for kname in ("spmv", "restrict", "prolong"):
         kms, kb = solver.time_kernel(kname, level=0, reps=20)
         extra[f"{kname}_fine_gbs"] = round(kb / (kms * 1e-3) / 1e9, 1)
@@ -336,6 +361,9 @@ def main():
         try:
             if args.serving == "full":
                 extra["serving"] = serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24),
+                                               p_range=(2, 6))
+            elif args.serving == "medium":
+                extra["serving"] = serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 16),
                                                p_range=(2, 6))
             else:
                 extra["serving"] = serving_leg(torch, Server, Options)
