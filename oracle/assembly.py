@@ -1,12 +1,15 @@
-"""Fine-level operator A = K + lambda M for GLL-nodal hexahedra (oracle).
+"""Fine-level operator A = K + lambda M for hexahedra of order p (oracle).
 
 Problem statement: the Helmholtz equation -lap u + lambda u = f on the unit
 cube with homogeneous Dirichlet data (Section 3.1, Helmholtz operator); the
 pressure-Poisson case is lambda = 0 (Section 3.2).  The paper assembles with
 Nektar++; the readings below replace that:
 
-* basis: tensor-product Lagrange on GLL points, local index
-  (p+1)^2 i + (p+1) j + k with i along x (appendix ordering);
+* basis: tensor-product Lagrange on GLL points ("nodal"), or the
+  appendix's hierarchical modal basis ("modal": 1-D modes (1-a)/2, (1+a)/2,
+  then bubbles); local index (p+1)^2 i + (p+1) j + k with i along x
+  (appendix ordering).  The vertex modes/nodes at a = -1 and a = +1 have
+  local index 0 and p (nodal) or 0 and 1 (modal);
 * geometry: the trilinear map of the element's eight corner nodes;
 * quadrature: Gauss-Legendre with p+2 points per direction, consistent mass;
 * pattern: (r, c) is stored when r and c belong to a common element
@@ -21,43 +24,58 @@ TEST INFRASTRUCTURE ONLY.
 import numpy as np
 import scipy.sparse as sp
 
-from .basis import gll_points, gauss_points, lagrange_eval, lagrange_deriv
+from .basis import (gll_points, gauss_points, lagrange_eval, lagrange_deriv, modal_eval,
+                    modal_deriv)
+
+BASES = ("nodal", "modal")
 
 
 def local_index(p: int, i, j, k):
     return (p + 1) * (p + 1) * i + (p + 1) * j + k
 
 
-def corner_local_indices(p: int) -> np.ndarray:
+def ends(p: int, basis: str = "nodal"):
+    """1-D local indices of the modes/nodes that are one at a = -1 and a = +1."""
+    if basis not in BASES:
+        raise ValueError(basis)
+    return (0, p) if basis == "nodal" else (0, 1)
+
+
+def corner_local_indices(p: int, basis: str = "nodal") -> np.ndarray:
     """Local indices of the 8 corners, corner c = 4 cx + 2 cy + cz."""
+    e = ends(p, basis)
     out = []
     for cx in (0, 1):
         for cy in (0, 1):
             for cz in (0, 1):
-                out.append(local_index(p, cx * p, cy * p, cz * p))
+                out.append(local_index(p, e[cx], e[cy], e[cz]))
     return np.array(out)
 
 
-def face_local_indices(p: int):
-    """The six faces of the reference hexahedron as lists of local indices."""
+def face_local_indices(p: int, basis: str = "nodal"):
+    """The six faces of the reference hexahedron: the local indices of the
+    modes/nodes not vanishing on each face, in (A, B) row-major order."""
     r = np.arange(p + 1)
     A, B = np.meshgrid(r, r, indexing="ij")
     A, B = A.ravel(), B.ravel()
     faces = []
-    for fixed in (0, p):
+    for fixed in ends(p, basis):
         faces.append(local_index(p, fixed, A, B))
         faces.append(local_index(p, A, fixed, B))
         faces.append(local_index(p, A, B, fixed))
     return faces
 
 
-def boundary_nodes(l2g: np.ndarray, p: int, n_nodes: int) -> np.ndarray:
-    """Boolean mask: node lies on a face that belongs to exactly one element."""
-    faces = face_local_indices(p)
+def boundary_nodes(l2g: np.ndarray, p: int, n_nodes: int, basis: str = "nodal") -> np.ndarray:
+    """Boolean mask: node (mode) lies on a face that belongs to exactly one
+    element; faces are told apart by their four corner ids."""
+    faces = face_local_indices(p, basis)
+    lo, hi = ends(p, basis)
+    cpos = [lo * (p + 1) + lo, lo * (p + 1) + hi, hi * (p + 1) + lo, hi * (p + 1) + hi]
     keys = []
     members = []
     for f in faces:
-        corners = l2g[:, [f[0], f[p], f[p * (p + 1)], f[-1]]].astype(np.int64)
+        corners = l2g[:, f[cpos]].astype(np.int64)
         keys.append(np.sort(corners, axis=1))
         members.append(l2g[:, f])
     keys = np.concatenate(keys, axis=0)
@@ -69,9 +87,9 @@ def boundary_nodes(l2g: np.ndarray, p: int, n_nodes: int) -> np.ndarray:
     return mask
 
 
-def constrained_mask(l2g, p, n_nodes, bc="dirichlet", pin=0):
+def constrained_mask(l2g, p, n_nodes, bc="dirichlet", pin=0, basis="nodal"):
     if bc == "dirichlet":
-        return boundary_nodes(l2g, p, n_nodes)
+        return boundary_nodes(l2g, p, n_nodes, basis)
     if bc == "pin":
         m = np.zeros(n_nodes, dtype=bool)
         m[pin] = True
@@ -81,13 +99,17 @@ def constrained_mask(l2g, p, n_nodes, bc="dirichlet", pin=0):
     raise ValueError(bc)
 
 
-def _reference_tables(p: int, nq: int):
+def _reference_tables(p: int, nq: int, basis: str = "nodal"):
     """Basis values/gradients and trilinear-map derivatives at the tensor
     Gauss points (x slowest)."""
     xg, wg = gauss_points(nq)
-    xn, _ = gll_points(p)
-    L = lagrange_eval(xn, xg)       # [p+1, nq]
-    D = lagrange_deriv(xn, xg)
+    if basis == "nodal":
+        xn, _ = gll_points(p)
+        L = lagrange_eval(xn, xg)       # [p+1, nq]
+        D = lagrange_deriv(xn, xg)
+    else:
+        L = modal_eval(p, xg)
+        D = modal_deriv(p, xg)
     nl = (p + 1) ** 3
     Q = nq ** 3
     phi = np.zeros((nl, Q))
@@ -119,27 +141,27 @@ def _reference_tables(p: int, nq: int):
     return phi, dphi, w, N, dN
 
 
-def element_geometry(coords, l2g, p, N, dN):
+def element_geometry(coords, l2g, p, N, dN, basis="nodal"):
     """Jacobian J[e, q, a, d] = d x_a / d xi_d and det J per element and point."""
-    X = coords[l2g[:, corner_local_indices(p)]]          # [E, 8, 3]
+    X = coords[l2g[:, corner_local_indices(p, basis)]]   # [E, 8, 3]
     J = np.einsum("eca,cqd->eqad", X, dN)
     det = np.linalg.det(J)
     xq = np.einsum("eca,cq->eqa", X, N)
     return J, det, xq
 
 
-def element_matrices(coords, l2g, p, nq, lam):
+def element_matrices(coords, l2g, p, nq, lam, basis="nodal"):
     """Element matrices K_e + lam M_e, symmetrised by mirroring the upper
     triangle so the assembled matrix is bitwise symmetric.  Yields chunks
     (element ids, matrices)."""
-    phi, dphi, w, N, dN = _reference_tables(p, nq)
+    phi, dphi, w, N, dN = _reference_tables(p, nq, basis)
     E = l2g.shape[0]
     nl = (p + 1) ** 3
     iu = np.triu_indices(nl, 1)
     chunk = max(1, int(2e7 // (nl * nl + nl * phi.shape[1] * 3)))
     for e0 in range(0, E, chunk):
         e1 = min(E, e0 + chunk)
-        J, det, _ = element_geometry(coords, l2g[e0:e1], p, N, dN)
+        J, det, _ = element_geometry(coords, l2g[e0:e1], p, N, dN, basis)
         if np.any(det <= 0):
             raise ValueError("non-positive Jacobian determinant")
         Jinv = np.linalg.inv(J)                                  # [e,q,d,a]
@@ -158,14 +180,14 @@ def element_matrices(coords, l2g, p, nq, lam):
         yield np.arange(e0, e1), A
 
 
-def assemble(coords, l2g, p, lam, bc="dirichlet", pin=0, nq=None):
+def assemble(coords, l2g, p, lam, bc="dirichlet", pin=0, nq=None, basis="nodal"):
     """Assembled CSR matrix (float64, int32 indices) and the constrained mask."""
     n_nodes = coords.shape[0]
     nq = p + 2 if nq is None else nq
-    cons = constrained_mask(l2g, p, n_nodes, bc, pin)
+    cons = constrained_mask(l2g, p, n_nodes, bc, pin, basis)
     nl = (p + 1) ** 3
     rows_l, cols_l, vals_l = [], [], []
-    for eids, Ae in element_matrices(coords, l2g, p, nq, lam):
+    for eids, Ae in element_matrices(coords, l2g, p, nq, lam, basis):
         g = l2g[eids].astype(np.int64)
         rows_l.append(np.repeat(g, nl, axis=1).ravel())
         cols_l.append(np.tile(g, (1, nl)).ravel())
@@ -210,21 +232,21 @@ def csr_from_sorted_or_not(r, c, v, nr, nc):
     return M
 
 
-def quadrature_points(coords, l2g, p, nq=None):
+def quadrature_points(coords, l2g, p, nq=None, basis="nodal"):
     """Physical coordinates of the tensor Gauss points, [E, nq^3, 3]."""
     nq = p + 2 if nq is None else nq
-    _, _, _, N, dN = _reference_tables(p, nq)
-    _, _, xq = element_geometry(coords, l2g, p, N, dN)
+    _, _, _, N, dN = _reference_tables(p, nq, basis)
+    _, _, xq = element_geometry(coords, l2g, p, N, dN, basis)
     return xq
 
 
-def load_vector(coords, l2g, p, fq, cons, nq=None):
+def load_vector(coords, l2g, p, fq, cons, nq=None, basis="nodal"):
     """b_i = sum over elements of the quadrature of f phi_i, with f given at
     the element quadrature points (fq: [E, nq^3]); b = 0 on constrained
     nodes (homogeneous Dirichlet data)."""
     nq = p + 2 if nq is None else nq
-    phi, _, w, N, dN = _reference_tables(p, nq)
-    _, det, _ = element_geometry(coords, l2g, p, N, dN)
+    phi, _, w, N, dN = _reference_tables(p, nq, basis)
+    _, det, _ = element_geometry(coords, l2g, p, N, dN, basis)
     be = np.einsum("iq,eq,eq->ei", phi, w[None, :] * det, fq)
     b = np.zeros(coords.shape[0])
     np.add.at(b, l2g.ravel(), be.ravel())

@@ -1,4 +1,4 @@
-"""1-D nodal basis and quadrature (oracle, test infrastructure only).
+"""1-D nodal and modal bases and quadrature (oracle, test infrastructure only).
 
 The paper's nodal variant builds prolongation by evaluating the lower-order
 basis at the higher-order nodes (Introduction; footnote to Algorithm 7).  The
@@ -63,4 +63,32 @@ def lagrange_deriv(nodes: np.ndarray, x: np.ndarray) -> np.ndarray:
                 if j != i and j != m:
                     term *= (x - nodes[j]) / (nodes[i] - nodes[j])
             D[i] += term
+    return D
+
+
+def modal_eval(p: int, x: np.ndarray) -> np.ndarray:
+    """V[n, q] = phi_n(x_q), n = 0..p, for the appendix's 1-D modal basis."""
+    from scipy.special import eval_jacobi
+    x = np.asarray(x, dtype=np.float64)
+    V = np.zeros((p + 1, x.size))
+    V[0] = (1.0 - x) / 2.0
+    V[1] = (1.0 + x) / 2.0
+    for n in range(2, p + 1):
+        V[n] = (1.0 - x) / 2.0 * (1.0 + x) / 2.0 * eval_jacobi(n - 2, 1, 1, x)
+    return V
+
+
+def modal_deriv(p: int, x: np.ndarray) -> np.ndarray:
+    """D[n, q] = phi_n'(x_q): product rule on the bubble, with
+    d/dx P^{1,1}_m = (m + 3)/2 P^{2,2}_{m-1}."""
+    from scipy.special import eval_jacobi
+    x = np.asarray(x, dtype=np.float64)
+    D = np.zeros((p + 1, x.size))
+    D[0] = -0.5
+    D[1] = 0.5
+    for n in range(2, p + 1):
+        m = n - 2
+        J = eval_jacobi(m, 1, 1, x)
+        dJ = (m + 3) / 2.0 * eval_jacobi(m - 1, 2, 2, x) if m >= 1 else np.zeros_like(x)
+        D[n] = -x / 2.0 * J + (1.0 - x * x) / 4.0 * dJ
     return D

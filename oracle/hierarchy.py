@@ -8,6 +8,10 @@ Galerkin product R A P with R = P^T, computed at setup (Section 2.1).  The
 coarsest level is solved directly (the paper uses SuperLU; here a dense
 Cholesky factorisation, which gives the same solution up to rounding).
 
+The modal basis (appendix) uses injection P (Algorithm 7 as printed); the
+order-1 level is the same in both bases (vertex modes are the Q1 nodes), so
+the smoothed-aggregation levels below it do not depend on the basis.
+
 Readings: p-coarsening always continues to order 1 (Table 1: p = 8 on eight
 elements gives four levels); h-levels stop when the level has at most
 ``coarse_max`` rows, when the hierarchy holds ``max_levels`` levels, or when
@@ -52,6 +56,7 @@ class Options:
     power_iters: int = 20
     cheb_lo: float = 0.1
     cheb_hi: float = 1.1
+    basis: str = "nodal"            # or "modal" (appendix basis, injection P)
 
 
 @dataclass
@@ -64,7 +69,7 @@ class Hierarchy:
 def build(coords, l2g, p, lam, opts: Options = None) -> Hierarchy:
     opts = opts or Options()
     n = coords.shape[0]
-    A, cons = assembly.assemble(coords, l2g, p, lam, bc=opts.bc, pin=opts.pin)
+    A, cons = assembly.assemble(coords, l2g, p, lam, bc=opts.bc, pin=opts.pin, basis=opts.basis)
     H = Hierarchy(opts=opts, constrained=cons)
     free = ~cons
     cur_l2g = l2g
@@ -75,7 +80,7 @@ def build(coords, l2g, p, lam, opts: Options = None) -> Hierarchy:
         if len(H.levels) >= opts.max_levels:
             break
         collect, l2g_nx, P = ptransfer.p_level(cur_l2g, level.order, q,
-                                               level.A.shape[0], free)
+                                               level.A.shape[0], free, opts.basis)
         if collect.size == 0:
             break
         R = galerkin.transpose(P)

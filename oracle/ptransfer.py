@@ -5,16 +5,19 @@ Algorithm 2 (extract the element dofs kept at the next level), Algorithm 3
 (collect the kept dofs over all elements and sort them), Algorithm 4 (the
 next-level l2g map through the rank of each kept dof in the sorted
 collection), and Section 2.4 / Algorithm 7 (prolongation as COO triples,
-sorted, duplicates removed).  The nodal variant (footnote to Algorithm 7;
-Introduction) replaces the injected 1.0 by the lower-order basis evaluated
-at the higher-order nodes.
+sorted, duplicates removed).  With the modal basis (appendix ordering)
+Algorithm 2 keeps the local modes i, j, k <= q, which are the order-q modes
+themselves, and P injects them (entries 1.0).  The nodal variant (footnote
+to Algorithm 7; Introduction) replaces the injected 1.0 by the lower-order
+basis evaluated at the higher-order nodes.
 
 Readings where the paper is silent:
 * schedule: q = p / (smallest prime factor of p), so the coarse order
   divides the fine one (8 -> 4 -> 2 -> 1 gives Table 1's four levels);
 * the coarse local node (a, b, c) is kept at the fine local node
-  (s a, s b, s c), s = p / q (Algorithm 2 keeps i, j, k <= p/2 in the modal
-  ordering; with nodal GLL bases the kept nodes are the lattice multiples);
+  (s a, s b, s c), s = p / q, for nodal GLL bases (the lattice multiples);
+  with the modal basis the coarse local mode (a, b, c) is the fine local
+  mode (a, b, c), a, b, c <= q (Algorithm 2 as printed, for any q < p);
 * constrained fine nodes have empty rows of P; coarse levels contain free
   nodes only, so a kept node that is constrained is marked -1 in l2g_next;
 * interpolation entries with |value| <= 1e-12 in the 1-D factor are
@@ -45,9 +48,14 @@ def p_schedule(p: int):
     return out
 
 
-def interp_1d(p: int, q: int) -> np.ndarray:
+def interp_1d(p: int, q: int, basis: str = "nodal") -> np.ndarray:
     """I1[i, a] = l^q_a(xi^p_i): order-q GLL Lagrange basis at order-p GLL
-    points, with |I1| <= 1e-12 set to exact zero."""
+    points, with |I1| <= 1e-12 set to exact zero.  Modal: the injection
+    I1[a, a] = 1 for a <= q (the order-q modes are fine modes)."""
+    if basis == "modal":
+        I1 = np.zeros((p + 1, q + 1))
+        I1[np.arange(q + 1), np.arange(q + 1)] = 1.0
+        return I1
     xp, _ = gll_points(p)
     xq, _ = gll_points(q)
     I1 = lagrange_eval(xq, xp).T          # [p+1, q+1]
@@ -55,10 +63,10 @@ def interp_1d(p: int, q: int) -> np.ndarray:
     return I1
 
 
-def extract_next_dof(p: int, q: int) -> np.ndarray:
+def extract_next_dof(p: int, q: int, basis: str = "nodal") -> np.ndarray:
     """Fine local index of each coarse local node, in coarse local order
-    (Algorithm 2, nodal reading)."""
-    s = p // q
+    (Algorithm 2: modal as printed, nodal reading for GLL nodes)."""
+    s = p // q if basis == "nodal" else 1
     out = []
     for a in range(q + 1):
         for b in range(q + 1):
@@ -67,19 +75,19 @@ def extract_next_dof(p: int, q: int) -> np.ndarray:
     return np.array(out, dtype=np.int64)
 
 
-def dof_next(l2g: np.ndarray, p: int, q: int, free: np.ndarray) -> np.ndarray:
+def dof_next(l2g: np.ndarray, p: int, q: int, free: np.ndarray, basis: str = "nodal") -> np.ndarray:
     """Sorted unique fine ids of kept, free nodes (Algorithm 3)."""
-    kept = l2g[:, extract_next_dof(p, q)].ravel()
+    kept = l2g[:, extract_next_dof(p, q, basis)].ravel()
     kept = kept[kept >= 0]
     kept = kept[free[kept]]
     return np.unique(kept)
 
 
 def l2g_next(l2g: np.ndarray, p: int, q: int, collect: np.ndarray,
-             free: np.ndarray) -> np.ndarray:
+             free: np.ndarray, basis: str = "nodal") -> np.ndarray:
     """Coarse ids through the rank in ``collect`` (Algorithm 4); -1 for kept
     nodes that are constrained."""
-    kept = l2g[:, extract_next_dof(p, q)].astype(np.int64)
+    kept = l2g[:, extract_next_dof(p, q, basis)].astype(np.int64)
     out = np.full(kept.shape, -1, dtype=np.int64)
     ok = kept >= 0
     ok[ok] = free[kept[ok]]
@@ -88,10 +96,10 @@ def l2g_next(l2g: np.ndarray, p: int, q: int, collect: np.ndarray,
     return out.astype(np.int32)
 
 
-def prolongation(l2g, l2g_nx, p, q, n_fine, n_coarse, free):
+def prolongation(l2g, l2g_nx, p, q, n_fine, n_coarse, free, basis="nodal"):
     """P as COO over elements, sorted by (row, col), first occurrence kept
-    (Algorithm 7 with interpolated values)."""
-    I1 = interp_1d(p, q)
+    (Algorithm 7: injected ones for modal, interpolated values for nodal)."""
+    I1 = interp_1d(p, q, basis)
     rows, cols, vals, elems = [], [], [], []
     eidx = np.arange(l2g.shape[0], dtype=np.int64)
     for i in range(p + 1):
@@ -133,9 +141,9 @@ def prolongation(l2g, l2g_nx, p, q, n_fine, n_coarse, free):
                                   n_fine, n_coarse)
 
 
-def p_level(l2g, p, q, n_fine, free):
+def p_level(l2g, p, q, n_fine, free, basis="nodal"):
     """One p-coarsening step.  Returns (collect, l2g_next, P)."""
-    collect = dof_next(l2g, p, q, free)
-    l2g_nx = l2g_next(l2g, p, q, collect, free)
-    P = prolongation(l2g, l2g_nx, p, q, n_fine, collect.size, free)
+    collect = dof_next(l2g, p, q, free, basis)
+    l2g_nx = l2g_next(l2g, p, q, collect, free, basis)
+    P = prolongation(l2g, l2g_nx, p, q, n_fine, collect.size, free, basis)
     return collect, l2g_nx, P

@@ -7,6 +7,16 @@ node (ix, iy, iz) has global id ``(ix*(n*p+1) + iy)*(n*p+1) + iz``.  Element
 row of ``l2g`` -- the tensor ordering of the paper's appendix (hexahedral
 dof ordering, i along x, j along y, k along z).
 
+Modal ordering (basis="modal").  The hierarchical modal basis of the
+paper's appendix numbers the 1-D modes 0 = (1-a)/2, 1 = (1+a)/2, then the
+bubbles 2..p.  A mode's global id is the lattice id of its position: mode 0
+at position 0, mode 1 at position p, bubble m at position m - 1.  Vertex
+modes are then shared between neighbouring elements exactly as nodal end
+nodes are, bubbles stay inside their element along that axis, and every
+element has the same orientation, so face and edge modes match across
+elements.  ``coords`` is the same lattice; only vertex-mode positions carry
+geometry.
+
 Geometry.  Mesh vertices form an (n+1)^3 grid with spacing h = 1/n.  Interior
 vertices (not on the cube's boundary) are moved by independent
 U(-perturb*h, +perturb*h) offsets per coordinate, drawn from numpy's PCG64
@@ -55,10 +65,20 @@ def _vertex_grid(n: int, perturb: float, seed) -> np.ndarray:
     return v
 
 
-def hex_mesh(n: int, p: int, perturb: float = 0.0, seed=None) -> HexMesh:
-    """Build the order-p structured mesh of n^3 hexahedra on the unit cube."""
+def modal_positions(p: int) -> np.ndarray:
+    """Lattice position (0..p) of each 1-D modal index in an element."""
+    pos = np.arange(p + 1) - 1
+    pos[0], pos[1] = 0, p
+    return pos
+
+
+def hex_mesh(n: int, p: int, perturb: float = 0.0, seed=None, basis: str = "nodal") -> HexMesh:
+    """Build the order-p structured mesh of n^3 hexahedra on the unit cube;
+    ``basis`` picks the local ordering of l2g ("nodal" or "modal")."""
     if n < 1 or p < 1:
         raise ValueError("n and p must be >= 1")
+    if basis not in ("nodal", "modal"):
+        raise ValueError("basis must be 'nodal' or 'modal'")
     L = n * p + 1
     verts = _vertex_grid(n, perturb, seed)
     V = verts.reshape(n + 1, n + 1, n + 1, 3)
@@ -82,7 +102,7 @@ def hex_mesh(n: int, p: int, perturb: float = 0.0, seed=None) -> HexMesh:
     # element -> node map in the (p+1)^2 i + (p+1) j + k ordering
     el = np.arange(n)
     EX, EY, EZ = np.meshgrid(el, el, el, indexing="ij")
-    loc = np.arange(p + 1)
+    loc = np.arange(p + 1) if basis == "nodal" else modal_positions(p)
     I, J, K = np.meshgrid(loc, loc, loc, indexing="ij")
     gx = EX.ravel()[:, None] * p + I.ravel()[None, :]
     gy = EY.ravel()[:, None] * p + J.ravel()[None, :]
