@@ -57,6 +57,11 @@ extern "C" {
 #define GIAMG_BC_PIN             1  /* only pin_node is constrained (pure Neumann + pin) */
 #define GIAMG_PREC_FP64          0  /* everything in double precision, standard PCG */
 #define GIAMG_PREC_MIXED         1  /* FP32 V-cycle (coarsest in FP64) inside FP64 flexible CG */
+#define GIAMG_BASIS_NODAL        0  /* tensor Lagrange on Gauss-Lobatto-Legendre points */
+#define GIAMG_BASIS_MODAL        1  /* hierarchical modal basis of the paper's appendix:
+                                       1-D modes (1-a)/2, (1+a)/2, then bubbles
+                                       (1-a)/2 (1+a)/2 P^{1,1}_{n-2}(a); p-transfers
+                                       inject the low modes (Algorithm 7) */
 
 typedef struct giamg_opts {
     int32_t  smoother;     /* GIAMG_SMOOTHER_*; default Chebyshev */
@@ -79,6 +84,8 @@ typedef struct giamg_opts {
                               first solve and replayed (same kernels, same results, bit for
                               bit; less host work per iteration); default 0: the host launches
                               every kernel, which measured slightly faster on the device */
+    int32_t  basis;        /* GIAMG_BASIS_*; default nodal */
+    int32_t  reserved;     /* set to 0 */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -101,21 +108,26 @@ typedef struct giamg_info {
  * giamg_setup -- build the hierarchy for A = K + lambda M.
  *
  * coords   host, double [n_nodes][3]: node coordinates.  Only the eight corner
- *          nodes of each element are read: an element is the trilinear image
- *          of its corners (local (i,j,k) in {0,p}^3).
+ *          dofs of each element are read: an element is the trilinear image
+ *          of its corners (local (i,j,k) in {0,p}^3 for the nodal basis, in
+ *          {0,1}^3 -- the vertex modes -- for the modal basis).
  * l2g      host, int32 [n_elem][(p+1)^3]: the element-to-dof map of
- *          Section 2.2.  Column (p+1)^2 i + (p+1) j + k holds the node with
+ *          Section 2.2.  Column (p+1)^2 i + (p+1) j + k holds the dof with
  *          basis index i along the first, j along the second and k along the
  *          third reference direction (the tensor ordering of the paper's
- *          appendix).  Every node must belong to at least one element.
+ *          appendix; modal index 0 and 1 are the vertex modes at -1 and +1,
+ *          2..p the bubbles).  Shared modal dofs must have the same
+ *          orientation in every element that holds them.  Every dof must
+ *          belong to at least one element.
  * p        order, 1 <= p <= 10.   lambda >= 0 (lambda = 0 needs at least one
  *          constrained node).
  * opts     NULL for defaults.
  * stream   hipStream_t for all work of this handle (NULL = default stream).
  * out      receives the handle; left untouched on error.
  *
- * Discretisation: tensor Lagrange basis on Gauss-Lobatto-Legendre points,
- * Gauss-Legendre quadrature with p+2 points per direction.  Constrained
+ * Discretisation: tensor Lagrange basis on Gauss-Lobatto-Legendre points
+ * (or the modal basis, opts->basis), Gauss-Legendre quadrature with p+2
+ * points per direction.  Constrained
  * nodes get identity rows and columns.  Coarse orders follow
  * q = p / (smallest prime factor of p) down to 1; coarse levels hold free
  * nodes only.  Errors: GIAMG_EINVAL, GIAMG_ENOMEM, GIAMG_EHIP, GIAMG_ENOTSUP.
@@ -249,23 +261,24 @@ int  giamg_hcsr_copy(giamg_hcsr m, int64_t* row_ptr, int32_t* col, double* val);
 void giamg_hcsr_free(giamg_hcsr m);
 
 /* Constrained-node mask of giamg_setup's boundary rule (faces owned by one
- * element), uint8 [n_nodes]. */
+ * element), uint8 [n_nodes]; basis GIAMG_BASIS_*. */
 int giamg_host_boundary(const int32_t* l2g, int64_t n_elem, int32_t p, int64_t n_nodes,
-                        uint8_t* mask);
+                        int32_t basis, uint8_t* mask);
 
-/* Fine-level assembly exactly as giamg_setup performs it (bc and pin_node as
- * in giamg_opts). */
+/* Fine-level assembly exactly as giamg_setup performs it (bc, pin_node and
+ * basis as in giamg_opts). */
 int giamg_host_assemble(const double* coords, int64_t n_nodes, const int32_t* l2g,
                         int64_t n_elem, int32_t p, double lambda, int32_t bc,
-                        int64_t pin_node, giamg_hcsr* A_out);
+                        int64_t pin_node, int32_t basis, giamg_hcsr* A_out);
 
-/* One p-coarsening step p -> q (q divides p) of Algorithms 2-4 and 7:
+/* One p-coarsening step p -> q of Algorithms 2-4 and 7 (nodal: q divides p,
+ * interpolation; modal: any q < p, injection):
  * free_mask uint8 [n_fine] marks the free fine nodes, l2g may hold -1 for
  * constrained nodes; writes l2g_next int32 [n_elem][(q+1)^3] (-1 for
  * constrained coarse nodes), the coarse size, and P. */
 int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t q,
-                          int64_t n_fine, const uint8_t* free_mask, int32_t* l2g_next,
-                          int64_t* n_coarse, giamg_hcsr* P_out);
+                          int64_t n_fine, const uint8_t* free_mask, int32_t basis,
+                          int32_t* l2g_next, int64_t* n_coarse, giamg_hcsr* P_out);
 
 /* Smoothed-aggregation transfer of Section 2.5 for a CSR operator (host
  * arrays, ascending columns): writes agg int32 [n], returns P. */

@@ -83,6 +83,8 @@ void giamg_default_opts(giamg_opts* o) {
     o->cheb_hi = 1.1;
     o->direct_gathers = 0;
     o->graph_launch = 0;
+    o->basis = GIAMG_BASIS_NODAL;
+    o->reserved = 0;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -114,6 +116,7 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
         GIAMG_REQUIRE(o.cheb_lo > 0.0 && o.cheb_hi > o.cheb_lo, "need 0 < cheb_lo < cheb_hi");
         GIAMG_REQUIRE(o.direct_gathers == 0 || o.direct_gathers == 1, "direct_gathers must be 0 or 1");
         GIAMG_REQUIRE(o.graph_launch == 0 || o.graph_launch == 1, "graph_launch must be 0 or 1");
+        GIAMG_REQUIRE(o.basis == GIAMG_BASIS_NODAL || o.basis == GIAMG_BASIS_MODAL, "unknown basis");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         for (int64_t i = 0; i < n_elem * nl; ++i)
             GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");
@@ -287,7 +290,7 @@ int giamg_load_vector(giamg_handle h, const double* fq, double* b) {
         bind_device(h);
         GIAMG_REQUIRE(fq != nullptr && b != nullptr, "fq and b must be non-null");
         giamg::load_vector(h->h.corners, h->h.l2g.data(), h->h.n_elem, h->h.porder, h->h.n_nodes,
-                           h->h.constrained, fq, b);
+                           h->h.constrained, fq, b, h->h.opts.basis);
         return GIAMG_OK;
     });
 }
@@ -324,13 +327,14 @@ int giamg_hcsr_copy(giamg_hcsr m, int64_t* row_ptr, int32_t* col, double* val) {
 void giamg_hcsr_free(giamg_hcsr m) { delete m; }
 
 int giamg_host_boundary(const int32_t* l2g, int64_t n_elem, int32_t p, int64_t n_nodes,
-                        uint8_t* mask) {
+                        int32_t basis, uint8_t* mask) {
     return guarded([&]() -> int {
         GIAMG_REQUIRE(l2g && mask && n_elem > 0 && n_nodes > 0 && p >= 1 && p <= 10, "bad arguments");
+        GIAMG_REQUIRE(basis == GIAMG_BASIS_NODAL || basis == GIAMG_BASIS_MODAL, "unknown basis");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         for (int64_t i = 0; i < n_elem * nl; ++i)
             GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");
-        auto m = giamg::boundary_mask(l2g, n_elem, p, n_nodes);
+        auto m = giamg::boundary_mask(l2g, n_elem, p, n_nodes, basis);
         std::memcpy(mask, m.data(), m.size());
         return GIAMG_OK;
     });
@@ -338,10 +342,11 @@ int giamg_host_boundary(const int32_t* l2g, int64_t n_elem, int32_t p, int64_t n
 
 int giamg_host_assemble(const double* coords, int64_t n_nodes, const int32_t* l2g,
                         int64_t n_elem, int32_t p, double lambda, int32_t bc, int64_t pin_node,
-                        giamg_hcsr* A_out) {
+                        int32_t basis, giamg_hcsr* A_out) {
     return guarded([&]() -> int {
         GIAMG_REQUIRE(coords && l2g && A_out && n_elem > 0 && n_nodes > 0 && p >= 1 && p <= 10,
                       "bad arguments");
+        GIAMG_REQUIRE(basis == GIAMG_BASIS_NODAL || basis == GIAMG_BASIS_MODAL, "unknown basis");
         GIAMG_REQUIRE(bc == GIAMG_BC_DIRICHLET || (bc == GIAMG_BC_PIN && pin_node >= 0 &&
                                                    pin_node < n_nodes), "bad boundary condition");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
@@ -349,31 +354,33 @@ int giamg_host_assemble(const double* coords, int64_t n_nodes, const int32_t* l2
             GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");
         std::vector<uint8_t> cons;
         if (bc == GIAMG_BC_DIRICHLET) {
-            cons = giamg::boundary_mask(l2g, n_elem, p, n_nodes);
+            cons = giamg::boundary_mask(l2g, n_elem, p, n_nodes, basis);
         } else {
             cons.assign(n_nodes, 0);
             cons[pin_node] = 1;
         }
         std::vector<double> corners;
-        giamg::element_corners(coords, l2g, n_elem, p, corners);
-        giamg::HostCSR A = giamg::assemble_fine(corners, l2g, n_elem, p, n_nodes, lambda, cons);
+        giamg::element_corners(coords, l2g, n_elem, p, corners, basis);
+        giamg::HostCSR A = giamg::assemble_fine(corners, l2g, n_elem, p, n_nodes, lambda, cons, basis);
         *A_out = new giamg_hcsr_s{std::move(A)};
         return GIAMG_OK;
     });
 }
 
 int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t q,
-                          int64_t n_fine, const uint8_t* free_mask, int32_t* l2g_next,
-                          int64_t* n_coarse, giamg_hcsr* P_out) {
+                          int64_t n_fine, const uint8_t* free_mask, int32_t basis,
+                          int32_t* l2g_next, int64_t* n_coarse, giamg_hcsr* P_out) {
     return guarded([&]() -> int {
         GIAMG_REQUIRE(l2g && free_mask && l2g_next && n_coarse && P_out, "null argument");
-        GIAMG_REQUIRE(p >= 1 && q >= 1 && q < p && p % q == 0, "q must divide p and be < p");
+        GIAMG_REQUIRE(basis == GIAMG_BASIS_NODAL || basis == GIAMG_BASIS_MODAL, "unknown basis");
+        GIAMG_REQUIRE(p >= 1 && q >= 1 && q < p && (basis == GIAMG_BASIS_MODAL || p % q == 0),
+                      "need q < p (and q dividing p for the nodal basis)");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         std::vector<int32_t> g(l2g, l2g + n_elem * nl);
         for (auto v : g) GIAMG_REQUIRE(v >= -1 && v < n_fine, "l2g entry out of range");
         std::vector<uint8_t> fm(free_mask, free_mask + n_fine);
         std::vector<int32_t> nx;
-        giamg::HostCSR P = giamg::p_transfer(g, n_elem, p, q, n_fine, fm, nx, *n_coarse);
+        giamg::HostCSR P = giamg::p_transfer(g, n_elem, p, q, n_fine, fm, nx, *n_coarse, basis);
         std::memcpy(l2g_next, nx.data(), nx.size() * sizeof(int32_t));
         *P_out = new giamg_hcsr_s{std::move(P)};
         return GIAMG_OK;

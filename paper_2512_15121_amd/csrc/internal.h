@@ -168,21 +168,23 @@ void gauss_points(int m, std::vector<double>& x, std::vector<double>& w);
 double lagrange_value(const std::vector<double>& nodes, int i, double x);
 double lagrange_derivative(const std::vector<double>& nodes, int i, double x);
 
-std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, int64_t n_nodes);
+// basis: GIAMG_BASIS_NODAL or GIAMG_BASIS_MODAL (local ordering and 1-D modes)
+std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, int64_t n_nodes,
+                                   int basis);
 void element_corners(const double* coords, const int32_t* l2g, int64_t n_elem, int p,
-                     std::vector<double>& corners);
+                     std::vector<double>& corners, int basis);
 HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
                       int p, int64_t n_nodes, double lambda,
-                      const std::vector<uint8_t>& constrained);
+                      const std::vector<uint8_t>& constrained, int basis);
 void quadrature_points(const std::vector<double>& corners, int64_t n_elem, int p, double* xq);
 void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
                  int p, int64_t n_nodes, const std::vector<uint8_t>& constrained,
-                 const double* fq, double* b);
+                 const double* fq, double* b, int basis);
 
 // p-transfer: returns P (n_fine x n_coarse) and fills the next l2g.
 HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q,
                    int64_t n_fine, const std::vector<uint8_t>& free_mask,
-                   std::vector<int32_t>& l2g_next, int64_t& n_coarse);
+                   std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis);
 // smoothed aggregation on a host copy of A: fills agg and returns P.
 HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg,
                     int64_t& n_agg);

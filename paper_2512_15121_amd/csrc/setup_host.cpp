@@ -147,17 +147,26 @@ double lagrange_derivative(const std::vector<double>& nodes, int i, double x) {
 
 static inline int lidx(int p, int i, int j, int k) { return ((p + 1) * i + j) * (p + 1) + k; }
 
+// 1-D local index of the vertex mode/node that is one at a = -1 (side 0) or
+// a = +1 (side 1): nodal GLL ends 0 and p; the modal ordering of the
+// appendix numbers the two vertex modes 0 and 1.
+static inline int vend(int p, int basis, int side) {
+    return side == 0 ? 0 : (basis == GIAMG_BASIS_MODAL ? 1 : p);
+}
+
 // ---------------------------------------------------------------------------
 // topology
 // ---------------------------------------------------------------------------
 // A face is identified by its four corner nodes; a face seen by exactly one
 // element lies on the boundary and all of its nodes are constrained.
-std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, int64_t n_nodes) {
+std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, int64_t n_nodes,
+                                   int basis) {
     const int nl = (p + 1) * (p + 1) * (p + 1);
+    const int e0 = vend(p, basis, 0), e1 = vend(p, basis, 1);
     struct Face { int32_t c[4]; int64_t elem; int8_t f; };
     std::vector<Face> faces(n_elem * 6);
-    auto face_node = [p](int f, int a, int b) {
-        int fixed = (f < 3) ? 0 : p;
+    auto face_node = [p, e0, e1](int f, int a, int b) {
+        int fixed = (f < 3) ? e0 : e1;
         switch (f % 3) {
             case 0: return lidx(p, fixed, a, b);
             case 1: return lidx(p, a, fixed, b);
@@ -169,10 +178,10 @@ std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, in
             const int32_t* g = l2g + el * nl;
             for (int f = 0; f < 6; ++f) {
                 Face F;
-                F.c[0] = g[face_node(f, 0, 0)];
-                F.c[1] = g[face_node(f, 0, p)];
-                F.c[2] = g[face_node(f, p, 0)];
-                F.c[3] = g[face_node(f, p, p)];
+                F.c[0] = g[face_node(f, e0, e0)];
+                F.c[1] = g[face_node(f, e0, e1)];
+                F.c[2] = g[face_node(f, e1, e0)];
+                F.c[3] = g[face_node(f, e1, e1)];
                 std::sort(F.c, F.c + 4);
                 F.elem = el;
                 F.f = (int8_t)f;
@@ -200,13 +209,13 @@ std::vector<uint8_t> boundary_mask(const int32_t* l2g, int64_t n_elem, int p, in
 }
 
 void element_corners(const double* coords, const int32_t* l2g, int64_t n_elem, int p,
-                     std::vector<double>& corners) {
+                     std::vector<double>& corners, int basis) {
     const int nl = (p + 1) * (p + 1) * (p + 1);
     corners.assign(n_elem * 24, 0.0);
     for (int64_t e = 0; e < n_elem; ++e)
         for (int c = 0; c < 8; ++c) {
             int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
-            int32_t g = l2g[e * nl + lidx(p, cx * p, cy * p, cz * p)];
+            int32_t g = l2g[e * nl + lidx(p, vend(p, basis, cx), vend(p, basis, cy), vend(p, basis, cz))];
             for (int a = 0; a < 3; ++a) corners[e * 24 + c * 3 + a] = coords[(int64_t)g * 3 + a];
         }
 }
@@ -222,16 +231,49 @@ struct RefTables {
     std::vector<double> L, D;           // [n1][nq] basis values / derivatives
 };
 
-RefTables make_tables(int p) {
+// Modal 1-D modes of the appendix through Legendre polynomials: for n >= 2
+// the bubble (1-a)/2 (1+a)/2 P^{1,1}_{n-2}(a) equals
+// (n-1)/(2(2n-1)) (P_{n-2}(a) - P_n(a)) and its derivative is
+// -(n-1)/2 P_{n-1}(a) (Legendre's equation); the vertex modes are (1-a)/2
+// and (1+a)/2.
+static void modal_value_derivative(int p, double x, double* v, double* d) {
+    std::vector<double> P(p + 1);
+    P[0] = 1.0;
+    if (p >= 1) P[1] = x;
+    for (int k = 1; k < p; ++k) P[k + 1] = ((2 * k + 1) * x * P[k] - k * P[k - 1]) / (k + 1);
+    v[0] = 0.5 * (1.0 - x);
+    d[0] = -0.5;
+    if (p >= 1) {
+        v[1] = 0.5 * (1.0 + x);
+        d[1] = 0.5;
+    }
+    for (int n = 2; n <= p; ++n) {
+        v[n] = (n - 1) / (2.0 * (2 * n - 1)) * (P[n - 2] - P[n]);
+        d[n] = -0.5 * (n - 1) * P[n - 1];
+    }
+}
+
+RefTables make_tables(int p, int basis) {
     RefTables t;
     t.p = p;
     t.nq = p + 2;
     t.n1 = p + 1;
-    std::vector<double> xn, wn;
-    gll_points(p, xn, wn);
     gauss_points(t.nq, t.g, t.wg);
     t.L.resize(t.n1 * t.nq);
     t.D.resize(t.n1 * t.nq);
+    if (basis == GIAMG_BASIS_MODAL) {
+        std::vector<double> v(p + 1), d(p + 1);
+        for (int q = 0; q < t.nq; ++q) {
+            modal_value_derivative(p, t.g[q], v.data(), d.data());
+            for (int i = 0; i < t.n1; ++i) {
+                t.L[i * t.nq + q] = v[i];
+                t.D[i * t.nq + q] = d[i];
+            }
+        }
+        return t;
+    }
+    std::vector<double> xn, wn;
+    gll_points(p, xn, wn);
     for (int i = 0; i < t.n1; ++i)
         for (int q = 0; q < t.nq; ++q) {
             t.L[i * t.nq + q] = lagrange_value(xn, i, t.g[q]);
@@ -374,7 +416,7 @@ bool element_matrix(const RefTables& t, const double* X, double lambda, double* 
 // ---------------------------------------------------------------------------
 HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
                       int p, int64_t n_nodes, double lambda,
-                      const std::vector<uint8_t>& cons) {
+                      const std::vector<uint8_t>& cons, int basis) {
     const int nl = (p + 1) * (p + 1) * (p + 1);
     // node -> (element, local) lists, elements ascending
     std::vector<int64_t> nstart(n_nodes + 1, 0);
@@ -421,7 +463,7 @@ HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, in
     A.val.assign(A.rp.back(), 0.0);
 
     // element matrices (all elements kept: n_elem * nl^2 doubles)
-    RefTables t = make_tables(p);
+    RefTables t = make_tables(p, basis);
     std::vector<double> Ke((size_t)n_elem * nl * nl);
     std::vector<uint8_t> bad(1, 0);
     parallel_for(n_elem, 16, [&](int64_t b, int64_t e) {
@@ -460,7 +502,7 @@ HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, in
 }
 
 void quadrature_points(const std::vector<double>& corners, int64_t n_elem, int p, double* xq) {
-    RefTables t = make_tables(p);
+    RefTables t = make_tables(p, GIAMG_BASIS_NODAL);   // only the Gauss points are used
     const int nq = t.nq, Q = nq * nq * nq;
     for (int64_t e = 0; e < n_elem; ++e) {
         const double* X = corners.data() + e * 24;
@@ -483,8 +525,8 @@ void quadrature_points(const std::vector<double>& corners, int64_t n_elem, int p
 
 void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
                  int p, int64_t n_nodes, const std::vector<uint8_t>& cons,
-                 const double* fq, double* b) {
-    RefTables t = make_tables(p);
+                 const double* fq, double* b, int basis) {
+    RefTables t = make_tables(p, basis);
     const int nq = t.nq, n1 = t.n1, Q = nq * nq * nq, nl = n1 * n1 * n1;
     std::fill(b, b + n_nodes, 0.0);
     std::vector<double> wf(Q);
@@ -516,15 +558,18 @@ void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// p-coarsening transfer (Algorithms 2-4 and 7, nodal interpolation)
+// p-coarsening transfer (Algorithms 2-4 and 7): nodal interpolation, or
+// injection for the modal basis
 // ---------------------------------------------------------------------------
 HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q,
                    int64_t n_fine, const std::vector<uint8_t>& free_mask,
-                   std::vector<int32_t>& l2g_next, int64_t& n_coarse) {
-    const int s = p / q;
+                   std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis) {
+    const bool modal = basis == GIAMG_BASIS_MODAL;
+    const int s = modal ? 1 : p / q;
     const int nl = (p + 1) * (p + 1) * (p + 1);
     const int ncl = (q + 1) * (q + 1) * (q + 1);
-    // coarse local (a,b,c) is kept at fine local (s a, s b, s c)
+    // coarse local (a,b,c) is kept at fine local (s a, s b, s c): the GLL
+    // lattice multiples (nodal), or the same low modes (modal, Algorithm 2)
     std::vector<int> extract(ncl);
     for (int a = 0; a <= q; ++a)
         for (int b = 0; b <= q; ++b)
@@ -546,16 +591,21 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
             int32_t g = l2g[e * nl + extract[a]];
             l2g_next[e * ncl + a] = is_free(g) ? rank[g] : -1;
         }
-    // 1-D interpolation: I1[i][a] = l^q_a(xi^p_i), |.| <= 1e-12 is a structural zero
-    std::vector<double> xp, wp, xq, wq;
-    gll_points(p, xp, wp);
-    gll_points(q, xq, wq);
-    std::vector<double> I1((p + 1) * (q + 1));
-    for (int i = 0; i <= p; ++i)
-        for (int a = 0; a <= q; ++a) {
-            double v = lagrange_value(xq, a, xp[i]);
-            I1[i * (q + 1) + a] = std::fabs(v) <= 1e-12 ? 0.0 : v;
-        }
+    // 1-D factor: interpolation I1[i][a] = l^q_a(xi^p_i) (|.| <= 1e-12 is a
+    // structural zero), or the injection I1[a][a] = 1 of the modal basis
+    std::vector<double> I1((p + 1) * (q + 1), 0.0);
+    if (modal) {
+        for (int a = 0; a <= q; ++a) I1[a * (q + 1) + a] = 1.0;
+    } else {
+        std::vector<double> xp, wp, xq, wq;
+        gll_points(p, xp, wp);
+        gll_points(q, xq, wq);
+        for (int i = 0; i <= p; ++i)
+            for (int a = 0; a <= q; ++a) {
+                double v = lagrange_value(xq, a, xp[i]);
+                I1[i * (q + 1) + a] = std::fabs(v) <= 1e-12 ? 0.0 : v;
+            }
+    }
     // node -> elements (ascending) for the rows of P
     std::vector<int64_t> nstart(n_fine + 1, 0);
     for (int64_t i = 0; i < n_elem * nl; ++i)

@@ -163,7 +163,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     auto t0 = clock_t_::now();
     // constrained nodes
     if (o.bc == GIAMG_BC_DIRICHLET) {
-        H.constrained = boundary_mask(l2g, ne, H.porder, n);
+        H.constrained = boundary_mask(l2g, ne, H.porder, n, o.basis);
     } else {
         H.constrained.assign(n, 0);
         H.constrained[o.pin_node] = 1;
@@ -171,9 +171,9 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     int64_t ncons = 0;
     for (auto c : H.constrained) ncons += c;
     GIAMG_REQUIRE(H.lambda > 0.0 || ncons > 0, "lambda = 0 needs at least one constrained node");
-    element_corners(coords, l2g, ne, H.porder, H.corners);
+    element_corners(coords, l2g, ne, H.porder, H.corners, o.basis);
     H.l2g.assign(l2g, l2g + ne * (int64_t)(H.porder + 1) * (H.porder + 1) * (H.porder + 1));
-    HostCSR A0 = assemble_fine(H.corners, l2g, ne, H.porder, n, H.lambda, H.constrained);
+    HostCSR A0 = assemble_fine(H.corners, l2g, ne, H.porder, n, H.lambda, H.constrained, o.basis);
     H.setup_ms[0] = ms_since(t0);
 
     H.levels.clear();
@@ -200,7 +200,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         std::vector<int32_t> l2g_next;
         int64_t nc = 0;
         Level& F = H.levels.back();
-        HostCSR P = p_transfer(F.l2g, ne, order, q, F.n, free_mask, l2g_next, nc);
+        HostCSR P = p_transfer(F.l2g, ne, order, q, F.n, free_mask, l2g_next, nc, o.basis);
         H.setup_ms[1] += ms_since(t0);
         if (nc == 0) break;
         HostCSR R = transpose(P);

@@ -20,6 +20,7 @@ BC = {"dirichlet": 0, "pin": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 LEVEL_KIND = {0: "p", 1: "h"}
 MAT = {"A": 0, "P": 1, "R": 2, "AP": 3}
+BASIS = {"nodal": 0, "modal": 1}
 OP = {"spmv": 0, "residual": 1, "restrict": 2, "prolong_add": 3, "presmooth": 4,
       "postsmooth": 5, "coarse": 6, "vcycle": 7}
 OP_FP32 = 256
@@ -39,7 +40,8 @@ class _Opts(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("agg_seed", ctypes.c_uint64),
                 ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
-                ("graph_launch", ctypes.c_int32)]
+                ("graph_launch", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -87,9 +89,11 @@ class Options:
     cheb_hi: float = 1.1
     direct_gathers: bool = False
     graph_launch: bool = False
+    basis: str = "nodal"            # or "modal"
 
     def _c(self) -> _Opts:
         d = asdict(self)
+        d["basis"] = BASIS[d["basis"]]
         d["direct_gathers"] = int(d["direct_gathers"])
         d["graph_launch"] = int(d["graph_launch"])
         d["smoother"] = SMOOTHER[d["smoother"]]
@@ -132,9 +136,9 @@ _SIGNATURES = {
     "giamg_hcsr_size": (I32, [P, P, P, P]),
     "giamg_hcsr_copy": (I32, [P, P, P, P]),
     "giamg_hcsr_free": (None, [P]),
-    "giamg_host_boundary": (I32, [P, I64, I32, I64, P]),
-    "giamg_host_assemble": (I32, [P, I64, P, I64, I32, F64, I32, I64, ctypes.POINTER(P)]),
-    "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, P, P, ctypes.POINTER(P)]),
+    "giamg_host_boundary": (I32, [P, I64, I32, I64, I32, P]),
+    "giamg_host_assemble": (I32, [P, I64, P, I64, I32, F64, I32, I64, I32, ctypes.POINTER(P)]),
+    "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, I32, P, P, ctypes.POINTER(P)]),
     "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, P, P, ctypes.POINTER(P)]),
     "giamg_time_kernel": (I32, [P, I32, I32, I32, P, P]),
     "giamg_session_create": (I32, [P, I32, F64, ctypes.POINTER(P)]),
@@ -335,30 +339,33 @@ def _take_hcsr(h):
     return rp, ci, val, (rows.value, cols.value)
 
 
-def host_boundary(l2g, p, n_nodes):
+def host_boundary(l2g, p, n_nodes, basis="nodal"):
     l2g = np.ascontiguousarray(l2g, dtype=np.int32)
     mask = np.zeros(n_nodes, dtype=np.uint8)
-    _check(library().giamg_host_boundary(_ptr(l2g), l2g.shape[0], p, n_nodes, _ptr(mask)))
+    _check(library().giamg_host_boundary(_ptr(l2g), l2g.shape[0], p, n_nodes, BASIS[basis],
+                                         _ptr(mask)))
     return mask.astype(bool)
 
 
-def host_assemble(coords, l2g, p, lam, bc="dirichlet", pin_node=0):
+def host_assemble(coords, l2g, p, lam, bc="dirichlet", pin_node=0, basis="nodal"):
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     l2g = np.ascontiguousarray(l2g, dtype=np.int32)
     h = ctypes.c_void_p()
     _check(library().giamg_host_assemble(_ptr(coords), coords.shape[0], _ptr(l2g), l2g.shape[0],
-                                         p, float(lam), BC[bc], pin_node, ctypes.byref(h)))
+                                         p, float(lam), BC[bc], pin_node, BASIS[basis],
+                                         ctypes.byref(h)))
     return _take_hcsr(h)
 
 
-def host_p_transfer(l2g, p, q, n_fine, free_mask):
+def host_p_transfer(l2g, p, q, n_fine, free_mask, basis="nodal"):
     l2g = np.ascontiguousarray(l2g, dtype=np.int32)
     fm = np.ascontiguousarray(free_mask, dtype=np.uint8)
     nxt = np.zeros((l2g.shape[0], (q + 1) ** 3), dtype=np.int32)
     nc = ctypes.c_int64()
     h = ctypes.c_void_p()
     _check(library().giamg_host_p_transfer(_ptr(l2g), l2g.shape[0], p, q, n_fine, _ptr(fm),
-                                           _ptr(nxt), ctypes.byref(nc), ctypes.byref(h)))
+                                           BASIS[basis], _ptr(nxt), ctypes.byref(nc),
+                                           ctypes.byref(h)))
     return nxt, nc.value, _take_hcsr(h)
 
 

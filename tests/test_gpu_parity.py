@@ -35,12 +35,16 @@ def torch_dev():
 
 
 CASES = {
-    # name: (n, p, lam, smoother, perturb, coarse_max, bc)
-    "manufactured_4cube_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet"),
-    "p4_6cube_cheb_sa": (6, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet"),
-    "p6_4cube_cheb": (4, 6, 0.5, "chebyshev", 0.1, 2000, "dirichlet"),
-    "p5_7cube_ragged": (7, 5, 3.0, "chebyshev", 0.1, 300, "dirichlet"),
-    "p3_pin_neumann": (5, 3, 0.0, "chebyshev", 0.1, 100, "pin"),
+    # name: (n, p, lam, smoother, perturb, coarse_max, bc, basis)
+    "manufactured_4cube_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet", "nodal"),
+    "p4_6cube_cheb_sa": (6, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet", "nodal"),
+    "p6_4cube_cheb": (4, 6, 0.5, "chebyshev", 0.1, 2000, "dirichlet", "nodal"),
+    "p5_7cube_ragged": (7, 5, 3.0, "chebyshev", 0.1, 300, "dirichlet", "nodal"),
+    "p3_pin_neumann": (5, 3, 0.0, "chebyshev", 0.1, 100, "pin", "nodal"),
+    # the appendix's modal basis: injection transfers (Algorithm 7)
+    "modal_p4_5cube_sa": (5, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet", "modal"),
+    "modal_p6_3cube": (3, 6, 1.0, "chebyshev", 0.1, 2000, "dirichlet", "modal"),
+    "modal_p3_pin_neumann": (4, 3, 0.0, "chebyshev", 0.1, 100, "pin", "modal"),
 }
 
 _cache = {}
@@ -48,20 +52,20 @@ _cache = {}
 
 def _case(name):
     if name not in _cache:
-        n, p, lam, sm, pert, cm, bc = CASES[name]
-        m = synth.hex_mesh(n, p, perturb=pert, seed=2)
+        n, p, lam, sm, pert, cm, bc, basis = CASES[name]
+        m = synth.hex_mesh(n, p, perturb=pert, seed=2, basis=basis)
         H = hierarchy.build(m.coords, m.l2g, p, lam,
-                            hierarchy.Options(smoother=sm, coarse_max=cm, bc=bc))
+                            hierarchy.Options(smoother=sm, coarse_max=cm, bc=bc, basis=basis))
         _cache[name] = (m, H)
     return _cache[name]
 
 
 def _solver(name, precision="fp64", **kw):
     from paper_2512_15121_amd import Solver, Options
-    n, p, lam, sm, pert, cm, bc = CASES[name]
+    n, p, lam, sm, pert, cm, bc, basis = CASES[name]
     m, _ = _case(name)
     return Solver(m.coords, m.l2g, p, lam,
-                  Options(smoother=sm, coarse_max=cm, bc=bc, precision=precision, **kw))
+                  Options(smoother=sm, coarse_max=cm, bc=bc, precision=precision, basis=basis, **kw))
 
 
 def _to(torch, dev, a, dtype=None):
@@ -162,7 +166,29 @@ def test_staged_gathers_mixed_bitwise_equal_direct(torch_dev):
     s2.close()
 
 
-@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "p3_pin_neumann", "manufactured_4cube_p2_jacobi"])
+@pytest.mark.parametrize("name", ["modal_p4_5cube_sa", "modal_p6_3cube", "modal_p3_pin_neumann"])
+def test_modal_galerkin_is_principal_submatrix_on_device(torch_dev, name):
+    """With injection P the device Galerkin product R (A P) sums one term per
+    entry: each coarse p-level operator is the finer one restricted to the
+    kept modes, bit for bit (and P holds ones only)."""
+    m, H = _case(name)
+    s = _solver(name)
+    for l, lv in enumerate(H.levels[:-1]):
+        if lv.collect is None:
+            break
+        rp, ci, val = s.level_csr(l, "A")
+        A = sp.csr_matrix((val, ci, rp), shape=(rp.size - 1, rp.size - 1))
+        prp, pci, pval = s.level_csr(l, "P")
+        assert np.all(pval == 1.0) and np.array_equal(pci, lv.P.indices)
+        rc, cc, vc = s.level_csr(l + 1, "A")
+        Ac = sp.csr_matrix((vc, cc, rc), shape=(rc.size - 1, rc.size - 1))
+        sub = A[lv.collect][:, lv.collect]
+        assert abs(sub - Ac).max() == 0.0, f"level {l}"
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "p3_pin_neumann", "manufactured_4cube_p2_jacobi",
+                                  "modal_p4_5cube_sa"])
 def test_each_vcycle_step(torch_dev, name):
     torch, dev = torch_dev
     m, H = _case(name)
@@ -229,8 +255,9 @@ def test_fp64_solve_parity(torch_dev, name):
     # fixed iteration count: the stopping boundary plays no part
     k = min(info.iters, ref.iters)
     from paper_2512_15121_amd import Solver, Options
-    n_, p, lam, sm, pert, cm, bc = CASES[name]
-    s2 = Solver(m.coords, m.l2g, p, lam, Options(smoother=sm, coarse_max=cm, bc=bc, maxit=k))
+    n_, p, lam, sm, pert, cm, bc, basis = CASES[name]
+    s2 = Solver(m.coords, m.l2g, p, lam, Options(smoother=sm, coarse_max=cm, bc=bc, maxit=k,
+                                                 basis=basis))
     x2, info2 = s2.solve(_to(torch, dev, b), tol=0.0)
     ref2 = krylov.giamg_pcg(H, b, tol=0.0, maxit=k)
     assert info2.iters == k == ref2.iters

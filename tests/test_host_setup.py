@@ -86,3 +86,43 @@ def test_aggregation_against_oracle(n, seed):
     assert na == roots.size and np.array_equal(agg, agg_o)
     assert np.array_equal(rp, P_o.indptr) and np.array_equal(ci, P_o.indices)
     assert np.max(np.abs(val - P_o.data)) <= 1e-15
+
+
+# ---- modal basis (appendix ordering, injection transfers) ----------------
+@pytest.mark.parametrize("n,p", [(3, 2), (2, 5)])
+def test_modal_boundary_bitexact(n, p):
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=1, basis="modal")
+    ref = assembly.boundary_nodes(m.l2g, p, m.n_nodes, "modal")
+    got = giamg.host_boundary(m.l2g, p, m.n_nodes, basis="modal")
+    assert np.array_equal(ref, got)
+
+
+@pytest.mark.parametrize("n,p,lam,bc", [(3, 2, 1.0, "dirichlet"), (2, 4, 10.0, "dirichlet"),
+                                        (2, 3, 0.0, "pin"), (2, 6, 0.5, "dirichlet")])
+def test_modal_assembly_against_oracle(n, p, lam, bc):
+    # library: Legendre closed forms of the modes; oracle: Jacobi polynomials
+    m = synth.hex_mesh(n, p, perturb=0.15, seed=3, basis="modal")
+    A, _ = assembly.assemble(m.coords, m.l2g, p, lam, bc=bc, basis="modal")
+    rp, ci, val, shape = giamg.host_assemble(m.coords, m.l2g, p, lam, bc=bc, basis="modal")
+    assert np.array_equal(rp, A.indptr) and np.array_equal(ci, A.indices)
+    assert np.max(np.abs(val - A.data)) <= 1e-13 * np.abs(A.data).max()
+    G = _csr(rp, ci, val, shape)
+    assert (G != G.T).nnz == 0
+
+
+@pytest.mark.parametrize("n,p,q", [(3, 4, 2), (2, 6, 3), (3, 3, 1), (2, 5, 2)])
+def test_modal_p_transfer_is_injection(n, p, q):
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=5, basis="modal")
+    cons = assembly.constrained_mask(m.l2g, p, m.n_nodes, "dirichlet", 0, "modal")
+    collect, l2g_nx, P = ptransfer.p_level(m.l2g, p, q, m.n_nodes, ~cons, "modal")
+    nxt, nc, (rp, ci, val, shape) = giamg.host_p_transfer(m.l2g, p, q, m.n_nodes, ~cons,
+                                                          basis="modal")
+    assert nc == collect.size and np.array_equal(nxt, l2g_nx)
+    assert np.array_equal(rp, P.indptr) and np.array_equal(ci, P.indices)
+    assert np.all(val == 1.0) and np.all(np.diff(rp) <= 1)
+
+
+def test_nodal_transfer_still_needs_divisor():
+    m = synth.hex_mesh(2, 5, basis="nodal")
+    with pytest.raises(giamg.GiamgError):
+        giamg.host_p_transfer(m.l2g, 5, 2, m.n_nodes, np.ones(m.n_nodes, dtype=bool))
