@@ -11,7 +11,7 @@ CG from x = 0 to the tolerance); the hierarchy is built once before timing
 (its setup time, including the device Galerkin products, is reported apart).
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup,
---workload {helmholtz16_p4,helmholtz32_p4}, --no-cpu-baseline, --no-mixed, --no-batched,
+--workload {helmholtz16_p4,helmholtz32_p4}, --no-cpu-baseline, --no-mixed, --no-modal, --no-batched,
 --serving {small,medium,full,off}.
 """
 import argparse
@@ -108,6 +108,30 @@ def cpu_baseline(mesh, b, lam, w, gpu_iters):
             "sample": f"{reps} complete oracle solves (FP64 PCG to 1e-10, {iters} iterations each; "
                       f"GPU took {gpu_iters}) on the same hierarchy and right-hand side, "
                       f"BLAS limited to 1 thread; oracle setup {setup_s:.1f} s not timed"}
+
+
+def modal_leg(torch, Solver, Options, w, lam, reps=3):
+    """The same workload in the appendix's modal basis (injection
+    transfers): same mesh vertices, order, lambda and right-hand side
+    distribution; FP64 GIAMG-PCG to 1e-10."""
+    import synth
+    mesh = synth.hex_mesh(w["n"], w["p"], perturb=0.1, seed=w["mesh_seed"], basis="modal")
+    b = torch.from_numpy(synth.normal_rhs(mesh.n_nodes, w["rhs_seed"])).to("cuda:0")
+    s = Solver(mesh.coords, mesh.l2g, w["p"], lam, Options(basis="modal"))
+    levels = [s.level(l) for l in range(s.num_levels())]
+    s.solve(b, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, info = s.solve(b, tol=1e-10)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    s.close()
+    out = {"solves_per_s": round(1.0 / dt, 3), "iterations": info.iters,
+           "true_relres": info.true_relres, "solve_gbs": round(info.bytes / dt / 1e9, 1),
+           "levels": [(d["kind"], d["order"], d["rows"], d["nnz_A"], d["nnz_P"]) for d in levels]}
+    log(f"modal: {out}")
+    return out
 
 
 def batched_leg(torch, Solver, Options, k=64, reps=3):
@@ -263,6 +287,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-modal", action="store_true")
     ap.add_argument("--serving", default="small", choices=["small", "medium", "full", "off"])
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy (3x) and the fine Chebyshev step (5x), "
@@ -354,6 +379,8 @@ def main():
         log(f"mixed: {args.steps / el_m:.2f} solves/s, {inf_m[-1].iters} iterations")
         sm.close()
 
+    if not args.no_modal:
+        extra["modal"] = modal_leg(torch, Solver, Options, w, lam)
     if not args.no_batched:
         extra["batched"] = batched_leg(torch, Solver, Options)
     if args.serving != "off":
