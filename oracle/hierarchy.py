@@ -57,6 +57,7 @@ class Options:
     cheb_lo: float = 0.1
     cheb_hi: float = 1.1
     basis: str = "nodal"            # or "modal" (appendix basis, injection P)
+    schedule: Optional[List[int]] = None   # coarse orders after p (default q = p / spf(p))
 
 
 @dataclass
@@ -73,7 +74,7 @@ def build(coords, l2g, p, lam, opts: Options = None) -> Hierarchy:
     H = Hierarchy(opts=opts, constrained=cons)
     free = ~cons
     cur_l2g = l2g
-    orders = ptransfer.p_schedule(p)
+    orders = ptransfer.p_schedule(p, opts.schedule)
     level = Level(A=A, kind="p", order=p, l2g=l2g)
     H.levels.append(level)
     for q in orders[1:]:

@@ -15,7 +15,12 @@ Readings where the paper is silent:
 * schedule: q = p / (smallest prime factor of p), so the coarse order
   divides the fine one (8 -> 4 -> 2 -> 1 gives Table 1's four levels);
 * the coarse local node (a, b, c) is kept at the fine local node
-  (s a, s b, s c), s = p / q, for nodal GLL bases (the lattice multiples);
+  (pos(a), pos(b), pos(c)) for nodal GLL bases, pos(a) = floor((2 a p + q) /
+  (2 q)) (the nearest lattice position; a p / q when q divides p).  The kept
+  fine node only numbers the coarse node; P interpolates from the order-q
+  GLL points whether or not they coincide with fine points;
+* explicit schedules (any decreasing orders ending at 1, e.g. 5 -> 4 -> 3
+  -> 2 -> 1 as in the paper's by-one schedule) use the same rules;
   with the modal basis the coarse local mode (a, b, c) is the fine local
   mode (a, b, c), a, b, c <= q (Algorithm 2 as printed, for any q < p);
 * constrained fine nodes have empty rows of P; coarse levels contain free
@@ -40,12 +45,23 @@ def smallest_prime_factor(p: int) -> int:
     return p
 
 
-def p_schedule(p: int):
-    """Orders visited by p-coarsening, finest first, ending at 1."""
+def p_schedule(p: int, schedule=None):
+    """Orders visited by p-coarsening, finest first, ending at 1: the given
+    coarse orders, or q = p / spf(p) repeatedly."""
+    if schedule:
+        out = [p] + [int(q) for q in schedule]
+        if any(b >= a for a, b in zip(out, out[1:])) or out[-1] < 1:
+            raise ValueError("schedule must decrease from p")
+        return out
     out = [p]
     while out[-1] > 1:
         out.append(out[-1] // smallest_prime_factor(out[-1]))
     return out
+
+
+def kept_position(p: int, q: int, a: int) -> int:
+    """Fine lattice position (0..p) that numbers coarse nodal position a."""
+    return (2 * a * p + q) // (2 * q)
 
 
 def interp_1d(p: int, q: int, basis: str = "nodal") -> np.ndarray:
@@ -66,12 +82,12 @@ def interp_1d(p: int, q: int, basis: str = "nodal") -> np.ndarray:
 def extract_next_dof(p: int, q: int, basis: str = "nodal") -> np.ndarray:
     """Fine local index of each coarse local node, in coarse local order
     (Algorithm 2: modal as printed, nodal reading for GLL nodes)."""
-    s = p // q if basis == "nodal" else 1
+    pos = [kept_position(p, q, a) if basis == "nodal" else a for a in range(q + 1)]
     out = []
     for a in range(q + 1):
         for b in range(q + 1):
             for c in range(q + 1):
-                out.append(local_index(p, s * a, s * b, s * c))
+                out.append(local_index(p, pos[a], pos[b], pos[c]))
     return np.array(out, dtype=np.int64)
 
 
