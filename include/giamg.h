@@ -85,6 +85,12 @@ typedef struct giamg_opts {
                               bit; less host work per iteration); default 0: the host launches
                               every kernel, which measured slightly faster on the device */
     int32_t  basis;        /* GIAMG_BASIS_*; default nodal */
+    int32_t  schedule[8];  /* coarse p-orders after p, decreasing, zero-terminated (e.g.
+                              {4,3,2,1} for p = 5: the by-one schedule); all zero (the
+                              default): q = p / (smallest prime factor of p) down to 1.
+                              A nodal step q < p that does not divide p numbers each
+                              coarse node by the fine node at the nearest lattice
+                              position and interpolates from the order-q GLL points */
     int32_t  reserved;     /* set to 0 */
 } giamg_opts;
 
@@ -128,9 +134,9 @@ typedef struct giamg_info {
  * Discretisation: tensor Lagrange basis on Gauss-Lobatto-Legendre points
  * (or the modal basis, opts->basis), Gauss-Legendre quadrature with p+2
  * points per direction.  Constrained
- * nodes get identity rows and columns.  Coarse orders follow
- * q = p / (smallest prime factor of p) down to 1; coarse levels hold free
- * nodes only.  Errors: GIAMG_EINVAL, GIAMG_ENOMEM, GIAMG_EHIP, GIAMG_ENOTSUP.
+ * nodes get identity rows and columns.  Coarse orders follow opts->schedule,
+ * by default q = p / (smallest prime factor of p) down to 1; coarse levels
+ * hold free nodes only.  Errors: GIAMG_EINVAL, GIAMG_ENOMEM, GIAMG_EHIP, GIAMG_ENOTSUP.
  */
 int giamg_setup(const double* coords, int64_t n_nodes,
                 const int32_t* l2g, int64_t n_elem, int32_t p,
@@ -271,8 +277,8 @@ int giamg_host_assemble(const double* coords, int64_t n_nodes, const int32_t* l2
                         int64_t n_elem, int32_t p, double lambda, int32_t bc,
                         int64_t pin_node, int32_t basis, giamg_hcsr* A_out);
 
-/* One p-coarsening step p -> q of Algorithms 2-4 and 7 (nodal: q divides p,
- * interpolation; modal: any q < p, injection):
+/* One p-coarsening step p -> q < p of Algorithms 2-4 and 7 (nodal:
+ * interpolation; modal: injection):
  * free_mask uint8 [n_fine] marks the free fine nodes, l2g may hold -1 for
  * constrained nodes; writes l2g_next int32 [n_elem][(q+1)^3] (-1 for
  * constrained coarse nodes), the coarse size, and P. */

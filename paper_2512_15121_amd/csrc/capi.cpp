@@ -84,6 +84,7 @@ void giamg_default_opts(giamg_opts* o) {
     o->direct_gathers = 0;
     o->graph_launch = 0;
     o->basis = GIAMG_BASIS_NODAL;
+    for (int i = 0; i < 8; ++i) o->schedule[i] = 0;
     o->reserved = 0;
 }
 
@@ -117,6 +118,14 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
         GIAMG_REQUIRE(o.direct_gathers == 0 || o.direct_gathers == 1, "direct_gathers must be 0 or 1");
         GIAMG_REQUIRE(o.graph_launch == 0 || o.graph_launch == 1, "graph_launch must be 0 or 1");
         GIAMG_REQUIRE(o.basis == GIAMG_BASIS_NODAL || o.basis == GIAMG_BASIS_MODAL, "unknown basis");
+        {
+            int prev = p;
+            for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
+                GIAMG_REQUIRE(o.schedule[i] >= 1 && o.schedule[i] < prev,
+                              "schedule must decrease from p and stay >= 1");
+                prev = o.schedule[i];
+            }
+        }
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         for (int64_t i = 0; i < n_elem * nl; ++i)
             GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");
@@ -373,8 +382,7 @@ int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t
     return guarded([&]() -> int {
         GIAMG_REQUIRE(l2g && free_mask && l2g_next && n_coarse && P_out, "null argument");
         GIAMG_REQUIRE(basis == GIAMG_BASIS_NODAL || basis == GIAMG_BASIS_MODAL, "unknown basis");
-        GIAMG_REQUIRE(p >= 1 && q >= 1 && q < p && (basis == GIAMG_BASIS_MODAL || p % q == 0),
-                      "need q < p (and q dividing p for the nodal basis)");
+        GIAMG_REQUIRE(p >= 1 && q >= 1 && q < p, "need 1 <= q < p");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         std::vector<int32_t> g(l2g, l2g + n_elem * nl);
         for (auto v : g) GIAMG_REQUIRE(v >= -1 && v < n_fine, "l2g entry out of range");

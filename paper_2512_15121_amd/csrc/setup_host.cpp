@@ -565,15 +565,18 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
                    int64_t n_fine, const std::vector<uint8_t>& free_mask,
                    std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis) {
     const bool modal = basis == GIAMG_BASIS_MODAL;
-    const int s = modal ? 1 : p / q;
     const int nl = (p + 1) * (p + 1) * (p + 1);
     const int ncl = (q + 1) * (q + 1) * (q + 1);
-    // coarse local (a,b,c) is kept at fine local (s a, s b, s c): the GLL
-    // lattice multiples (nodal), or the same low modes (modal, Algorithm 2)
+    // Coarse local (a,b,c) is numbered by the fine local node at the nearest
+    // lattice positions, pos(a) = floor((2 a p + q) / (2 q)) (a p / q when q
+    // divides p; the kept node only numbers the coarse node, P interpolates),
+    // or by the same low mode (modal, Algorithm 2).
+    std::vector<int> pos(q + 1);
+    for (int a = 0; a <= q; ++a) pos[a] = modal ? a : (2 * a * p + q) / (2 * q);
     std::vector<int> extract(ncl);
     for (int a = 0; a <= q; ++a)
         for (int b = 0; b <= q; ++b)
-            for (int c = 0; c <= q; ++c) extract[lidx(q, a, b, c)] = lidx(p, s * a, s * b, s * c);
+            for (int c = 0; c <= q; ++c) extract[lidx(q, a, b, c)] = lidx(p, pos[a], pos[b], pos[c]);
     auto is_free = [&](int32_t g) { return g >= 0 && free_mask[g]; };
     // collect: kept free fine nodes, sorted, unique; coarse id = rank
     std::vector<int32_t> rank(n_fine, -1);

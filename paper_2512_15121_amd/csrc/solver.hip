@@ -191,11 +191,18 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     std::vector<uint8_t> free_mask(n);
     for (int64_t i = 0; i < n; ++i) free_mask[i] = !H.constrained[i];
     int order = H.porder;
-    while (order > 1 && (int)H.levels.size() < o.max_levels) {
-        int spf = 2;
-        while (spf * spf <= order && order % spf) ++spf;
-        if (order % spf) spf = order;
-        const int q = order / spf;
+    const bool explicit_schedule = o.schedule[0] != 0;
+    for (int step = 0; order > 1 && (int)H.levels.size() < o.max_levels; ++step) {
+        int q;
+        if (explicit_schedule) {   // the listed orders only
+            if (step >= 8 || o.schedule[step] == 0) break;
+            q = o.schedule[step];
+        } else {                   // q = p / spf(p)
+            int spf = 2;
+            while (spf * spf <= order && order % spf) ++spf;
+            if (order % spf) spf = order;
+            q = order / spf;
+        }
         t0 = clock_t_::now();
         std::vector<int32_t> l2g_next;
         int64_t nc = 0;

@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
                 ("graph_launch", ctypes.c_int32), ("basis", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32 * 8), ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -90,10 +90,15 @@ class Options:
     direct_gathers: bool = False
     graph_launch: bool = False
     basis: str = "nodal"            # or "modal"
+    schedule: tuple = ()            # coarse p-orders after p, e.g. (4, 3, 2, 1); () = default
 
     def _c(self) -> _Opts:
         d = asdict(self)
         d["basis"] = BASIS[d["basis"]]
+        sched = [int(q) for q in d["schedule"]]
+        if len(sched) > 8:
+            raise ValueError("at most 8 coarse orders")
+        d["schedule"] = (ctypes.c_int32 * 8)(*(sched + [0] * (8 - len(sched))))
         d["direct_gathers"] = int(d["direct_gathers"])
         d["graph_launch"] = int(d["graph_launch"])
         d["smoother"] = SMOOTHER[d["smoother"]]

@@ -35,16 +35,19 @@ def torch_dev():
 
 
 CASES = {
-    # name: (n, p, lam, smoother, perturb, coarse_max, bc, basis)
-    "manufactured_4cube_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet", "nodal"),
-    "p4_6cube_cheb_sa": (6, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet", "nodal"),
-    "p6_4cube_cheb": (4, 6, 0.5, "chebyshev", 0.1, 2000, "dirichlet", "nodal"),
-    "p5_7cube_ragged": (7, 5, 3.0, "chebyshev", 0.1, 300, "dirichlet", "nodal"),
-    "p3_pin_neumann": (5, 3, 0.0, "chebyshev", 0.1, 100, "pin", "nodal"),
+    # name: (n, p, lam, smoother, perturb, coarse_max, bc, basis, schedule)
+    "manufactured_4cube_p2_jacobi": (4, 2, 1.0, "jacobi", 0.0, 2000, "dirichlet", "nodal", ()),
+    "p4_6cube_cheb_sa": (6, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet", "nodal", ()),
+    "p6_4cube_cheb": (4, 6, 0.5, "chebyshev", 0.1, 2000, "dirichlet", "nodal", ()),
+    "p5_7cube_ragged": (7, 5, 3.0, "chebyshev", 0.1, 300, "dirichlet", "nodal", ()),
+    "p3_pin_neumann": (5, 3, 0.0, "chebyshev", 0.1, 100, "pin", "nodal", ()),
     # the appendix's modal basis: injection transfers (Algorithm 7)
-    "modal_p4_5cube_sa": (5, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet", "modal"),
-    "modal_p6_3cube": (3, 6, 1.0, "chebyshev", 0.1, 2000, "dirichlet", "modal"),
-    "modal_p3_pin_neumann": (4, 3, 0.0, "chebyshev", 0.1, 100, "pin", "modal"),
+    "modal_p4_5cube_sa": (5, 4, 10.0, "chebyshev", 0.1, 100, "dirichlet", "modal", ()),
+    "modal_p6_3cube": (3, 6, 1.0, "chebyshev", 0.1, 2000, "dirichlet", "modal", ()),
+    "modal_p3_pin_neumann": (4, 3, 0.0, "chebyshev", 0.1, 100, "pin", "modal", ()),
+    # the by-one schedule (non-divisor nodal steps: nearest-lattice numbering)
+    "p5_5cube_by_one": (5, 5, 2.0, "chebyshev", 0.1, 100, "dirichlet", "nodal", (4, 3, 2, 1)),
+    "modal_p5_4cube_by_one": (4, 5, 2.0, "chebyshev", 0.1, 100, "dirichlet", "modal", (4, 3, 2, 1)),
 }
 
 _cache = {}
@@ -52,20 +55,22 @@ _cache = {}
 
 def _case(name):
     if name not in _cache:
-        n, p, lam, sm, pert, cm, bc, basis = CASES[name]
+        n, p, lam, sm, pert, cm, bc, basis, sched = CASES[name]
         m = synth.hex_mesh(n, p, perturb=pert, seed=2, basis=basis)
         H = hierarchy.build(m.coords, m.l2g, p, lam,
-                            hierarchy.Options(smoother=sm, coarse_max=cm, bc=bc, basis=basis))
+                            hierarchy.Options(smoother=sm, coarse_max=cm, bc=bc, basis=basis,
+                                              schedule=list(sched) or None))
         _cache[name] = (m, H)
     return _cache[name]
 
 
 def _solver(name, precision="fp64", **kw):
     from paper_2512_15121_amd import Solver, Options
-    n, p, lam, sm, pert, cm, bc, basis = CASES[name]
+    n, p, lam, sm, pert, cm, bc, basis, sched = CASES[name]
     m, _ = _case(name)
     return Solver(m.coords, m.l2g, p, lam,
-                  Options(smoother=sm, coarse_max=cm, bc=bc, precision=precision, basis=basis, **kw))
+                  Options(smoother=sm, coarse_max=cm, bc=bc, precision=precision, basis=basis,
+                          schedule=tuple(sched), **kw))
 
 
 def _to(torch, dev, a, dtype=None):
@@ -255,9 +260,9 @@ def test_fp64_solve_parity(torch_dev, name):
     # fixed iteration count: the stopping boundary plays no part
     k = min(info.iters, ref.iters)
     from paper_2512_15121_amd import Solver, Options
-    n_, p, lam, sm, pert, cm, bc, basis = CASES[name]
+    n_, p, lam, sm, pert, cm, bc, basis, sched = CASES[name]
     s2 = Solver(m.coords, m.l2g, p, lam, Options(smoother=sm, coarse_max=cm, bc=bc, maxit=k,
-                                                 basis=basis))
+                                                 basis=basis, schedule=tuple(sched)))
     x2, info2 = s2.solve(_to(torch, dev, b), tol=0.0)
     ref2 = krylov.giamg_pcg(H, b, tol=0.0, maxit=k)
     assert info2.iters == k == ref2.iters

@@ -122,7 +122,20 @@ def test_modal_p_transfer_is_injection(n, p, q):
     assert np.all(val == 1.0) and np.all(np.diff(rp) <= 1)
 
 
-def test_nodal_transfer_still_needs_divisor():
-    m = synth.hex_mesh(2, 5, basis="nodal")
+@pytest.mark.parametrize("n,p,q", [(2, 5, 4), (3, 6, 4), (2, 5, 3), (3, 4, 3)])
+def test_nodal_non_divisor_transfer_against_oracle(n, p, q):
+    # a coarse order that does not divide p: nearest-lattice numbering, and
+    # interpolation from GLL points that are not fine points
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=6)
+    cons = assembly.constrained_mask(m.l2g, p, m.n_nodes, "dirichlet", 0)
+    collect, l2g_nx, P = ptransfer.p_level(m.l2g, p, q, m.n_nodes, ~cons)
+    nxt, nc, (rp, ci, val, shape) = giamg.host_p_transfer(m.l2g, p, q, m.n_nodes, ~cons)
+    assert nc == collect.size and np.array_equal(nxt, l2g_nx)
+    assert np.array_equal(rp, P.indptr) and np.array_equal(ci, P.indices)
+    assert np.max(np.abs(val - P.data)) <= 1e-14
+
+
+def test_transfer_rejects_non_decreasing_order():
+    m = synth.hex_mesh(2, 3, basis="nodal")
     with pytest.raises(giamg.GiamgError):
-        giamg.host_p_transfer(m.l2g, 5, 2, m.n_nodes, np.ones(m.n_nodes, dtype=bool))
+        giamg.host_p_transfer(m.l2g, 3, 3, m.n_nodes, np.ones(m.n_nodes, dtype=bool))
