@@ -134,6 +134,45 @@ def modal_leg(torch, Solver, Options, w, lam, reps=3):
     return out
 
 
+def study(torch, Solver, Options, reps=3):
+    """The paper's parameter studies at p = 5 (Section 3.2, detailed
+    analysis: number of Chebyshev smoothing steps; p-coarsening by one or by
+    two) on a synthetic workload of the benchmark's size: Helmholtz lambda =
+    10 on a 13^3 perturbed hex mesh, p = 5 (287,496 dofs), N(0,1) right-hand
+    side, FP64 GIAMG-PCG to 1e-10; both bases."""
+    import synth
+    rows = []
+    for basis in ("nodal", "modal"):
+        mesh = synth.hex_mesh(13, 5, perturb=0.1, seed=7, basis=basis)
+        b = torch.from_numpy(synth.normal_rhs(mesh.n_nodes, 17)).to("cuda:0")
+        for sched in ((), (3, 1), (4, 3, 2, 1)):
+            for degree in (1, 2, 3, 4):
+                t0 = time.perf_counter()
+                s = Solver(mesh.coords, mesh.l2g, 5, 10.0,
+                           Options(basis=basis, schedule=sched, degree=degree, maxit=2000))
+                setup_s = time.perf_counter() - t0
+                s.solve(b, tol=1e-10)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    x, info = s.solve(b, tol=1e-10)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                orders = [s.level(l)["order"] for l in range(s.num_levels())
+                          if s.level(l)["kind"] == "p"]
+                s.close()
+                row = {"basis": basis, "schedule": "->".join(str(o) for o in orders),
+                       "chebyshev_degree": degree, "iterations": info.iters,
+                       "status": info.status, "solve_ms": round(dt * 1e3, 3),
+                       "ms_per_iteration": round(dt * 1e3 / max(info.iters, 1), 4),
+                       "solves_per_s": round(1.0 / dt, 3), "setup_s": round(setup_s, 3)}
+                rows.append(row)
+                log(f"study: {row}")
+    return {"workload": "Helmholtz lambda=10, 13^3 perturbed hex mesh (seed 7), p=5, "
+                        "287496 dofs, N(0,1) rhs (seed 17), FP64 GIAMG-PCG to 1e-10",
+            "rows": rows}
+
+
 def batched_leg(torch, Solver, Options, k=64, reps=3):
     """Pressure-Poisson-like batch: lambda = 0, pure Neumann with node 0
     pinned, 20^3 perturbed mesh (seed 4), p = 3, 64 right-hand sides N(0,1)
@@ -288,6 +327,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-modal", action="store_true")
+    ap.add_argument("--study", action="store_true",
+                    help="only run the parameter studies at p = 5 (Chebyshev degree x "
+                         "p-schedule x basis) and print them as one JSON line")
     ap.add_argument("--serving", default="small", choices=["small", "medium", "full", "off"])
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy (3x) and the fine Chebyshev step (5x), "
@@ -303,6 +345,9 @@ def main():
     from paper_2512_15121_amd import Solver, Options
 
     dev = torch.device("cuda:0")
+    if args.study:
+        print(json.dumps({"study": study(torch, Solver, Options)}), flush=True)
+        return
     mesh, b, lam, w = problem(args.workload)
     if args.pmc_probe:
         src = torch.zeros(1 << 27, dtype=torch.float64, device=dev)
