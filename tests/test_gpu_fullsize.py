@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import synth
+from _rows import oracle_rows
 from oracle import assembly, ptransfer, sa
 
 pytestmark = pytest.mark.gpu
@@ -34,22 +35,7 @@ def full():
 
 
 def _oracle_rows(coords, l2g, p, lam, cons, rows, nq):
-    """Rows of the assembled operator (free rows) from the elements around
-    each node, with the constrained columns removed."""
-    out = {}
-    for r in rows:
-        els = np.nonzero((l2g == r).any(axis=1))[0]
-        sub = l2g[els]
-        acc = {}
-        for eids, Ae in assembly.element_matrices(coords, sub, p, nq, lam):
-            for e_local, A in zip(eids, Ae):
-                g = sub[e_local]
-                a = int(np.nonzero(g == r)[0][0])
-                for b, c in enumerate(g):
-                    if not cons[c]:
-                        acc[int(c)] = acc.get(int(c), 0.0) + A[a, b]
-        out[r] = acc
-    return out
+    return oracle_rows(coords, l2g, p, lam, cons, rows, nq)
 
 
 def test_fine_rows_and_product(full):
