@@ -57,6 +57,10 @@ extern "C" {
 #define GIAMG_BC_PIN             1  /* only pin_node is constrained (pure Neumann + pin) */
 #define GIAMG_PREC_FP64          0  /* everything in double precision, standard PCG */
 #define GIAMG_PREC_MIXED         1  /* FP32 V-cycle (coarsest in FP64) inside FP64 flexible CG */
+#define GIAMG_BATCH_AUTO  0   /* batch_kernel: fastest shape, timed per operator */
+#define GIAMG_BATCH_LANES 1   /* 8 to 64 lanes per row, each lane loads its own (column, value) */
+#define GIAMG_BATCH_WAVE  2   /* one row per wavefront, (column, value) pairs shared by readlane */
+#define GIAMG_BATCH_GROUP 3   /* one group of rows with identical column lists per wavefront */
 #define GIAMG_BASIS_NODAL        0  /* tensor Lagrange on Gauss-Lobatto-Legendre points */
 #define GIAMG_BASIS_MODAL        1  /* hierarchical modal basis of the paper's appendix:
                                        1-D modes (1-a)/2, (1+a)/2, then bubbles
@@ -91,7 +95,11 @@ typedef struct giamg_opts {
                               A nodal step q < p that does not divide p numbers each
                               coarse node by the fine node at the nearest lattice
                               position and interpolates from the order-q GLL points */
-    int32_t  reserved;     /* set to 0 */
+    int32_t  batch_kernel; /* GIAMG_BATCH_*: kernel shape of the block products in
+                              giamg_solve_batch.  AUTO (the default) times every shape on
+                              an operator's first batched product and keeps the fastest;
+                              LANES, WAVE and GROUP force one.  All give the same results,
+                              bit for bit */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */

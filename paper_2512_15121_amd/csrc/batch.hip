@@ -48,7 +48,37 @@ struct SpmmArgs {
     T c1 = 0, c2 = 0, inv_theta = 0, omega = 0;
     int flags = 0;
     const int* run = nullptr;  // skip all work when *run == 0
+    const int32_t* gptr = nullptr;   // row groups (spmm_group_kernel only)
+    const int32_t* grows = nullptr;
+    int64_t ngroups = 0;
 };
+
+// Row-local tail of a block product: acc = (A v)[row][col].
+template <typename T, int MODE>
+__device__ __forceinline__ void spmm_epilogue(const SpmmArgs<T>& a, int64_t row, int64_t col, T acc) {
+    const int64_t idx = row * a.k + col;
+    if constexpr (MODE == SPMV_PLAIN) {
+        a.y[idx] = acc;
+    } else if constexpr (MODE == SPMV_RESID) {
+        a.y[idx] = a.f[idx] - acc;
+    } else if constexpr (MODE == SPMV_ADD) {
+        a.y[idx] += acc;
+    } else if constexpr (MODE == SPMV_CHEB_INIT) {
+        const T res = a.dinv[row] * (a.f[idx] - acc);
+        a.r[idx] = res;
+        a.y[idx] = res * a.inv_theta;
+    } else if constexpr (MODE == SPMV_CHEB_STEP) {
+        const T rr = a.r[idx] - a.dinv[row] * acc;
+        const T dold = a.v[idx];
+        const T dn = a.c1 * dold + a.c2 * rr;
+        a.r[idx] = rr;
+        a.y[idx] = dn;
+        const T inc = (a.flags & CHEB_LAST) ? dold + dn : dold;
+        a.x[idx] = ((a.flags & CHEB_ASSIGN) ? T(0) : a.x[idx]) + inc;
+    } else if constexpr (MODE == SPMV_JACOBI) {
+        a.y[idx] = a.v[idx] + a.omega * a.dinv[row] * (a.f[idx] - acc);
+    }
+}
 
 // One wavefront covers RPW = 64 / KT rows; KT lanes per row take KT columns.
 template <typename T, int MODE, int KT, int WPB>
@@ -75,36 +105,171 @@ __global__ void __launch_bounds__(WPB* BW) spmm_kernel(SpmmArgs<T> a) {
         acc += a3 * x3;
     }
     for (; j < e; ++j) acc += a.val[j] * a.v[a.ci[j] * k + col];
-    const int64_t idx = row * k + col;
-    if constexpr (MODE == SPMV_PLAIN) {
-        a.y[idx] = acc;
-    } else if constexpr (MODE == SPMV_RESID) {
-        a.y[idx] = a.f[idx] - acc;
-    } else if constexpr (MODE == SPMV_ADD) {
-        a.y[idx] += acc;
-    } else if constexpr (MODE == SPMV_CHEB_INIT) {
-        const T res = a.dinv[row] * (a.f[idx] - acc);
-        a.r[idx] = res;
-        a.y[idx] = res * a.inv_theta;
-    } else if constexpr (MODE == SPMV_CHEB_STEP) {
-        const T rr = a.r[idx] - a.dinv[row] * acc;
-        const T dold = a.v[idx];
-        const T dn = a.c1 * dold + a.c2 * rr;
-        a.r[idx] = rr;
-        a.y[idx] = dn;
-        const T inc = (a.flags & CHEB_LAST) ? dold + dn : dold;
-        a.x[idx] = ((a.flags & CHEB_ASSIGN) ? T(0) : a.x[idx]) + inc;
-    } else if constexpr (MODE == SPMV_JACOBI) {
-        a.y[idx] = a.v[idx] + a.omega * a.dinv[row] * (a.f[idx] - acc);
+    spmm_epilogue<T, MODE>(a, row, col, acc);
+}
+
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One wavefront per row, 64 columns per wave (blockIdx.y selects the column
+// tile).  The lanes fetch 64 consecutive (column, value) pairs of the row in
+// one coalesced access each and hand them to the whole wave by readlane, so
+// each gather of a block-vector row v[c][tile] is one load with a
+// wave-uniform base instead of three per-lane loads.  The row sum runs over
+// the nonzeros in CSR order, as in spmm_kernel, so both give the same bits.
+// Lanes past k read column k-1 (in bounds) and store nothing.
+template <typename T, int MODE, int WPB>
+__global__ void __launch_bounds__(WPB* BW) spmm_wave_kernel(SpmmArgs<T> a) {
+    if (a.run && *a.run == 0) return;
+    constexpr int U = 8;   // gathers in flight per wave
+    const int lane = threadIdx.x % BW;
+    const int64_t row = (int64_t)blockIdx.x * WPB + threadIdx.x / BW;
+    if (row >= a.n) return;
+    const int64_t k = a.k;
+    const int64_t col = (int64_t)blockIdx.y * BW + lane;
+    const int64_t lc = col < k ? col : k - 1;
+    const int64_t s = a.rp[row], e = a.rp[row + 1];
+    T acc = 0;
+    for (int64_t b = s; b < e; b += BW) {
+        const int m = (int)min((int64_t)BW, e - b);
+        const int li = lane < m ? lane : m - 1;
+        const int32_t cw = a.ci[b + li];
+        const T aw = a.val[b + li];
+        int t = 0;
+        for (; t + U <= m; t += U) {
+            T xs[U], as[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t c = __builtin_amdgcn_readlane(cw, t + u);
+                as[u] = lane_value(aw, t + u);
+                xs[u] = a.v[c * k + lc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += as[u] * xs[u];
+        }
+        for (; t < m; ++t) {
+            const int64_t c = __builtin_amdgcn_readlane(cw, t);
+            acc += lane_value(aw, t) * a.v[c * k + lc];
+        }
+    }
+    if (col < k) spmm_epilogue<T, MODE>(a, row, col, acc);
+}
+
+// The G rows of one group share their column list; the wave reads each
+// block-vector row v[c][tile] once and applies it to all G rows.  Row i of
+// the group sums over its nonzeros in CSR order, as in spmm_kernel.
+template <typename T, int MODE, int G>
+__device__ __forceinline__ void group_rows(const SpmmArgs<T>& a, int32_t row_lane, int64_t start_lane,
+                                           int lane, int64_t col, int64_t lc) {
+    constexpr int U = G >= 4 ? 4 : 8;   // gathers in flight per wave
+    const int64_t k = a.k;
+    int64_t r[G], st[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        r[i] = __builtin_amdgcn_readlane(row_lane, i);
+        const int lo = __builtin_amdgcn_readlane((int)start_lane, i);
+        const int hi = __builtin_amdgcn_readlane((int)(start_lane >> 32), i);
+        st[i] = ((int64_t)hi << 32) | (uint32_t)lo;
+    }
+    const int64_t m = a.rp[r[0] + 1] - st[0];
+    T acc[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) acc[i] = 0;
+    for (int64_t b = 0; b < m; b += BW) {
+        const int mb = (int)min((int64_t)BW, m - b);
+        const int li = lane < mb ? lane : mb - 1;
+        const int32_t cw = a.ci[st[0] + b + li];
+        T vw[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) vw[i] = a.val[st[i] + b + li];
+        int t = 0;
+        for (; t + U <= mb; t += U) {
+            T xs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t c = __builtin_amdgcn_readlane(cw, t + u);
+                xs[u] = a.v[c * k + lc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < G; ++i) acc[i] += lane_value(vw[i], t + u) * xs[u];
+        }
+        for (; t < mb; ++t) {
+            const int64_t c = __builtin_amdgcn_readlane(cw, t);
+            const T x = a.v[c * k + lc];
+#pragma unroll
+            for (int i = 0; i < G; ++i) acc[i] += lane_value(vw[i], t) * x;
+        }
+    }
+    if (col < k) {
+#pragma unroll
+        for (int i = 0; i < G; ++i) spmm_epilogue<T, MODE>(a, r[i], col, acc[i]);
+    }
+}
+
+// One wavefront per group of rows with identical column lists (at most
+// GROUP_MAX rows; a.gptr / a.grows list them), 64 columns per wave.
+template <typename T, int MODE, int WPB>
+__global__ void __launch_bounds__(WPB* BW) spmm_group_kernel(SpmmArgs<T> a) {
+    if (a.run && *a.run == 0) return;
+    const int lane = threadIdx.x % BW;
+    const int64_t w = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x / BW);
+    if (w >= a.ngroups) return;
+    const int32_t g0 = __builtin_amdgcn_readfirstlane(a.gptr[w]);
+    const int g = __builtin_amdgcn_readfirstlane(a.gptr[w + 1]) - g0;
+    const int32_t row_lane = a.grows[g0 + (lane < g ? lane : g - 1)];
+    const int64_t start_lane = a.rp[row_lane];
+    const int64_t col = (int64_t)blockIdx.y * BW + lane;
+    const int64_t lc = col < a.k ? col : a.k - 1;
+    switch (g) {
+        case 1: group_rows<T, MODE, 1>(a, row_lane, start_lane, lane, col, lc); break;
+        case 2: group_rows<T, MODE, 2>(a, row_lane, start_lane, lane, col, lc); break;
+        case 3: group_rows<T, MODE, 3>(a, row_lane, start_lane, lane, col, lc); break;
+        case 4: group_rows<T, MODE, 4>(a, row_lane, start_lane, lane, col, lc); break;
+        case 5: group_rows<T, MODE, 5>(a, row_lane, start_lane, lane, col, lc); break;
+        case 6: group_rows<T, MODE, 6>(a, row_lane, start_lane, lane, col, lc); break;
+        case 7: group_rows<T, MODE, 7>(a, row_lane, start_lane, lane, col, lc); break;
+        default: group_rows<T, MODE, 8>(a, row_lane, start_lane, lane, col, lc); break;
     }
 }
 
 // Tile shapes the tuner chooses from.
-struct Tile { int kt, wpb; };
-const Tile kTiles[] = {{64, 4}, {64, 8}, {64, 2}, {32, 4}, {32, 8}, {16, 4}, {16, 8}, {8, 8}};
+// kind: 0 spmm_kernel (kt lanes per row), 1 spmm_wave_kernel (one row per
+// wavefront), 2 spmm_group_kernel (one row group per wavefront); kinds 1 and
+// 2 take 64 columns per wave.
+enum TileKind { TILE_LANES = 0, TILE_WAVE = 1, TILE_GROUP = 2 };
+struct Tile { int kt, wpb, kind; };
+const Tile kTiles[] = {{64, 8, TILE_GROUP}, {64, 4, TILE_GROUP}, {64, 8, TILE_WAVE}, {64, 4, TILE_WAVE},
+                       {64, 4, TILE_LANES}, {64, 8, TILE_LANES}, {64, 2, TILE_LANES}, {32, 4, TILE_LANES},
+                       {32, 8, TILE_LANES}, {16, 4, TILE_LANES}, {16, 8, TILE_LANES}, {8, 8, TILE_LANES}};
+constexpr int GROUP_MAX = 8;
 
 template <typename T, int MODE>
 void launch_spmm_tile(const SpmmArgs<T>& a, Tile t, hipStream_t s) {
+    if (t.kind == TILE_WAVE || t.kind == TILE_GROUP) {
+        const int64_t units = t.kind == TILE_WAVE ? a.n : a.ngroups;
+        if (t.kind == TILE_GROUP && (a.gptr == nullptr || a.grows == nullptr))
+            throw Error(GIAMG_EINVAL, "row groups missing");
+        if (units <= 0) return;
+        const dim3 grid((unsigned)((units + t.wpb - 1) / t.wpb), (unsigned)((a.k + BW - 1) / BW));
+#define GIAMG_WTILE(KIND, WPB, KERNEL)                                              \
+        if (t.kind == KIND && t.wpb == WPB) {                                       \
+            KERNEL<T, MODE, WPB><<<grid, dim3(WPB * BW), 0, s>>>(a);                \
+            return;                                                                 \
+        }
+        GIAMG_WTILE(TILE_WAVE, 8, spmm_wave_kernel) GIAMG_WTILE(TILE_WAVE, 4, spmm_wave_kernel)
+        GIAMG_WTILE(TILE_GROUP, 8, spmm_group_kernel) GIAMG_WTILE(TILE_GROUP, 4, spmm_group_kernel)
+#undef GIAMG_WTILE
+        throw Error(GIAMG_EINVAL, "unknown tile");
+    }
     const int rpw = BW / t.kt;
     const int64_t rows_per_block = (int64_t)rpw * t.wpb;
     const dim3 grid((unsigned)((a.n + rows_per_block - 1) / rows_per_block),
@@ -415,6 +580,14 @@ struct BatchLevel {
     DevBuf<float> f32, x32, r32, d032, d132, t32;
 };
 
+// Rows of one operator with identical column lists, split into groups of at
+// most GROUP_MAX rows (near-equal sizes): rows[ptr[g] .. ptr[g+1]) are group
+// g, groups in order of their first row.
+struct RowGroups {
+    DevBuf<int32_t> ptr, rows;
+    int64_t count = 0;
+};
+
 struct BatchState {
     int k = 0;
     bool mixed = false;
@@ -424,6 +597,7 @@ struct BatchState {
     DevBuf<ColState> st;
     DevBuf<int> run;
     std::map<std::string, Tile> tiles;   // tuned tile per operator and precision
+    std::map<std::string, RowGroups> groups;   // per operator (pattern only)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const double* graph_b = nullptr;
@@ -499,6 +673,88 @@ double spmm_bytes(const DevCSR& M, int k, double vb, double rowvecs) {
            rowvecs * vb * (double)M.nrows * k;
 }
 
+// Group the rows of M by identical column lists (host pass over the pattern:
+// a hash per row, exact comparison within equal hashes).
+RowGroups build_row_groups(const DevCSR& M, hipStream_t s) {
+    RowGroups G;
+    const int64_t n = M.nrows;
+    if (n <= 0) return G;
+    std::vector<int64_t> rp((size_t)n + 1);
+    std::vector<int32_t> ci((size_t)M.nnz);
+    GIAMG_HIP(hipMemcpyAsync(rp.data(), M.rp.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (M.nnz > 0)
+        GIAMG_HIP(hipMemcpyAsync(ci.data(), M.ci.get(), ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    std::vector<uint64_t> h((size_t)n);
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t x = 0x9e3779b97f4a7c15ull * (uint64_t)(rp[r + 1] - rp[r] + 1);
+        for (int64_t j = rp[r]; j < rp[r + 1]; ++j) {
+            x ^= (uint64_t)(uint32_t)ci[j] + 0x9e3779b97f4a7c15ull + (x << 6) + (x >> 2);
+            x *= 0xbf58476d1ce4e5b9ull;
+        }
+        h[r] = x;
+    }
+    std::vector<int32_t> order((size_t)n);
+    for (int64_t r = 0; r < n; ++r) order[r] = (int32_t)r;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return h[a] != h[b] ? h[a] < h[b] : a < b;
+    });
+    auto same = [&](int32_t a, int32_t b) {
+        const int64_t la = rp[a + 1] - rp[a];
+        return la == rp[b + 1] - rp[b] && std::equal(ci.data() + rp[a], ci.data() + rp[a] + la, ci.data() + rp[b]);
+    };
+    std::vector<std::vector<int32_t>> groups;
+    for (size_t i = 0; i < order.size();) {
+        size_t j = i;
+        while (j < order.size() && h[order[j]] == h[order[i]]) ++j;
+        // classes of exactly equal lists among rows [i, j) (in row order)
+        std::vector<std::vector<int32_t>> cls;
+        for (size_t q = i; q < j; ++q) {
+            const int32_t r = order[q];
+            bool put = false;
+            for (auto& c : cls)
+                if (same(c.front(), r)) { c.push_back(r); put = true; break; }
+            if (!put) cls.push_back({r});
+        }
+        for (auto& c : cls) {   // ceil(size / GROUP_MAX) groups of near-equal size
+            const size_t parts = (c.size() + GROUP_MAX - 1) / GROUP_MAX;
+            for (size_t q = 0; q < parts; ++q)
+                groups.emplace_back(c.begin() + c.size() * q / parts, c.begin() + c.size() * (q + 1) / parts);
+        }
+        i = j;
+    }
+    std::sort(groups.begin(), groups.end(),
+              [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) { return a.front() < b.front(); });
+    std::vector<int32_t> ptr{0}, rows;
+    rows.reserve((size_t)n);
+    for (auto& g : groups) {
+        rows.insert(rows.end(), g.begin(), g.end());
+        ptr.push_back((int32_t)rows.size());
+    }
+    G.count = (int64_t)groups.size();
+    G.ptr = DevBuf<int32_t>(ptr.size());
+    G.rows = DevBuf<int32_t>(rows.size());
+    GIAMG_HIP(hipMemcpyAsync(G.ptr.get(), ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GIAMG_HIP(hipMemcpyAsync(G.rows.get(), rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    return G;
+}
+
+const RowGroups& row_groups(BatchCtx& c, const DevCSR& M, const std::string& key) {
+    auto it = c.B.groups.find(key);
+    if (it == c.B.groups.end()) it = c.B.groups.emplace(key, build_row_groups(M, c.s())).first;
+    return it->second;
+}
+
+template <typename T>
+void with_groups(BatchCtx& c, const DevCSR& M, const std::string& key, Tile t, SpmmArgs<T>& a) {
+    if (t.kind != TILE_GROUP) return;
+    const RowGroups& G = row_groups(c, M, key);
+    a.gptr = G.ptr.get();
+    a.grows = G.rows.get();
+    a.ngroups = G.count;
+}
+
 // tile lookup (tuned on first use, outside any capture)
 template <typename T>
 Tile tile_for(BatchCtx& c, const DevCSR& M, const std::string& key);
@@ -508,6 +764,7 @@ void spmm(BatchCtx& c, int mode, const DevCSR& M, SpmmArgs<T> a, const std::stri
           double rowvecs) {
     const Tile t = tile_for<T>(c, M, key);
     if (c.count_bytes) c.H.bytes += spmm_bytes(M, c.k, sizeof(T), rowvecs);
+    with_groups<T>(c, M, key, t, a);
     launch_spmm_any<T>(mode, a, t, c.s());
 }
 
@@ -529,8 +786,11 @@ Tile tile_for(BatchCtx& c, const DevCSR& M, const std::string& key) {
     hipEvent_t e0, e1;
     GIAMG_HIP(hipEventCreate(&e0));
     GIAMG_HIP(hipEventCreate(&e1));
+    // GIAMG_BATCH_LANES / WAVE / GROUP force TILE_LANES / WAVE / GROUP
+    const int want = c.H.opts.batch_kernel - GIAMG_BATCH_LANES;
     for (const Tile& t : kTiles) {
-        if (t.kt > 2 * c.k && t.kt > 8) continue;   // mostly idle lanes
+        if (want >= 0 ? t.kind != want : (t.kt > 2 * c.k && t.kt > 8)) continue;   // forced / idle lanes
+        with_groups<T>(c, M, key, t, a);
         launch_spmm_any<T>(SPMV_PLAIN, a, t, c.s());
         GIAMG_HIP(hipEventRecord(e0, c.s()));
         for (int i = 0; i < 3; ++i) launch_spmm_any<T>(SPMV_PLAIN, a, t, c.s());

@@ -85,7 +85,7 @@ void giamg_default_opts(giamg_opts* o) {
     o->graph_launch = 0;
     o->basis = GIAMG_BASIS_NODAL;
     for (int i = 0; i < 8; ++i) o->schedule[i] = 0;
-    o->reserved = 0;
+    o->batch_kernel = GIAMG_BATCH_AUTO;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -118,6 +118,8 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
         GIAMG_REQUIRE(o.direct_gathers == 0 || o.direct_gathers == 1, "direct_gathers must be 0 or 1");
         GIAMG_REQUIRE(o.graph_launch == 0 || o.graph_launch == 1, "graph_launch must be 0 or 1");
         GIAMG_REQUIRE(o.basis == GIAMG_BASIS_NODAL || o.basis == GIAMG_BASIS_MODAL, "unknown basis");
+        GIAMG_REQUIRE(o.batch_kernel >= GIAMG_BATCH_AUTO && o.batch_kernel <= GIAMG_BATCH_GROUP,
+                      "unknown batch_kernel");
         {
             int prev = p;
             for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {

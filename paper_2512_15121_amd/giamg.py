@@ -21,6 +21,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 LEVEL_KIND = {0: "p", 1: "h"}
 MAT = {"A": 0, "P": 1, "R": 2, "AP": 3}
 BASIS = {"nodal": 0, "modal": 1}
+BATCH_KERNEL = {"auto": 0, "lanes": 1, "wave": 2, "group": 3}
 OP = {"spmv": 0, "residual": 1, "restrict": 2, "prolong_add": 3, "presmooth": 4,
       "postsmooth": 5, "coarse": 6, "vcycle": 7}
 OP_FP32 = 256
@@ -41,7 +42,7 @@ class _Opts(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
                 ("graph_launch", ctypes.c_int32), ("basis", ctypes.c_int32),
-                ("schedule", ctypes.c_int32 * 8), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -91,10 +92,12 @@ class Options:
     graph_launch: bool = False
     basis: str = "nodal"            # or "modal"
     schedule: tuple = ()            # coarse p-orders after p, e.g. (4, 3, 2, 1); () = default
+    batch_kernel: str = "auto"      # block-product shape of solve_batch: auto, lanes, wave, group
 
     def _c(self) -> _Opts:
         d = asdict(self)
         d["basis"] = BASIS[d["basis"]]
+        d["batch_kernel"] = BATCH_KERNEL[d["batch_kernel"]]
         sched = [int(q) for q in d["schedule"]]
         if len(sched) > 8:
             raise ValueError("at most 8 coarse orders")

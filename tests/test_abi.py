@@ -87,3 +87,33 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, f"{cname}.{field}"
+
+
+def test_option_constants_match_header():
+    from paper_2512_15121_amd import giamg
+    text = open(os.path.join(ROOT, "include", "giamg.h")).read()
+    defs = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"#define\s+(GIAMG_\w+)\s+\(?(-?\d+)\)?", text)}
+    tables = {"GIAMG_BATCH_": giamg.BATCH_KERNEL, "GIAMG_BASIS_": giamg.BASIS,
+              "GIAMG_BC_": giamg.BC, "GIAMG_PREC_": giamg.PRECISION,
+              "GIAMG_SMOOTHER_": giamg.SMOOTHER}
+    for prefix, table in tables.items():
+        for name, value in table.items():
+            assert defs[prefix + name.upper()] == value, prefix + name
+
+
+def test_unknown_batch_kernel_is_rejected_before_device_work():
+    from paper_2512_15121_amd import giamg
+    import numpy as np
+    lib = giamg.library()
+    o = giamg._Opts()
+    lib.giamg_default_opts(ctypes.byref(o))
+    assert o.batch_kernel == giamg.BATCH_KERNEL["auto"]
+    o.batch_kernel = 7
+    coords = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], dtype=np.float64)
+    l2g = np.arange(8, dtype=np.int32)[None, :]
+    h = ctypes.c_void_p()
+    rc = lib.giamg_setup(giamg._ptr(coords), 8, giamg._ptr(l2g), 1, 1, 1.0, ctypes.byref(o), None,
+                         ctypes.byref(h))
+    assert rc == giamg.EINVAL and b"batch_kernel" in lib.giamg_last_error()
+    assert not h.value

@@ -77,3 +77,41 @@ def test_batch_iteration_cap(env):
     X, infos = s.solve_batch(torch.from_numpy(B).to(dev), tol=1e-10)
     assert all(i.status == giamg.ENOTCONV and i.iters == 2 for i in infos)
     s.close()
+
+
+def _shape_solutions(torch, dev, m, p, lam, bc, precision, B):
+    from paper_2512_15121_amd import Solver, Options
+    out = {}
+    for kind in ("lanes", "wave", "group"):
+        s = Solver(m.coords, m.l2g, p, lam, Options(bc=bc, coarse_max=100, precision=precision,
+                                                    batch_kernel=kind))
+        X, infos = s.solve_batch(torch.from_numpy(B).to(dev), tol=1e-10)
+        out[kind] = (X, [(i.iters, i.status) for i in infos])
+        s.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["p3_pin", "p4_dirichlet"])
+def test_batch_kernel_shapes_give_the_same_bits(env, precision, case):
+    """Every block-product shape (lanes per row, a row per wavefront, a group
+    of rows with one column list per wavefront) sums each row in CSR order, so
+    the whole batched solve is bitwise the same.  k = 70: two 64-column tiles,
+    the second ragged.  p = 3 groups rows by 8, 4, 2 and 1; p = 4 (27, 9 and 3
+    rows per pattern, Dirichlet rows single) by 7, 6, 5, 4, 3 and 1."""
+    torch, dev, m, H = env
+    k = 70
+    if case == "p3_pin":
+        p, lam, bc = 3, 0.0, "pin"
+        B = synth.pinned_normal_batch(m.n_nodes, k, 33)
+    else:
+        p, lam, bc = 4, 2.0, "dirichlet"
+        m = synth.hex_mesh(3, 4, perturb=0.1, seed=6)
+        B = np.ascontiguousarray(synth.normal_rhs(m.n_nodes * k, 34).reshape(m.n_nodes, k))
+    out = _shape_solutions(torch, dev, m, p, lam, bc, precision, B)
+    X0, it0 = out["lanes"]
+    assert all(st == 0 for _, st in it0)
+    for kind in ("wave", "group"):
+        X, it = out[kind]
+        assert it == it0, kind
+        assert torch.equal(X, X0), kind
