@@ -100,6 +100,17 @@ typedef struct giamg_opts {
                               an operator's first batched product and keeps the fastest;
                               LANES, WAVE and GROUP force one.  All give the same results,
                               bit for bit */
+    int32_t  row_groups;   /* 1: an operator whose rows share column lists in groups (in
+                              a high-order mesh the interior, face and edge nodes of an
+                              element, face or edge) is multiplied in the grouped form:
+                              one list of 16-bit LDS slots per group of up to 8 rows,
+                              values reordered into per-block planes, the row sums in the
+                              order of the CSR form (same rows, bit for bit; the block
+                              partial sums of CG dot products add the rows in another
+                              order).  Built where it removes at least a fifth of the
+                              slots; needs direct_gathers = 0.  Default 0 (CSR form
+                              only): the grouped form moves fewer bytes but measured
+                              slower on gfx950 */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -200,8 +211,11 @@ typedef struct giamg_level_desc {
     int64_t nnz_A, nnz_P, nnz_R;   /* P/R are 0 on the coarsest level */
     double  lam_hat;     /* lambda_max(D^-1 A) estimate (0 on the coarsest level) */
     int64_t nnz_AP;      /* 0 on the coarsest level */
-    int64_t staged_nnz_A;  /* nonzeros of A in row blocks with staged gathers (0: all direct) */
+    int64_t staged_nnz_A;  /* nonzeros of A in row blocks with staged gathers (0: all direct,
+                              or A runs in the grouped form) */
     int64_t runs_A;        /* column runs those blocks stage */
+    int64_t groups_A;      /* grouped form of A (see row_groups): row groups, 0 if not built */
+    int64_t group_entries_A; /* 16-bit slots of that form (sum of the groups' row lengths) */
 } giamg_level_desc;
 
 int giamg_num_levels(giamg_handle h);
@@ -260,7 +274,8 @@ int giamg_load_vector(giamg_handle h, const double* fq, double* b);
 
 /* Setup timings in milliseconds: [0] host assembly, [1] p-transfers,
  * [2] aggregation, [3] device Galerkin products, [4] coarsest factor,
- * [5] smoother parameters, [6] total.  host out double[7]. */
+ * [5] grouped product forms and smoother parameters, [6] total.
+ * host out double[7]. */
 int giamg_setup_times(giamg_handle h, double* ms);
 
 

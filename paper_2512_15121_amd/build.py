@@ -15,8 +15,8 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["setup_host.cpp", "kernels.hip", "spgemm.hip", "solver.hip", "batch.hip", "serve.cpp",
-           "capi.cpp"]
+SOURCES = ["setup_host.cpp", "kernels.hip", "groups.cpp", "spgemm.hip", "solver.hip", "batch.hip",
+           "serve.cpp", "capi.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -673,8 +673,7 @@ double spmm_bytes(const DevCSR& M, int k, double vb, double rowvecs) {
            rowvecs * vb * (double)M.nrows * k;
 }
 
-// Group the rows of M by identical column lists (host pass over the pattern:
-// a hash per row, exact comparison within equal hashes).
+// Group the rows of M by identical column lists (host pass over the pattern).
 RowGroups build_row_groups(const DevCSR& M, hipStream_t s) {
     RowGroups G;
     const int64_t n = M.nrows;
@@ -685,43 +684,11 @@ RowGroups build_row_groups(const DevCSR& M, hipStream_t s) {
     if (M.nnz > 0)
         GIAMG_HIP(hipMemcpyAsync(ci.data(), M.ci.get(), ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GIAMG_HIP(hipStreamSynchronize(s));
-    std::vector<uint64_t> h((size_t)n);
-    for (int64_t r = 0; r < n; ++r) {
-        uint64_t x = 0x9e3779b97f4a7c15ull * (uint64_t)(rp[r + 1] - rp[r] + 1);
-        for (int64_t j = rp[r]; j < rp[r + 1]; ++j) {
-            x ^= (uint64_t)(uint32_t)ci[j] + 0x9e3779b97f4a7c15ull + (x << 6) + (x >> 2);
-            x *= 0xbf58476d1ce4e5b9ull;
-        }
-        h[r] = x;
-    }
-    std::vector<int32_t> order((size_t)n);
-    for (int64_t r = 0; r < n; ++r) order[r] = (int32_t)r;
-    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return h[a] != h[b] ? h[a] < h[b] : a < b;
-    });
-    auto same = [&](int32_t a, int32_t b) {
-        const int64_t la = rp[a + 1] - rp[a];
-        return la == rp[b + 1] - rp[b] && std::equal(ci.data() + rp[a], ci.data() + rp[a] + la, ci.data() + rp[b]);
-    };
     std::vector<std::vector<int32_t>> groups;
-    for (size_t i = 0; i < order.size();) {
-        size_t j = i;
-        while (j < order.size() && h[order[j]] == h[order[i]]) ++j;
-        // classes of exactly equal lists among rows [i, j) (in row order)
-        std::vector<std::vector<int32_t>> cls;
-        for (size_t q = i; q < j; ++q) {
-            const int32_t r = order[q];
-            bool put = false;
-            for (auto& c : cls)
-                if (same(c.front(), r)) { c.push_back(r); put = true; break; }
-            if (!put) cls.push_back({r});
-        }
-        for (auto& c : cls) {   // ceil(size / GROUP_MAX) groups of near-equal size
-            const size_t parts = (c.size() + GROUP_MAX - 1) / GROUP_MAX;
-            for (size_t q = 0; q < parts; ++q)
-                groups.emplace_back(c.begin() + c.size() * q / parts, c.begin() + c.size() * (q + 1) / parts);
-        }
-        i = j;
+    for (const auto& c : identical_row_classes(rp, ci, n)) {   // ceil(size / GROUP_MAX) near-equal groups
+        const size_t parts = (c.size() + GROUP_MAX - 1) / GROUP_MAX;
+        for (size_t q = 0; q < parts; ++q)
+            groups.emplace_back(c.begin() + c.size() * q / parts, c.begin() + c.size() * (q + 1) / parts);
     }
     std::sort(groups.begin(), groups.end(),
               [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) { return a.front() < b.front(); });

@@ -86,6 +86,7 @@ void giamg_default_opts(giamg_opts* o) {
     o->basis = GIAMG_BASIS_NODAL;
     for (int i = 0; i < 8; ++i) o->schedule[i] = 0;
     o->batch_kernel = GIAMG_BATCH_AUTO;
+    o->row_groups = 0;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -120,6 +121,7 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
         GIAMG_REQUIRE(o.basis == GIAMG_BASIS_NODAL || o.basis == GIAMG_BASIS_MODAL, "unknown basis");
         GIAMG_REQUIRE(o.batch_kernel >= GIAMG_BATCH_AUTO && o.batch_kernel <= GIAMG_BATCH_GROUP,
                       "unknown batch_kernel");
+        GIAMG_REQUIRE(o.row_groups == 0 || o.row_groups == 1, "row_groups must be 0 or 1");
         {
             int prev = p;
             for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
@@ -215,6 +217,8 @@ int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out) {
         out->nnz_AP = L.AP.nnz;
         out->staged_nnz_A = L.A.nnz_staged;
         out->runs_A = L.A.nruns;
+        out->groups_A = L.A.gnblk > 0 ? L.A.ggroups : 0;
+        out->group_entries_A = L.A.gnblk > 0 ? L.A.gentries : 0;
         return GIAMG_OK;
     });
 }

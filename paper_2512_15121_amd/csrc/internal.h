@@ -97,6 +97,24 @@ struct DevCSR {
     DevBuf<int32_t> runs;     // [2 * nruns] (first column, LDS slot | length << 16)
     DevBuf<uint16_t> slot;    // [nnz] LDS slot of each nonzero's column within its block
     int64_t nruns = 0, nnz_staged = 0;
+    // Grouped form: rows with identical column lists share one list of LDS
+    // slots (a group, at most 8 rows); a block holds groups of one size g and
+    // stores its values as g planes (plane i: row i of every group, entry by
+    // entry).  gnblk == 0: not built.  Layout in kernels.h (GBlock).
+    int64_t gnblk = 0, gentries = 0, ggroups = 0, gnruns = 0;
+    DevBuf<int64_t> gblk;     // [4 * (gnblk + 1)] GBlock records
+    DevBuf<int32_t> grows;    // [nrows] rows, block by block, group by group
+    DevBuf<uint32_t> ggrp;    // [ggroups] local entry offset << 16 | entries
+    DevBuf<uint16_t> gslot;   // [gentries]
+    DevBuf<int32_t> grun_ptr; // [gnblk + 1]
+    DevBuf<int32_t> gruns;    // [2 * gnruns]
+    DevBuf<double> gval;      // [nnz]
+    DevBuf<float> gval32;     // [nnz] (mixed precision)
+    void release_grouping() {
+        gnblk = gentries = ggroups = gnruns = 0;
+        gblk.release(); grows.release(); ggrp.release(); gslot.release();
+        grun_ptr.release(); gruns.release(); gval.release(); gval32.release();
+    }
 };
 // Build the row blocks of d from a host copy of its row pointers.
 void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);

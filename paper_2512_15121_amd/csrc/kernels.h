@@ -26,6 +26,15 @@ constexpr int SPMV_THREADS = 512;
 constexpr int CHEB_ASSIGN = 1;   // x = d_old (+ d_new) instead of x += ...
 constexpr int CHEB_LAST = 2;     // add the new direction as well (last step)
 
+// A block of the grouped product form (DevCSR::gblk, one more entry than
+// blocks: block b spans entries [e0, next.e0), rows [r0, next.r0) of grows
+// and groups [q0, next.q0) of ggrp; its g * E values start at v0).
+struct GBlock {
+    int64_t e0, v0;
+    int32_t r0, q0, g, pad;
+};
+static_assert(sizeof(GBlock) == 32, "GBlock layout");
+
 template <typename T>
 struct SpmvArgs {
     const int64_t* rp = nullptr;
@@ -53,6 +62,17 @@ struct SpmvArgs {
     const uint16_t* slot = nullptr;
     int64_t nnz = 0, ncols = 0;      // host-side byte accounting only
     int64_t nnz_staged = 0, nruns = 0;
+    // grouped form (DevCSR, build_grouping): when gblk is set the product
+    // runs over nblk grouped blocks and reads gval / gslot / grows / ggrp
+    // and the block run tables grun_ptr / gruns instead of the CSR arrays.
+    const GBlock* gblk = nullptr;
+    const int32_t* grows = nullptr;
+    const uint32_t* ggrp = nullptr;   // per group: local entry offset << 16 | entries
+    const uint16_t* gslot = nullptr;  // per entry: LDS slot of its column
+    const int32_t* grun_ptr = nullptr;
+    const int32_t* gruns = nullptr;
+    const T* gval = nullptr;
+    int64_t gentries = 0, ggroups = 0, gnruns = 0;   // host-side byte accounting only
 };
 
 template <typename T>
@@ -66,6 +86,21 @@ void make_row_blocks(const int64_t* rp, int64_t n, std::vector<int64_t>& blocks,
 // long-row blocks, keep direct gathers.
 constexpr int64_t STAGE_SPAN = 262144;
 void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
+// Grouped form of d (groups.cpp): rows with identical column lists in groups
+// of at most GROUP_ROWS, blocks of one group size, every block staged.  rp and
+// ci are host copies of d's pattern.  Returns false (and leaves d without the
+// form) when the form would not pay or an operator does not fit it.
+constexpr int GROUP_ROWS = 8;
+// Rows of a CSR pattern (host copy) with identical column lists: classes in
+// order of their first row, rows ascending within a class.
+std::vector<std::vector<int32_t>> identical_row_classes(const std::vector<int64_t>& rp,
+                                                        const std::vector<int32_t>& ci, int64_t n);
+bool build_grouping(DevCSR& d, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                    hipStream_t s);
+// Values of the grouped form in FP32 (after make_fp32_values of the CSR).
+void make_fp32_group_values(DevCSR& d, hipStream_t s);
+// Device gather y[i] = x[idx[i]] (setup: value reordering).
+void launch_gather_values(int64_t n, const int64_t* idx, const double* x, double* y, hipStream_t s);
 
 // row-local kernels
 template <typename T>

@@ -166,6 +166,37 @@ __device__ __forceinline__ void block_sum2(double* red, int tid, double a, doubl
 // only their stores are guarded: guards there split the code into blocks
 // that the compiler separates with waits for every load in flight.
 
+// Copy the runs of the gathered vector v that this wave owns (mine of them,
+// descriptors in dsc: lane i holds the wave's run i) into LDS, one run (at
+// most 64 entries) per load.  One batch copies SB runs: SB loads in flight,
+// then the LDS stores.  The first batch is straight-line code that runs even
+// in a wave without runs (its loads then repeat a valid run and store
+// nothing): its loads issue while the caller's value stream is in flight,
+// and no loop head makes the compiler wait for that stream first.
+template <typename T>
+__device__ __forceinline__ void stage_runs(const T* __restrict__ v, int2 dsc, int mine, int lane,
+                                           T* prod) {
+    constexpr int SB = 8;   // runs copied per batch (loads in flight); fits 64 registers
+    auto stage_batch = [&](int i0) {
+        T tmp[SB];
+        int dst[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+            const int i = max(0, min(i0 + j, mine - 1));
+            const T* __restrict__ vr = v + __builtin_amdgcn_readlane(dsc.x, i);   // run start
+            const int ol = __builtin_amdgcn_readlane(dsc.y, i);
+            const int len = ol >> 16;
+            tmp[j] = vr[min((unsigned)lane, (unsigned)(len - 1))];
+            dst[j] = (i0 + j < mine && lane < len) ? (ol & 0xffff) + lane : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+            if (dst[j] >= 0) prod[dst[j]] = tmp[j];
+    };
+    stage_batch(0);
+    for (int i0 = SB; i0 < mine; i0 += SB) stage_batch(i0);
+}
+
 // Staged: run table first, then values and slots, then the vector runs
 // (copied into prod), then the products (into prod).  nruns > 0.
 template <typename T>
@@ -173,9 +204,7 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int64_t lb,
                                                int nruns, T* prod) {
     constexpr int PER = SPMV_CAP / SPMV_THREADS;
     constexpr int NW = SPMV_THREADS / WAVE;
-    constexpr int SB = 8;   // runs copied per batch (loads in flight); fits 64 registers
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
-    const T* __restrict__ v = a.v;
     const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + a.run_ptr[lb];
     // runs w, w + NW, ... of this wave; a staged block has at most
     // STAGE_MAX_RUNS = NW * WAVE runs, so one descriptor per lane
@@ -199,29 +228,7 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int64_t lb,
             av[k] = T(0);
         }
     }
-    // One batch copies SB runs: SB loads in flight, then the LDS stores.
-    // The first batch is straight-line code that runs even in a wave
-    // without runs (its loads then repeat a valid run and store nothing):
-    // its loads issue while the value stream is in flight, and no loop head
-    // makes the compiler wait for that stream first.
-    auto stage_batch = [&](int i0) {
-        T tmp[SB];
-        int dst[SB];
-#pragma unroll
-        for (int j = 0; j < SB; ++j) {
-            const int i = max(0, min(i0 + j, mine - 1));
-            const T* __restrict__ vr = v + __builtin_amdgcn_readlane(dsc.x, i);   // run start
-            const int ol = __builtin_amdgcn_readlane(dsc.y, i);
-            const int len = ol >> 16;
-            tmp[j] = vr[min((unsigned)lane, (unsigned)(len - 1))];
-            dst[j] = (i0 + j < mine && lane < len) ? (ol & 0xffff) + lane : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < SB; ++j)
-            if (dst[j] >= 0) prod[dst[j]] = tmp[j];
-    };
-    stage_batch(0);
-    for (int i0 = SB; i0 < mine; i0 += SB) stage_batch(i0);
+    stage_runs<T>(a.v, dsc, mine, lane, prod);
     __syncthreads();
     T pr[PER];
 #pragma unroll
@@ -365,6 +372,138 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = red[SPMV_THREADS];
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Grouped form.  Rows whose column lists are identical (in a high-order
+// element mesh: the interior, face-interior and edge-interior nodes of one
+// element, face or edge) form groups of at most GROUP_ROWS rows; they share
+// one list of 16-bit LDS slots, so the slot stream shrinks by the group size.
+// A block holds groups of one size G (E entries: the union of its groups'
+// lists, group after group) and stores its values as G planes of E values,
+// plane i holding row i of every group; its columns are staged in LDS as in
+// the CSR form.  Row sums use the CSR form's order and lane split, so both
+// forms give the same row results bit for bit (block partial sums of the
+// DOT and RINIT epilogues add the rows in another order).
+// ---------------------------------------------------------------------------
+
+// Steps 1 and 2 for a block of G-row groups.  Thread t takes entries
+// t + k * SPMV_THREADS (k < 8 / G): per entry one slot and G values (one per
+// plane), all loads issued before the run copies; products go to LDS plane
+// by plane (prod[i * E + e]); then groups of L lanes sum the rows.
+template <typename T, int L, int G>
+__device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, const GBlock& B, int E,
+                                            int R, int nruns, T* prod, T* rowsum) {
+    constexpr int KPT = SPMV_CAP / SPMV_THREADS / G;   // entries per thread
+    constexpr int NW = SPMV_THREADS / WAVE;
+    static_assert(KPT >= 1 && KPT * G <= SPMV_CAP / SPMV_THREADS, "entries per thread");
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    if (nruns > 0) {   // 0 only for blocks of empty rows (E == 0)
+        const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.gruns) + a.grun_ptr[lb];
+        const int mine = nruns > w ? (nruns - w + NW - 1) / NW : 0;
+        const int2 dsc = runs[min(w + NW * lane, nruns - 1)];
+        const uint16_t* __restrict__ sl = a.gslot + B.e0;
+        const T* __restrict__ val = a.gval + B.v0;
+        int c[KPT];
+        T av[KPT][G];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            const unsigned idx = (unsigned)(tid + k * SPMV_THREADS);
+            if (idx < (unsigned)E) {
+                c[k] = (int)ldnt(sl + idx);
+#pragma unroll
+                for (int i = 0; i < G; ++i) av[k][i] = ldnt(val + (unsigned)(i * E) + idx);
+            } else {
+                c[k] = 0;
+#pragma unroll
+                for (int i = 0; i < G; ++i) av[k][i] = T(0);
+            }
+        }
+        stage_runs<T>(a.v, dsc, mine, lane, prod);
+        __syncthreads();
+        T pr[KPT][G];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            const T xv = prod[c[k]];
+#pragma unroll
+            for (int i = 0; i < G; ++i) pr[k][i] = av[k][i] * xv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            const int idx = tid + k * SPMV_THREADS;
+            if (idx < E) {
+#pragma unroll
+                for (int i = 0; i < G; ++i) prod[i * E + idx] = pr[k][i];
+            }
+        }
+    }
+    __syncthreads();
+    const int gi = tid / L, gl = tid % L;
+    for (int rr = gi; rr < R; rr += SPMV_THREADS / L) {
+        const int q = rr / G, i = rr - q * G;
+        const uint32_t gq = a.ggrp[B.q0 + q];
+        const int s = i * E + (int)(gq >> 16), e = s + (int)(gq & 0xffffu);
+        T acc = 0;
+        for (int j = s + gl; j < e; j += L) acc += prod[j];
+        acc = group_sum<L>(acc);
+        if (gl == 0) rowsum[rr] = acc;
+    }
+}
+
+// Product over the grouped form: block lb (XCD-remapped as in the CSR form)
+// owns R = G * groups rows listed in grows; thread t finishes row t.
+template <typename T, int MODE, int L>
+__global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+spmv_group_kernel(SpmvArgs<T> a) {
+    if (stopped(a.stop)) return;
+    __shared__ T prod[SPMV_CAP];
+    __shared__ T rowsum[SPMV_THREADS];
+    double* red = reinterpret_cast<double*>(prod);
+    const int tid = threadIdx.x;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const GBlock B = a.gblk[lb];
+    const int E = (int)(a.gblk[lb + 1].e0 - B.e0), R = a.gblk[lb + 1].r0 - B.r0;
+    const int nruns = a.grun_ptr[lb + 1] - a.grun_ptr[lb];
+    double dot = 0.0, dot2 = 0.0;
+    RowIn<T> in{};
+    int64_t row = 0;
+    if ((tid / WAVE) * WAVE < R) {
+        row = a.grows[B.r0 + min(tid, R - 1)];
+        epilogue_load<T, MODE>(a, row, in);
+    }
+    switch (B.g) {
+        case 1: group_block<T, L, 1>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        case 2: group_block<T, L, 2>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        case 3: group_block<T, L, 3>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        case 4: group_block<T, L, 4>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        case 5: group_block<T, L, 5>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        case 6: group_block<T, L, 6>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        case 7: group_block<T, L, 7>(a, lb, B, E, R, nruns, prod, rowsum); break;
+        default: group_block<T, L, 8>(a, lb, B, E, R, nruns, prod, rowsum); break;
+    }
+    __syncthreads();
+    if (tid < R) epilogue_store<T, MODE>(a, row, rowsum[tid], in, dot, dot2);
+    if constexpr (has_partials<MODE>()) {
+        block_sum2(red, tid, dot, dot2);
+        if (tid == 0) {
+            a.partial[lb] = red[0];
+            if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = red[SPMV_THREADS];
+        }
+    }
+}
+
+__global__ void gather_values_kernel(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ x,
+                                     double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[idx[i]];
+}
+
+void launch_gather_values(int64_t n, const int64_t* idx, const double* x, double* y, hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    gather_values_kernel<<<g, 256, 0, s>>>(n, idx, x, y);
+    GIAMG_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
@@ -553,6 +692,15 @@ void launch_spmv_kernel(const SpmvArgs<T>& a, hipStream_t s) {
         spmv_stream_kernel<T, MODE, L, STAGE><<<grid, block, 0, s>>>(a);
 }
 
+template <typename T, int MODE, int L>
+void launch_group_kernel(const SpmvArgs<T>& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
+    if (a.ev_start != nullptr)
+        hipExtLaunchKernelGGL(spmv_group_kernel<T, MODE, L>, grid, block, 0, s, a.ev_start, a.ev_stop, 0, a);
+    else
+        spmv_group_kernel<T, MODE, L><<<grid, block, 0, s>>>(a);
+}
+
 template <typename T, int MODE, int STAGE>
 void launch_spmv_form(const SpmvArgs<T>& a, hipStream_t s) {
     switch (a.lanes) {
@@ -565,7 +713,14 @@ void launch_spmv_form(const SpmvArgs<T>& a, hipStream_t s) {
 
 template <typename T, int MODE>
 void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
-    if (a.run_ptr == nullptr)
+    if (a.gblk != nullptr) {
+        switch (a.lanes) {
+            case 16: launch_group_kernel<T, MODE, 16>(a, s); break;
+            case 4: launch_group_kernel<T, MODE, 4>(a, s); break;
+            case 1: launch_group_kernel<T, MODE, 1>(a, s); break;
+            default: throw Error(GIAMG_EINVAL, "unsupported reduction width");
+        }
+    } else if (a.run_ptr == nullptr)
         launch_spmv_form<T, MODE, 0>(a, s);
     else if (a.nnz_staged == a.nnz)
         launch_spmv_form<T, MODE, 1>(a, s);

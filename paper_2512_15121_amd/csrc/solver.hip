@@ -81,7 +81,9 @@ void download_csr(const DevCSR& d, HostCSR& h, hipStream_t s) {
     GIAMG_HIP(hipStreamSynchronize(s));
 }
 
-// Product arguments over one CSR operator (values in the precision of T).
+// Product arguments over one operator (values in the precision of T): its
+// grouped form when built (with values in that precision), else its CSR
+// blocks.
 template <typename T>
 SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     SpmvArgs<T> a;
@@ -90,7 +92,45 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
     a.run_ptr = M.run_ptr.get(); a.runs = M.runs.get(); a.slot = M.slot.get();
     a.nnz_staged = M.nnz_staged; a.nruns = M.nruns;
+    const T* gval = nullptr;
+    if constexpr (sizeof(T) == sizeof(double)) gval = M.gval.get(); else gval = M.gval32.get();
+    if (M.gnblk > 0 && gval != nullptr) {
+        a.gblk = reinterpret_cast<const GBlock*>(M.gblk.get());
+        a.grows = M.grows.get(); a.ggrp = M.ggrp.get(); a.gslot = M.gslot.get();
+        a.grun_ptr = M.grun_ptr.get(); a.gruns = M.gruns.get(); a.gval = gval;
+        a.nblk = M.gnblk; a.gentries = M.gentries; a.ggroups = M.ggroups; a.gnruns = M.gnruns;
+    }
     return a;
+}
+
+// Blocks of the product form args_of picks for FP64 values (the number of
+// block partials its DOT and RINIT epilogues write).
+int64_t product_blocks(const DevCSR& M) { return M.gnblk > 0 ? M.gnblk : M.nblk; }
+
+// Grouped forms (groups.cpp) of the operators whose rows share column lists;
+// an operator that gets one drops its CSR staging tables (its products then
+// always run grouped).
+void build_grouped_forms(Handle& H, bool mixed) {
+    for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
+        Level& L = H.levels[l];
+        for (DevCSR* M : {&L.A, &L.AP, &L.P, &L.R}) {
+            if (M->nnz <= 0) continue;
+            std::vector<int64_t> rp((size_t)M->nrows + 1);
+            std::vector<int32_t> ci((size_t)M->nnz);
+            GIAMG_HIP(hipMemcpyAsync(rp.data(), M->rp.get(), rp.size() * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, H.stream));
+            GIAMG_HIP(hipMemcpyAsync(ci.data(), M->ci.get(), ci.size() * sizeof(int32_t),
+                                     hipMemcpyDeviceToHost, H.stream));
+            GIAMG_HIP(hipStreamSynchronize(H.stream));
+            if (!build_grouping(*M, rp, ci, H.stream)) continue;
+            if (mixed) make_fp32_group_values(*M, H.stream);
+            M->run_ptr.release();
+            M->runs.release();
+            M->slot.release();
+            M->nruns = M->nnz_staged = 0;
+        }
+    }
+    GIAMG_HIP(hipStreamSynchronize(H.stream));
 }
 
 void make_fp32_values(DevCSR& d, hipStream_t s) {
@@ -274,11 +314,15 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         }
     }
     H.setup_ms[4] = ms_since(t0);
+    t0 = clock_t_::now();
+    if (o.row_groups && !o.direct_gathers) build_grouped_forms(H, mixed);
+    const double grouping_ms = ms_since(t0);
     // work buffers
     int64_t maxn = 1, maxblk = 1;
     for (auto& L : H.levels) {
         maxn = std::max(maxn, L.n);
-        maxblk = std::max({maxblk, L.A.nblk, L.P.nblk, L.R.nblk, L.AP.nblk});
+        maxblk = std::max({maxblk, L.A.nblk, L.P.nblk, L.R.nblk, L.AP.nblk, L.A.gnblk, L.P.gnblk,
+                           L.R.gnblk, L.AP.gnblk});
     }
     H.partial_cap = std::max<int64_t>(2 * maxblk, 2 * vec_blocks(maxn)) + 16;
     H.partial.alloc(H.partial_cap);
@@ -311,7 +355,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         }
         L.lam_hat = power_estimate(H, L);
     }
-    H.setup_ms[5] = ms_since(t0);
+    H.setup_ms[5] = ms_since(t0) + grouping_ms;
     const int64_t nn = std::max<int64_t>(n, 1);
     H.x.alloc(nn); H.r.alloc(nn); H.z.alloc(nn); H.p.alloc(nn); H.q.alloc(nn); H.rold.alloc(nn);
     H.tmp.alloc(nn);
@@ -336,7 +380,9 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
 int64_t handle_device_bytes(const Handle& H) {
     auto csr = [](const DevCSR& m) {
         return (int64_t)(m.rp.n + m.rblk.n) * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 +
-               (int64_t)m.val32.n * 4 + (int64_t)(m.run_ptr.n + m.runs.n) * 4 + (int64_t)m.slot.n * 2;
+               (int64_t)m.val32.n * 4 + (int64_t)(m.run_ptr.n + m.runs.n) * 4 + (int64_t)m.slot.n * 2 +
+               (int64_t)m.gblk.n * 8 + (int64_t)(m.grows.n + m.ggrp.n + m.grun_ptr.n + m.gruns.n) * 4 +
+               (int64_t)m.gslot.n * 2 + (int64_t)m.gval.n * 8 + (int64_t)m.gval32.n * 4;
     };
     int64_t b = 0;
     for (const Level& L : H.levels) {
@@ -406,6 +452,9 @@ double spmv_bytes(int mode, const SpmvArgs<T>& a) {
         case SPMV_DOT: rows = 1; break;               // y
         case SPMV_DINV: rows = 2; break;              // dinv, y
     }
+    if (a.gblk != nullptr)   // grouped: slots per entry, block records, row list, group table
+        return vb * a.nnz + 2.0 * a.gentries + 8.0 * a.gnruns + (4.0 + 32.0) * (a.nblk + 1) + 4.0 * a.n +
+               4.0 * a.ggroups + vb * a.ncols + rows * vb * a.n;
     const double staged = a.run_ptr ? 2.0 * a.nnz_staged + 8.0 * a.nruns + 4.0 * (a.nblk + 1) : 0.0;
     return vb * a.nnz + 4.0 * (a.nnz - a.nnz_staged) + staged + 8.0 * (a.n + 1) + vb * a.ncols +
            rows * vb * a.n;
@@ -595,7 +644,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     const Level& L0 = H.levels[0];
     const bool flexible = H.opts.precision == GIAMG_PREC_MIXED;
     hipStream_t s = H.stream;
-    const int64_t gs = L0.A.nblk, gv = vec_blocks(n);
+    const int64_t gs = product_blocks(L0.A), gv = vec_blocks(n);
     auto rinit = [&](double* out) {
         SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
         a.v = x; a.f = b; a.y = out; a.partial = H.partial.get();

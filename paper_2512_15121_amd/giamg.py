@@ -42,7 +42,8 @@ class _Opts(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
                 ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
                 ("graph_launch", ctypes.c_int32), ("basis", ctypes.c_int32),
-                ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32),
+                ("row_groups", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -70,7 +71,8 @@ class _LevelDesc(ctypes.Structure):
                 ("rows", ctypes.c_int64), ("nnz_A", ctypes.c_int64),
                 ("nnz_P", ctypes.c_int64), ("nnz_R", ctypes.c_int64),
                 ("lam_hat", ctypes.c_double), ("nnz_AP", ctypes.c_int64),
-                ("staged_nnz_A", ctypes.c_int64), ("runs_A", ctypes.c_int64)]
+                ("staged_nnz_A", ctypes.c_int64), ("runs_A", ctypes.c_int64),
+                ("groups_A", ctypes.c_int64), ("group_entries_A", ctypes.c_int64)]
 
 
 @dataclass
@@ -93,6 +95,7 @@ class Options:
     basis: str = "nodal"            # or "modal"
     schedule: tuple = ()            # coarse p-orders after p, e.g. (4, 3, 2, 1); () = default
     batch_kernel: str = "auto"      # block-product shape of solve_batch: auto, lanes, wave, group
+    row_groups: bool = False        # grouped product form where rows share column lists
 
     def _c(self) -> _Opts:
         d = asdict(self)
@@ -104,6 +107,7 @@ class Options:
         d["schedule"] = (ctypes.c_int32 * 8)(*(sched + [0] * (8 - len(sched))))
         d["direct_gathers"] = int(d["direct_gathers"])
         d["graph_launch"] = int(d["graph_launch"])
+        d["row_groups"] = int(d["row_groups"])
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]
@@ -266,7 +270,7 @@ class Solver:
         return {"kind": LEVEL_KIND[d.kind], "order": d.order, "coarsest": bool(d.coarsest),
                 "rows": d.rows, "nnz_A": d.nnz_A, "nnz_P": d.nnz_P, "nnz_R": d.nnz_R,
                 "nnz_AP": d.nnz_AP, "lam_hat": d.lam_hat, "staged_nnz_A": d.staged_nnz_A,
-                "runs_A": d.runs_A}
+                "runs_A": d.runs_A, "groups_A": d.groups_A, "group_entries_A": d.group_entries_A}
 
     def level_csr(self, l, which="A"):
         d = self.level(l)

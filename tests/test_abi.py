@@ -117,3 +117,20 @@ def test_unknown_batch_kernel_is_rejected_before_device_work():
                          ctypes.byref(h))
     assert rc == giamg.EINVAL and b"batch_kernel" in lib.giamg_last_error()
     assert not h.value
+
+
+def test_row_groups_option_default_and_validation():
+    from paper_2512_15121_amd import giamg
+    import numpy as np
+    lib = giamg.library()
+    o = giamg._Opts()
+    lib.giamg_default_opts(ctypes.byref(o))
+    assert o.row_groups == 0
+    o.row_groups = 2
+    coords = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], dtype=np.float64)
+    l2g = np.arange(8, dtype=np.int32)[None, :]
+    h = ctypes.c_void_p()
+    rc = lib.giamg_setup(giamg._ptr(coords), 8, giamg._ptr(l2g), 1, 1, 1.0, ctypes.byref(o), None,
+                         ctypes.byref(h))
+    assert rc == giamg.EINVAL and b"row_groups" in lib.giamg_last_error()
+    assert not h.value

@@ -123,6 +123,7 @@ def test_staged_gathers_bitwise_equal_direct(torch_dev, name):
     s1 = _solver(name)
     s2 = _solver(name, direct_gathers=True)
     d0 = s1.level(0)
+    assert d0["groups_A"] == 0
     assert d0["staged_nnz_A"] > 0.9 * d0["nnz_A"] and d0["runs_A"] > 0
     assert s2.level(0)["staged_nnz_A"] == 0 and s2.level(0)["runs_A"] == 0
     rng = np.random.default_rng(7)
@@ -167,6 +168,79 @@ def test_staged_gathers_mixed_bitwise_equal_direct(torch_dev):
     x1, i1 = s1.solve(b, tol=1e-10)
     x2, i2 = s2.solve(b, tol=1e-10)
     assert i1.status == 0 and i1.iters == i2.iters and torch.equal(x1, x2)
+    s1.close()
+    s2.close()
+
+
+def _levels_bitwise(torch, dev, s1, s2, fp32=False):
+    """spmv, restriction, prolongation and the V-cycle of every level agree
+    bit for bit between two solvers of the same hierarchy."""
+    rng = np.random.default_rng(11)
+    dt = torch.float32 if fp32 else torch.float64
+    nl = s1.num_levels()
+    for l in range(nl):
+        n = s1.level(l)["rows"]
+        x = _to(torch, dev, rng.standard_normal(n), dt)
+        o1 = torch.zeros(n, dtype=dt, device=dev)
+        o2 = torch.zeros_like(o1)
+        s1.apply("spmv", l, x, out=o1, fp32=fp32)
+        s2.apply("spmv", l, x, out=o2, fp32=fp32)
+        assert torch.equal(o1, o2), f"spmv {l}"
+        if l + 1 == nl:
+            continue
+        nc = s1.level(l + 1)["rows"]
+        c1 = torch.zeros(nc, dtype=dt, device=dev)
+        c2 = torch.zeros_like(c1)
+        s1.apply("restrict", l, x, out=c1, fp32=fp32)
+        s2.apply("restrict", l, x, out=c2, fp32=fp32)
+        assert torch.equal(c1, c2), f"restrict {l}"
+        y1, y2 = x.clone(), x.clone()
+        s1.apply("prolong_add", l, c1, out=y1, fp32=fp32)
+        s2.apply("prolong_add", l, c1, out=y2, fp32=fp32)
+        assert torch.equal(y1, y2), f"prolong {l}"
+        s1.apply("vcycle", l, x, out=o1, fp32=fp32)
+        s2.apply("vcycle", l, x, out=o2, fp32=fp32)
+        assert torch.equal(o1, o2), f"vcycle {l}"
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_grouped_form_rows_bitwise_equal_csr(torch_dev, name):
+    """The grouped form (rows with one column list share their slots, values
+    in per-block planes) sums every row in the CSR form's order: products,
+    transfers and V-cycles of every level agree bit for bit.  A solve differs
+    only through the CG dot products, whose block partials add the rows in
+    another order: same iterations, iterates equal to rounding."""
+    torch, dev = torch_dev
+    n, p, lam, sm, pert, cm, bc, basis, sched = CASES[name]
+    s1 = _solver(name, row_groups=True)
+    s2 = _solver(name)
+    d1, d2 = s1.level(0), s2.level(0)
+    assert d2["groups_A"] == 0 and d2["group_entries_A"] == 0
+    if p >= 3:   # interior, face and edge nodes share column lists
+        assert d1["groups_A"] > 0 and d1["group_entries_A"] <= 0.8 * d1["nnz_A"]
+        assert d1["staged_nnz_A"] == 0 and d1["runs_A"] == 0
+    _levels_bitwise(torch, dev, s1, s2)
+    b = _to(torch, dev, np.random.default_rng(12).standard_normal(d1["rows"]))
+    x1, i1 = s1.solve(b, tol=1e-10)
+    x2, i2 = s2.solve(b, tol=1e-10)
+    assert i1.status == 0 and i2.status == 0 and abs(i1.iters - i2.iters) <= 1
+    assert torch.linalg.norm(x1 - x2) <= 1e-10 * torch.linalg.norm(x2)
+    s1.close()
+    s2.close()
+
+
+@pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "modal_p5_4cube_by_one"])
+def test_grouped_form_fp32_rows_bitwise_equal_csr(torch_dev, name):
+    torch, dev = torch_dev
+    s1 = _solver(name, precision="mixed", row_groups=True)
+    s2 = _solver(name, precision="mixed")
+    assert s1.level(0)["groups_A"] > 0
+    _levels_bitwise(torch, dev, s1, s2, fp32=True)
+    b = _to(torch, dev, np.random.default_rng(13).standard_normal(s1.level(0)["rows"]))
+    x1, i1 = s1.solve(b, tol=1e-10)
+    x2, i2 = s2.solve(b, tol=1e-10)
+    assert i1.status == 0 and i2.status == 0 and abs(i1.iters - i2.iters) <= 1
+    assert torch.linalg.norm(x1 - x2) <= 1e-9 * torch.linalg.norm(x2)
     s1.close()
     s2.close()
 
