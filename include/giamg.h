@@ -111,6 +111,13 @@ typedef struct giamg_opts {
                               slots; needs direct_gathers = 0.  Default 0 (CSR form
                               only): the grouped form moves fewer bytes but measured
                               slower on gfx950 */
+    int32_t  pad;
+    int64_t  lean_max_nnz; /* operators with at most this many nonzeros (and no row longer
+                              than 4096) are multiplied by a kernel that reads each row
+                              straight from memory: a shorter chain of dependent loads
+                              than the blocked, staged form, for the small coarse levels
+                              (same rows, bit for bit; CG dot partials over other
+                              blocks).  0: never.  Default 2000000 */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -216,6 +223,7 @@ typedef struct giamg_level_desc {
     int64_t runs_A;        /* column runs those blocks stage */
     int64_t groups_A;      /* grouped form of A (see row_groups): row groups, 0 if not built */
     int64_t group_entries_A; /* 16-bit slots of that form (sum of the groups' row lengths) */
+    int64_t lean_A;        /* 1: A is multiplied in the lean form (see lean_max_nnz) */
 } giamg_level_desc;
 
 int giamg_num_levels(giamg_handle h);

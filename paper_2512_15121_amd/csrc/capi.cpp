@@ -87,6 +87,8 @@ void giamg_default_opts(giamg_opts* o) {
     for (int i = 0; i < 8; ++i) o->schedule[i] = 0;
     o->batch_kernel = GIAMG_BATCH_AUTO;
     o->row_groups = 0;
+    o->pad = 0;
+    o->lean_max_nnz = 2000000;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -122,6 +124,7 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
         GIAMG_REQUIRE(o.batch_kernel >= GIAMG_BATCH_AUTO && o.batch_kernel <= GIAMG_BATCH_GROUP,
                       "unknown batch_kernel");
         GIAMG_REQUIRE(o.row_groups == 0 || o.row_groups == 1, "row_groups must be 0 or 1");
+        GIAMG_REQUIRE(o.lean_max_nnz >= 0, "lean_max_nnz must be >= 0");
         {
             int prev = p;
             for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
@@ -219,6 +222,7 @@ int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out) {
         out->runs_A = L.A.nruns;
         out->groups_A = L.A.gnblk > 0 ? L.A.ggroups : 0;
         out->group_entries_A = L.A.gnblk > 0 ? L.A.gentries : 0;
+        out->lean_A = L.A.lean ? 1 : 0;
         return GIAMG_OK;
     });
 }

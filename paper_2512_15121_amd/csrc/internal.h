@@ -110,6 +110,11 @@ struct DevCSR {
     DevBuf<int32_t> gruns;    // [2 * gnruns]
     DevBuf<double> gval;      // [nnz]
     DevBuf<float> gval32;     // [nnz] (mixed precision)
+    // Lean form: small operators (at most giamg_opts.lean_max_nnz nonzeros,
+    // no row longer than SPMV_CAP) run a kernel that reads rows straight from
+    // memory in blocks of LEAN_THREADS / lanes rows; no staging tables.
+    bool lean = false;
+    int64_t lean_nblk = 0;
     void release_grouping() {
         gnblk = gentries = ggroups = gnruns = 0;
         gblk.release(); grows.release(); ggrp.release(); gslot.release();

@@ -21,6 +21,9 @@ enum SpmvMode : int {
 // Nonzeros one block stages in LDS; rows longer than this get a block each.
 constexpr int SPMV_CAP = 4096;
 constexpr int SPMV_THREADS = 512;
+// Lean form (small operators): threads per block; a block holds
+// LEAN_THREADS / L rows.
+constexpr int LEAN_THREADS = 256;
 
 // flags of SPMV_CHEB_STEP
 constexpr int CHEB_ASSIGN = 1;   // x = d_old (+ d_new) instead of x += ...
@@ -73,6 +76,9 @@ struct SpmvArgs {
     const int32_t* gruns = nullptr;
     const T* gval = nullptr;
     int64_t gentries = 0, ggroups = 0, gnruns = 0;   // host-side byte accounting only
+    // lean form (DevCSR::lean): nblk blocks of LEAN_THREADS / lanes rows,
+    // reading rp / ci / val / v directly
+    bool lean = false;
 };
 
 template <typename T>

@@ -147,15 +147,16 @@ __device__ __forceinline__ void epilogue_store(const SpmvArgs<T>& a, int64_t row
 template <int MODE>
 constexpr bool has_partials() { return MODE == SPMV_DOT || MODE == SPMV_RINIT; }
 
-// Fixed-order block sum of two values per thread; red holds 2*SPMV_THREADS.
+// Fixed-order block sum of two values per thread; red holds 2*NT.
+template <int NT = SPMV_THREADS>
 __device__ __forceinline__ void block_sum2(double* red, int tid, double a, double b) {
     red[tid] = a;
-    red[SPMV_THREADS + tid] = b;
+    red[NT + tid] = b;
     __syncthreads();
-    for (int o = SPMV_THREADS / 2; o > 0; o >>= 1) {
+    for (int o = NT / 2; o > 0; o >>= 1) {
         if (tid < o) {
             red[tid] += red[tid + o];
-            red[SPMV_THREADS + tid] += red[SPMV_THREADS + tid + o];
+            red[NT + tid] += red[NT + tid + o];
         }
         __syncthreads();
     }
@@ -493,6 +494,62 @@ spmv_group_kernel(SpmvArgs<T> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lean form for small operators (DevCSR::lean): groups of L lanes read a row
+// straight from memory (column ids and values, then the vector), with no
+// row-block bounds, run tables or LDS staging, so a launch waits on a chain
+// three loads deep; the coarse levels (kilobytes to a few MB each) are
+// bound by that chain, not by bytes.  Lane gl sums the row's products at
+// positions gl, gl + L, ... in order, each product rounded before it is
+// added (as the LDS products of the CSR form are), and the L lanes combine
+// by the same butterfly: rows equal the CSR form's bit for bit (operators
+// with rows longer than SPMV_CAP keep the CSR form).
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, int L>
+__global__ void __launch_bounds__(LEAN_THREADS) spmv_lean_kernel(SpmvArgs<T> a) {
+    if (stopped(a.stop)) return;
+    constexpr int RPB = LEAN_THREADS / L;
+    const int tid = threadIdx.x, gl = tid % L;
+    const int64_t row = (int64_t)blockIdx.x * RPB + tid / L;
+    const bool live = row < a.n;
+    const int64_t rr = live ? row : a.n - 1;
+    RowIn<T> in{};
+    if (gl == 0) epilogue_load<T, MODE>(a, rr, in);
+    const int64_t s = a.rp[rr], e = a.rp[rr + 1];
+    const int32_t* __restrict__ ci = a.ci;
+    const T* __restrict__ val = a.val;
+    const T* __restrict__ v = a.v;
+    T acc = 0;
+    {
+#pragma clang fp contract(off)
+        int64_t j = s + gl;
+        for (; j + 3 * L < e; j += 4 * L) {
+            const int32_t c0 = ci[j], c1 = ci[j + L], c2 = ci[j + 2 * L], c3 = ci[j + 3 * L];
+            const T a0 = val[j], a1 = val[j + L], a2 = val[j + 2 * L], a3 = val[j + 3 * L];
+            const T p0 = a0 * v[c0], p1 = a1 * v[c1], p2 = a2 * v[c2], p3 = a3 * v[c3];
+            acc += p0;
+            acc += p1;
+            acc += p2;
+            acc += p3;
+        }
+        for (; j < e; j += L) {
+            const T p = val[j] * v[ci[j]];
+            acc += p;
+        }
+    }
+    acc = group_sum<L>(acc);
+    double dot = 0.0, dot2 = 0.0;
+    if (live && gl == 0) epilogue_store<T, MODE>(a, row, acc, in, dot, dot2);
+    if constexpr (has_partials<MODE>()) {
+        __shared__ double red[2 * LEAN_THREADS];
+        block_sum2<LEAN_THREADS>(red, tid, dot, dot2);
+        if (tid == 0) {
+            a.partial[blockIdx.x] = red[0];
+            if (MODE == SPMV_RINIT) a.partial[a.nblk + blockIdx.x] = red[LEAN_THREADS];
+        }
+    }
+}
+
 __global__ void gather_values_kernel(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ x,
                                      double* __restrict__ y) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -711,9 +768,25 @@ void launch_spmv_form(const SpmvArgs<T>& a, hipStream_t s) {
     }
 }
 
+template <typename T, int MODE, int L>
+void launch_lean_kernel(const SpmvArgs<T>& a, hipStream_t s) {
+    const dim3 grid((unsigned)a.nblk), block(LEAN_THREADS);
+    if (a.ev_start != nullptr)
+        hipExtLaunchKernelGGL(spmv_lean_kernel<T, MODE, L>, grid, block, 0, s, a.ev_start, a.ev_stop, 0, a);
+    else
+        spmv_lean_kernel<T, MODE, L><<<grid, block, 0, s>>>(a);
+}
+
 template <typename T, int MODE>
 void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
-    if (a.gblk != nullptr) {
+    if (a.lean) {
+        switch (a.lanes) {
+            case 16: launch_lean_kernel<T, MODE, 16>(a, s); break;
+            case 4: launch_lean_kernel<T, MODE, 4>(a, s); break;
+            case 1: launch_lean_kernel<T, MODE, 1>(a, s); break;
+            default: throw Error(GIAMG_EINVAL, "unsupported reduction width");
+        }
+    } else if (a.gblk != nullptr) {
         switch (a.lanes) {
             case 16: launch_group_kernel<T, MODE, 16>(a, s); break;
             case 4: launch_group_kernel<T, MODE, 4>(a, s); break;

@@ -92,6 +92,11 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
     a.run_ptr = M.run_ptr.get(); a.runs = M.runs.get(); a.slot = M.slot.get();
     a.nnz_staged = M.nnz_staged; a.nruns = M.nruns;
+    if (M.lean) {
+        a.lean = true;
+        a.nblk = M.lean_nblk;
+        return a;
+    }
     const T* gval = nullptr;
     if constexpr (sizeof(T) == sizeof(double)) gval = M.gval.get(); else gval = M.gval32.get();
     if (M.gnblk > 0 && gval != nullptr) {
@@ -105,7 +110,32 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
 
 // Blocks of the product form args_of picks for FP64 values (the number of
 // block partials its DOT and RINIT epilogues write).
-int64_t product_blocks(const DevCSR& M) { return M.gnblk > 0 ? M.gnblk : M.nblk; }
+int64_t product_blocks(const DevCSR& M) { return M.lean ? M.lean_nblk : M.gnblk > 0 ? M.gnblk : M.nblk; }
+
+// Lean form for the operators with at most max_nnz nonzeros and no row longer
+// than SPMV_CAP (their staging tables are released).
+void assign_lean_forms(Handle& H, int64_t max_nnz) {
+    for (Level& L : H.levels)
+        for (DevCSR* M : {&L.A, &L.AP, &L.P, &L.R}) {
+            M->lean = false;
+            M->lean_nblk = 0;
+            if (M->nrows <= 0 || M->nnz > max_nnz) continue;
+            std::vector<int64_t> rp((size_t)M->nrows + 1);
+            GIAMG_HIP(hipMemcpyAsync(rp.data(), M->rp.get(), rp.size() * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, H.stream));
+            GIAMG_HIP(hipStreamSynchronize(H.stream));
+            int64_t maxlen = 0;
+            for (int64_t r = 0; r < M->nrows; ++r) maxlen = std::max(maxlen, rp[r + 1] - rp[r]);
+            if (maxlen > SPMV_CAP) continue;
+            const int64_t rpb = LEAN_THREADS / M->lanes;
+            M->lean = true;
+            M->lean_nblk = (M->nrows + rpb - 1) / rpb;
+            M->run_ptr.release();
+            M->runs.release();
+            M->slot.release();
+            M->nruns = M->nnz_staged = 0;
+        }
+}
 
 // Grouped forms (groups.cpp) of the operators whose rows share column lists;
 // an operator that gets one drops its CSR staging tables (its products then
@@ -114,7 +144,7 @@ void build_grouped_forms(Handle& H, bool mixed) {
     for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
         Level& L = H.levels[l];
         for (DevCSR* M : {&L.A, &L.AP, &L.P, &L.R}) {
-            if (M->nnz <= 0) continue;
+            if (M->nnz <= 0 || M->lean) continue;
             std::vector<int64_t> rp((size_t)M->nrows + 1);
             std::vector<int32_t> ci((size_t)M->nnz);
             GIAMG_HIP(hipMemcpyAsync(rp.data(), M->rp.get(), rp.size() * sizeof(int64_t),
@@ -315,14 +345,15 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     }
     H.setup_ms[4] = ms_since(t0);
     t0 = clock_t_::now();
+    if (o.lean_max_nnz > 0) assign_lean_forms(H, o.lean_max_nnz);
     if (o.row_groups && !o.direct_gathers) build_grouped_forms(H, mixed);
     const double grouping_ms = ms_since(t0);
     // work buffers
     int64_t maxn = 1, maxblk = 1;
     for (auto& L : H.levels) {
         maxn = std::max(maxn, L.n);
-        maxblk = std::max({maxblk, L.A.nblk, L.P.nblk, L.R.nblk, L.AP.nblk, L.A.gnblk, L.P.gnblk,
-                           L.R.gnblk, L.AP.gnblk});
+        for (const DevCSR* M : {&L.A, &L.P, &L.R, &L.AP})
+            maxblk = std::max({maxblk, M->nblk, M->gnblk, M->lean_nblk});
     }
     H.partial_cap = std::max<int64_t>(2 * maxblk, 2 * vec_blocks(maxn)) + 16;
     H.partial.alloc(H.partial_cap);

@@ -43,7 +43,8 @@ class _Opts(ctypes.Structure):
                 ("cheb_hi", ctypes.c_double), ("direct_gathers", ctypes.c_int32),
                 ("graph_launch", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32),
-                ("row_groups", ctypes.c_int32)]
+                ("row_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("lean_max_nnz", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -72,7 +73,8 @@ class _LevelDesc(ctypes.Structure):
                 ("nnz_P", ctypes.c_int64), ("nnz_R", ctypes.c_int64),
                 ("lam_hat", ctypes.c_double), ("nnz_AP", ctypes.c_int64),
                 ("staged_nnz_A", ctypes.c_int64), ("runs_A", ctypes.c_int64),
-                ("groups_A", ctypes.c_int64), ("group_entries_A", ctypes.c_int64)]
+                ("groups_A", ctypes.c_int64), ("group_entries_A", ctypes.c_int64),
+                ("lean_A", ctypes.c_int64)]
 
 
 @dataclass
@@ -96,6 +98,7 @@ class Options:
     schedule: tuple = ()            # coarse p-orders after p, e.g. (4, 3, 2, 1); () = default
     batch_kernel: str = "auto"      # block-product shape of solve_batch: auto, lanes, wave, group
     row_groups: bool = False        # grouped product form where rows share column lists
+    lean_max_nnz: int = 2000000     # row-direct kernel for operators up to this many nonzeros
 
     def _c(self) -> _Opts:
         d = asdict(self)
@@ -108,6 +111,7 @@ class Options:
         d["direct_gathers"] = int(d["direct_gathers"])
         d["graph_launch"] = int(d["graph_launch"])
         d["row_groups"] = int(d["row_groups"])
+        d["pad"] = 0
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]
@@ -270,7 +274,8 @@ class Solver:
         return {"kind": LEVEL_KIND[d.kind], "order": d.order, "coarsest": bool(d.coarsest),
                 "rows": d.rows, "nnz_A": d.nnz_A, "nnz_P": d.nnz_P, "nnz_R": d.nnz_R,
                 "nnz_AP": d.nnz_AP, "lam_hat": d.lam_hat, "staged_nnz_A": d.staged_nnz_A,
-                "runs_A": d.runs_A, "groups_A": d.groups_A, "group_entries_A": d.group_entries_A}
+                "runs_A": d.runs_A, "groups_A": d.groups_A, "group_entries_A": d.group_entries_A,
+                "lean_A": bool(d.lean_A)}
 
     def level_csr(self, l, which="A"):
         d = self.level(l)

@@ -134,3 +134,20 @@ def test_row_groups_option_default_and_validation():
                          ctypes.byref(h))
     assert rc == giamg.EINVAL and b"row_groups" in lib.giamg_last_error()
     assert not h.value
+
+
+def test_lean_threshold_default_and_validation():
+    from paper_2512_15121_amd import giamg
+    import numpy as np
+    lib = giamg.library()
+    o = giamg._Opts()
+    lib.giamg_default_opts(ctypes.byref(o))
+    assert o.lean_max_nnz == 2000000 and giamg.Options().lean_max_nnz == 2000000
+    o.lean_max_nnz = -1
+    coords = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], dtype=np.float64)
+    l2g = np.arange(8, dtype=np.int32)[None, :]
+    h = ctypes.c_void_p()
+    rc = lib.giamg_setup(giamg._ptr(coords), 8, giamg._ptr(l2g), 1, 1, 1.0, ctypes.byref(o), None,
+                         ctypes.byref(h))
+    assert rc == giamg.EINVAL and b"lean_max_nnz" in lib.giamg_last_error()
+    assert not h.value

@@ -120,10 +120,10 @@ def test_staged_gathers_bitwise_equal_direct(torch_dev, name):
     operands and sum in the same order as direct gathers: every operator
     product, the V-cycle and the whole solve agree bit for bit."""
     torch, dev = torch_dev
-    s1 = _solver(name)
-    s2 = _solver(name, direct_gathers=True)
+    s1 = _solver(name, lean_max_nnz=0)
+    s2 = _solver(name, direct_gathers=True, lean_max_nnz=0)
     d0 = s1.level(0)
-    assert d0["groups_A"] == 0
+    assert d0["groups_A"] == 0 and not d0["lean_A"]
     assert d0["staged_nnz_A"] > 0.9 * d0["nnz_A"] and d0["runs_A"] > 0
     assert s2.level(0)["staged_nnz_A"] == 0 and s2.level(0)["runs_A"] == 0
     rng = np.random.default_rng(7)
@@ -162,8 +162,8 @@ def test_staged_gathers_bitwise_equal_direct(torch_dev, name):
 def test_staged_gathers_mixed_bitwise_equal_direct(torch_dev):
     torch, dev = torch_dev
     name = "p4_6cube_cheb_sa"
-    s1 = _solver(name, precision="mixed")
-    s2 = _solver(name, precision="mixed", direct_gathers=True)
+    s1 = _solver(name, precision="mixed", lean_max_nnz=0)
+    s2 = _solver(name, precision="mixed", direct_gathers=True, lean_max_nnz=0)
     b = _to(torch, dev, np.random.default_rng(8).standard_normal(s1.level(0)["rows"]))
     x1, i1 = s1.solve(b, tol=1e-10)
     x2, i2 = s2.solve(b, tol=1e-10)
@@ -212,8 +212,8 @@ def test_grouped_form_rows_bitwise_equal_csr(torch_dev, name):
     another order: same iterations, iterates equal to rounding."""
     torch, dev = torch_dev
     n, p, lam, sm, pert, cm, bc, basis, sched = CASES[name]
-    s1 = _solver(name, row_groups=True)
-    s2 = _solver(name)
+    s1 = _solver(name, row_groups=True, lean_max_nnz=0)
+    s2 = _solver(name, lean_max_nnz=0)
     d1, d2 = s1.level(0), s2.level(0)
     assert d2["groups_A"] == 0 and d2["group_entries_A"] == 0
     if p >= 3:   # interior, face and edge nodes share column lists
@@ -229,11 +229,50 @@ def test_grouped_form_rows_bitwise_equal_csr(torch_dev, name):
     s2.close()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_lean_form_rows_bitwise_equal_csr(torch_dev, name):
+    """Operators up to lean_max_nnz nonzeros run the row-direct kernel: every
+    level's products, transfers and V-cycle equal the CSR form's bit for bit
+    (FP64, and FP32 for the mixed hierarchy); solves agree to rounding (the
+    CG dot partials of a lean fine level add rows over other blocks)."""
+    torch, dev = torch_dev
+    s1 = _solver(name, lean_max_nnz=10 ** 9)   # every operator lean
+    s2 = _solver(name, lean_max_nnz=0)
+    assert s1.level(0)["lean_A"] and not s2.level(0)["lean_A"]
+    assert s1.level(0)["staged_nnz_A"] == 0 and s1.level(0)["runs_A"] == 0
+    _levels_bitwise(torch, dev, s1, s2)
+    b = _to(torch, dev, np.random.default_rng(14).standard_normal(s1.level(0)["rows"]))
+    x1, i1 = s1.solve(b, tol=1e-10)
+    x2, i2 = s2.solve(b, tol=1e-10)
+    assert i1.status == 0 and i2.status == 0 and abs(i1.iters - i2.iters) <= 1
+    assert torch.linalg.norm(x1 - x2) <= 1e-10 * torch.linalg.norm(x2)
+    s1.close()
+    s2.close()
+    m1 = _solver(name, precision="mixed", lean_max_nnz=10 ** 9)
+    m2 = _solver(name, precision="mixed", lean_max_nnz=0)
+    _levels_bitwise(torch, dev, m1, m2, fp32=True)
+    m1.close()
+    m2.close()
+
+
+def test_lean_threshold_picks_small_operators(torch_dev):
+    """The default threshold leaves the fine operator of a mid-size case in
+    the staged CSR form and moves the small coarse levels to the lean form."""
+    name = "p4_6cube_cheb_sa"
+    s = _solver(name)
+    levels = [s.level(l) for l in range(s.num_levels())]
+    for d in levels:
+        assert d["lean_A"] == (d["nnz_A"] <= 2000000)
+    assert not levels[0]["lean_A"] and levels[0]["staged_nnz_A"] > 0
+    assert any(d["lean_A"] for d in levels[1:])
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["p4_6cube_cheb_sa", "modal_p5_4cube_by_one"])
 def test_grouped_form_fp32_rows_bitwise_equal_csr(torch_dev, name):
     torch, dev = torch_dev
-    s1 = _solver(name, precision="mixed", row_groups=True)
-    s2 = _solver(name, precision="mixed")
+    s1 = _solver(name, precision="mixed", row_groups=True, lean_max_nnz=0)
+    s2 = _solver(name, precision="mixed", lean_max_nnz=0)
     assert s1.level(0)["groups_A"] > 0
     _levels_bitwise(torch, dev, s1, s2, fp32=True)
     b = _to(torch, dev, np.random.default_rng(13).standard_normal(s1.level(0)["rows"]))
