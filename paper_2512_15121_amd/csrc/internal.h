@@ -89,6 +89,7 @@ struct DevCSR {
     DevBuf<double> val;
     DevBuf<float> val32;
     DevBuf<int64_t> rblk;   // row blocks of the streaming product kernel
+    DevBuf<int64_t> bdesc;  // [4 * nblk] BlockDesc records of those blocks
     int64_t nblk = 0;
     int lanes = 16;
     // Staged gathers: per row block, the distinct columns its nonzeros touch,

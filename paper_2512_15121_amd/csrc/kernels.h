@@ -29,6 +29,14 @@ constexpr int LEAN_THREADS = 256;
 constexpr int CHEB_ASSIGN = 1;   // x = d_old (+ d_new) instead of x += ...
 constexpr int CHEB_LAST = 2;     // add the new direction as well (last step)
 
+// A row block of the CSR product form (DevCSR::bdesc): rows [r0, r0 + nrows)
+// with n nonzeros from base; staged blocks own runs [run0, run0 + nruns).
+struct BlockDesc {
+    int64_t base, r0;
+    int32_t nrows, n, run0, nruns;
+};
+static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout");
+
 // A block of the grouped product form (DevCSR::gblk, one more entry than
 // blocks: block b spans entries [e0, next.e0), rows [r0, next.r0) of grows
 // and groups [q0, next.q0) of ggrp; its g * E values start at v0).
@@ -54,6 +62,7 @@ struct SpmvArgs {
     T c1 = 0, c2 = 0, inv_theta = 0, omega = 0;
     int flags = 0;
     const int64_t* rblk = nullptr;   // row-block boundaries (nblk + 1 entries)
+    const BlockDesc* bdesc = nullptr;  // per row block (nblk entries)
     int64_t nblk = 0;
     int lanes = 16;                  // lanes that reduce one row (16, 4 or 1)
     const int* stop = nullptr;       // device stop flag (null: the thread's StopScope flag)

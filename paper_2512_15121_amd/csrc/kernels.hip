@@ -201,12 +201,12 @@ __device__ __forceinline__ void stage_runs(const T* __restrict__ v, int2 dsc, in
 // Staged: run table first, then values and slots, then the vector runs
 // (copied into prod), then the products (into prod).  nruns > 0.
 template <typename T>
-__device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int64_t lb, int64_t base, int n,
+__device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, int64_t base, int n,
                                                int nruns, T* prod) {
     constexpr int PER = SPMV_CAP / SPMV_THREADS;
     constexpr int NW = SPMV_THREADS / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
-    const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + a.run_ptr[lb];
+    const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + run0;
     // runs w, w + NW, ... of this wave; a staged block has at most
     // STAGE_MAX_RUNS = NW * WAVE runs, so one descriptor per lane
     const int mine = nruns > w ? (nruns - w + NW - 1) / NW : 0;
@@ -269,8 +269,11 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 }
 
 // Streaming CSR product.  A block owns a run of at most SPMV_THREADS whole
-// rows whose nonzeros (at most SPMV_CAP = 8 per thread) are contiguous:
-//  0. thread t prefetches the row-local operands of row r0 + t;
+// rows whose nonzeros (at most SPMV_CAP = 8 per thread) are contiguous, and
+// reads where they start from one 32-byte descriptor, so the value stream
+// waits on one load only:
+//  0. thread t prefetches the row-local operands of row r0 + t and the end
+//     of that row (the row sums read the row bounds from LDS);
 //  1. every thread issues its eight value loads and eight column loads at
 //     once (coalesced, non-temporal) and forms the products in LDS.  With
 //     staged gathers the block first copies the vector entries it needs
@@ -295,12 +298,12 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     if (stopped(a.stop)) return;
     __shared__ T prod[SPMV_CAP];
     __shared__ T rowsum[SPMV_THREADS];
+    __shared__ int rowoff[SPMV_THREADS + 1];
     double* red = reinterpret_cast<double*>(prod);   // reused once products are consumed
     const int tid = threadIdx.x;
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t r0 = a.rblk[lb], r1 = a.rblk[lb + 1];
-    const int64_t base = a.rp[r0];
-    const int64_t cnt = a.rp[r1] - base;
+    const BlockDesc B = a.bdesc[lb];   // one load: no dependent row-pointer reads ahead of the values
+    const int64_t r0 = B.r0, base = B.base, cnt = B.n;
     double dot = 0.0, dot2 = 0.0;
     if constexpr (STAGE != 1) {
         if (cnt > SPMV_CAP) {
@@ -332,32 +335,38 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             return;
         }
     }
-    const int nrows = (int)(r1 - r0);
+    const int nrows = B.nrows;
     const int n = (int)cnt;
-    // 0. row-local operands of this thread's row
+    // 0. row-local operands of this thread's row, and the end of that row
+    // (low word of the int64 row pointer: offsets in a block are < 2^12)
     RowIn<T> in{};
     const bool own = tid < nrows;
+    uint32_t row_end = 0;
     // (whole waves without rows skip it: a wave-uniform branch, measured 3 %
     // faster on the fine Chebyshev step than every wave loading clamped rows)
-    if ((tid / WAVE) * WAVE < nrows) epilogue_load<T, MODE>(a, r0 + min(tid, nrows - 1), in);
+    if ((tid / WAVE) * WAVE < nrows) {
+        const int64_t row = r0 + min(tid, nrows - 1);
+        epilogue_load<T, MODE>(a, row, in);
+        row_end = reinterpret_cast<const uint32_t*>(a.rp)[2 * (row + 1)];
+    }
     // 1. products into LDS
     if constexpr (STAGE == 0) {
         if (n > 0) direct_products<T>(a, base, n, prod);
     } else if constexpr (STAGE == 1) {
-        const int nruns = a.run_ptr[lb + 1] - a.run_ptr[lb];   // 0 only for blocks of empty rows
-        if (nruns > 0) stage_products<T>(a, lb, base, n, nruns, prod);
+        if (B.nruns > 0) stage_products<T>(a, B.run0, base, n, B.nruns, prod);   // 0: empty rows only
     } else {
-        const int nruns = a.run_ptr[lb + 1] - a.run_ptr[lb];
-        if (nruns > 0)
-            stage_products<T>(a, lb, base, n, nruns, prod);
+        if (B.nruns > 0)
+            stage_products<T>(a, B.run0, base, n, B.nruns, prod);
         else if (n > 0)
             direct_products<T>(a, base, n, prod);
     }
+    if (own) rowoff[tid + 1] = (int)(row_end - (uint32_t)base);
+    if (tid == 0) rowoff[0] = 0;
     __syncthreads();
     // 2. row sums, L lanes per row
     const int g = tid / L, gl = tid % L;
     for (int rr = g; rr < nrows; rr += SPMV_THREADS / L) {
-        const int s = (int)(a.rp[r0 + rr] - base), e = (int)(a.rp[r0 + rr + 1] - base);
+        const int s = rowoff[rr], e = rowoff[rr + 1];
         T acc = 0;
         for (int j = s + gl; j < e; j += L) acc += prod[j];
         acc = group_sum<L>(acc);
@@ -806,7 +815,7 @@ void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
     SpmvArgs<T> a = args;
     if (a.stop == nullptr) a.stop = g_stop;
     if (a.n <= 0 || a.nblk <= 0) return;
-    if (a.rblk == nullptr) throw Error(GIAMG_EINVAL, "operator without row blocks");
+    if (a.rblk == nullptr || a.bdesc == nullptr) throw Error(GIAMG_EINVAL, "operator without row blocks");
     switch (mode) {
         case SPMV_PLAIN: launch_spmv_mode<T, SPMV_PLAIN>(a, s); break;
         case SPMV_RESID: launch_spmv_mode<T, SPMV_RESID>(a, s); break;

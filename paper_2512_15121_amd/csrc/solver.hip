@@ -47,6 +47,28 @@ void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) 
                              hipMemcpyHostToDevice, s));
     GIAMG_HIP(hipStreamSynchronize(s));
     build_staging(d, rp, s);
+    // block descriptors (run fields from the staging tables, if any)
+    std::vector<int32_t> run_ptr;
+    if (d.run_ptr.get() != nullptr) {
+        run_ptr.resize((size_t)d.nblk + 1);
+        GIAMG_HIP(hipMemcpyAsync(run_ptr.data(), d.run_ptr.get(), run_ptr.size() * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+        GIAMG_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<BlockDesc> desc((size_t)std::max<int64_t>(d.nblk, 1));
+    for (int64_t b = 0; b < d.nblk; ++b) {
+        BlockDesc& B = desc[b];
+        B.r0 = blocks[b];
+        B.base = rp[blocks[b]];
+        B.nrows = (int32_t)(blocks[b + 1] - blocks[b]);
+        B.n = (int32_t)(rp[blocks[b + 1]] - B.base);
+        B.run0 = run_ptr.empty() ? 0 : run_ptr[b];
+        B.nruns = run_ptr.empty() ? 0 : run_ptr[b + 1] - run_ptr[b];
+    }
+    d.bdesc.alloc(4 * desc.size());
+    GIAMG_HIP(hipMemcpyAsync(d.bdesc.get(), desc.data(), desc.size() * sizeof(BlockDesc),
+                             hipMemcpyHostToDevice, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
 }
 
 void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
@@ -90,6 +112,7 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows;
     a.nnz = M.nnz; a.ncols = M.ncols;
     a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
+    a.bdesc = reinterpret_cast<const BlockDesc*>(M.bdesc.get());
     a.run_ptr = M.run_ptr.get(); a.runs = M.runs.get(); a.slot = M.slot.get();
     a.nnz_staged = M.nnz_staged; a.nruns = M.nruns;
     if (M.lean) {
@@ -410,7 +433,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
 
 int64_t handle_device_bytes(const Handle& H) {
     auto csr = [](const DevCSR& m) {
-        return (int64_t)(m.rp.n + m.rblk.n) * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 +
+        return (int64_t)(m.rp.n + m.rblk.n + m.bdesc.n) * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 +
                (int64_t)m.val32.n * 4 + (int64_t)(m.run_ptr.n + m.runs.n) * 4 + (int64_t)m.slot.n * 2 +
                (int64_t)m.gblk.n * 8 + (int64_t)(m.grows.n + m.ggrp.n + m.grun_ptr.n + m.gruns.n) * 4 +
                (int64_t)m.gslot.n * 2 + (int64_t)m.gval.n * 8 + (int64_t)m.gval32.n * 4;
