@@ -16,6 +16,8 @@ enum SpmvMode : int {
     SPMV_DOT = 6,        // y = A v, block partials of v . y
     SPMV_DINV = 7,       // y = dinv A v
     SPMV_RINIT = 8,      // y = f - A v, block partials of f . f and y . y
+    SPMV_RCHEB0 = 9,     // restriction fused with the next level's zero-start Chebyshev
+                         // init: y = A v, r = dinv y, x = r / theta (x holds d_0)
 };
 
 // Nonzeros one block stages in LDS; rows longer than this get a block each.
@@ -167,6 +169,11 @@ private:
 };
 void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const double* p,
                        const double* q, const double* scal, double* partial, hipStream_t s);
+// The same update fused with the fine level's zero-start Chebyshev init of
+// the next preconditioning: cr = dinv r_new, cd = cr inv_theta.
+void launch_pcg_update_cheb0(int64_t n, double* x, double* r, const double* p, const double* q,
+                             const double* scal, double* partial, const double* dinv, double* cr,
+                             double* cd, double inv_theta, hipStream_t s);
 void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s);
 void launch_power_start(int64_t n, double* v, hipStream_t s);
 void launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);

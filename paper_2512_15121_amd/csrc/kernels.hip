@@ -96,7 +96,7 @@ __device__ __forceinline__ void epilogue_load(const SpmvArgs<T>& a, int64_t row,
                   MODE == SPMV_RINIT)
         in.f = a.f[row];
     if constexpr (MODE == SPMV_CHEB_INIT || MODE == SPMV_CHEB_STEP || MODE == SPMV_JACOBI ||
-                  MODE == SPMV_DINV)
+                  MODE == SPMV_DINV || MODE == SPMV_RCHEB0)
         in.dinv = a.dinv[row];
     if constexpr (MODE == SPMV_CHEB_STEP) {
         in.r = a.r[row];
@@ -129,6 +129,11 @@ __device__ __forceinline__ void epilogue_store(const SpmvArgs<T>& a, int64_t row
         a.y[row] = dn;
         const T inc = (a.flags & CHEB_LAST) ? in.v + dn : in.v;
         a.x[row] = in.x + inc;
+    } else if constexpr (MODE == SPMV_RCHEB0) {
+        a.y[row] = y;
+        const T res = in.dinv * y;
+        a.r[row] = res;
+        a.x[row] = res * a.inv_theta;
     } else if constexpr (MODE == SPMV_JACOBI) {
         a.y[row] = in.v + a.omega * in.dinv * (in.f - y);
     } else if constexpr (MODE == SPMV_DOT) {
@@ -826,6 +831,7 @@ void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
         case SPMV_DOT: launch_spmv_mode<T, SPMV_DOT>(a, s); break;
         case SPMV_DINV: launch_spmv_mode<T, SPMV_DINV>(a, s); break;
         case SPMV_RINIT: launch_spmv_mode<T, SPMV_RINIT>(a, s); break;
+        case SPMV_RCHEB0: launch_spmv_mode<T, SPMV_RCHEB0>(a, s); break;
         default: throw Error(GIAMG_EINVAL, "unknown product mode");
     }
     GIAMG_HIP(hipGetLastError());
@@ -1150,6 +1156,36 @@ void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const doub
                        const double* q, const double* scal, double* partial, hipStream_t s) {
     pcg_update_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, x, r, rold, p, q, scal, partial,
                                                                     g_stop);
+    GIAMG_HIP(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(VEC_THREADS) pcg_update_cheb0_kernel(
+    int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ q, const double* __restrict__ scal, double* __restrict__ partial,
+    const double* __restrict__ dinv, double* __restrict__ cr, double* __restrict__ cd, double inv_theta,
+    const int* stop) {
+    if (stopped(stop)) return;
+    __shared__ double sh[VEC_THREADS];
+    const double alpha = scal[S_ALPHA];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * VEC_THREADS) {
+        x[i] += alpha * p[i];
+        const double rn = r[i] - alpha * q[i];
+        r[i] = rn;
+        s += rn * rn;
+        const double res = dinv[i] * rn;   // the operations of cheb_init0_kernel
+        cr[i] = res;
+        cd[i] = res * inv_theta;
+    }
+    s = block_sum<VEC_THREADS>(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+void launch_pcg_update_cheb0(int64_t n, double* x, double* r, const double* p, const double* q,
+                             const double* scal, double* partial, const double* dinv, double* cr,
+                             double* cd, double inv_theta, hipStream_t s) {
+    pcg_update_cheb0_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, x, r, p, q, scal, partial,
+                                                                          dinv, cr, cd, inv_theta, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 

@@ -505,6 +505,8 @@ double spmv_bytes(int mode, const SpmvArgs<T>& a) {
         case SPMV_JACOBI: rows = 3; break;            // f, dinv, y
         case SPMV_DOT: rows = 1; break;               // y
         case SPMV_DINV: rows = 2; break;              // dinv, y
+        case SPMV_RINIT: rows = 2; break;             // f, y
+        case SPMV_RCHEB0: rows = 4; break;            // dinv, y, r, d_0
     }
     if (a.gblk != nullptr)   // grouped: slots per entry, block records, row list, group table
         return vb * a.nnz + 2.0 * a.gentries + 8.0 * a.gnruns + (4.0 + 32.0) * (a.nblk + 1) + 4.0 * a.n +
@@ -548,21 +550,24 @@ ChebCoef cheb_coef(const Handle& H, const Level& L) {
 //   d_{j+1} = rho_{j+1} rho_j d_j + (2 rho_{j+1} / delta) r_{j+1}.
 // The update of x by d_j is deferred into the next product's epilogue (the
 // product gathers d, never x), so no kernel reads and writes x at once.
-// zero_start: pre-smoothing from x = 0 (x is not read).
+// zero_start: pre-smoothing from x = 0 (x is not read); init_done: the
+// kernel that produced f already wrote r_0 and d_0 (fused_init_ok).
 // Post-smoothing after a coarse correction x = x' + P e may pass the residual
 // t = f - A x' from before the correction and the coarse vector e: then
 // f - A x = t - (A P) e, a product with A P, whose rows are several times
 // shorter than those of A on the p-levels.
 template <typename T>
 void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start,
-                      const T* t = nullptr, const T* e = nullptr) {
+                      const T* t = nullptr, const T* e = nullptr, bool init_done = false) {
     const int k = H.opts.degree;
     const ChebCoef c = cheb_coef(H, L);
     T* r = LV<T>::r(L);
     T* d[2] = {LV<T>::d0(L), LV<T>::d1(L)};
     if (zero_start) {
-        H.bytes += (k == 1 ? 5.0 : 4.0) * sizeof(T) * L.n;
-        launch_cheb_init0<T>(L.n, f, LV<T>::dinv(L), r, d[0], x, (T)c.inv_theta, k == 1, H.stream);
+        if (!init_done) {
+            H.bytes += (k == 1 ? 5.0 : 4.0) * sizeof(T) * L.n;
+            launch_cheb_init0<T>(L.n, f, LV<T>::dinv(L), r, d[0], x, (T)c.inv_theta, k == 1, H.stream);
+        }
     } else if (e != nullptr) {
         SpmvArgs<T> a = args_of<T>(L.AP, LV<T>::AP(L));
         a.dinv = LV<T>::dinv(L);
@@ -588,6 +593,13 @@ void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start,
         a.flags = (j == k - 1 ? CHEB_LAST : 0) | ((zero_start && j == 1) ? CHEB_ASSIGN : 0);
         run_spmv(H, SPMV_CHEB_STEP, a);
     }
+}
+
+// Fused inits for the Chebyshev smoother with degree >= 2: the restriction
+// writes the next level's r_0, d_0 and the CG update the fine level's (the
+// same operations as cheb_init0_kernel, so the same bits).
+bool fused_init_ok(const Handle& H) {
+    return H.opts.smoother == GIAMG_SMOOTHER_CHEBYSHEV && H.opts.degree >= 2;
 }
 
 // Weighted Jacobi x <- x + omega D^-1 (f - A x), ping-pong between x and d0.
@@ -616,9 +628,9 @@ void smooth_jacobi(Handle& H, Level& L, const T* f, T* x, bool zero_start) {
 
 template <typename T>
 void smooth(Handle& H, Level& L, const T* f, T* x, bool zero_start, const T* t = nullptr,
-            const T* e = nullptr) {
+            const T* e = nullptr, bool init_done = false) {
     if (H.opts.smoother == GIAMG_SMOOTHER_CHEBYSHEV)
-        smooth_chebyshev<T>(H, L, f, x, zero_start, t, e);
+        smooth_chebyshev<T>(H, L, f, x, zero_start, t, e, init_done);
     else
         smooth_jacobi<T>(H, L, f, x, zero_start);
 }
@@ -637,6 +649,16 @@ void restrict_to(Handle& H, Level& L, const T* r, T* fc) {
     run_spmv(H, SPMV_PLAIN, a);
 }
 
+// Restriction fused with the zero-start Chebyshev init of level C.
+template <typename T>
+void restrict_cheb0(Handle& H, Level& L, Level& C, const T* r) {
+    SpmvArgs<T> a = args_of<T>(L.R, LV<T>::R(L));
+    a.v = r; a.y = LV<T>::f(C); a.dinv = LV<T>::dinv(C);
+    a.r = LV<T>::r(C); a.x = LV<T>::d0(C);
+    a.inv_theta = (T)cheb_coef(H, C).inv_theta;
+    run_spmv(H, SPMV_RCHEB0, a);
+}
+
 template <typename T>
 void prolong_add(Handle& H, Level& L, const T* ec, T* x) {
     SpmvArgs<T> a = args_of<T>(L.P, LV<T>::P(L));
@@ -645,8 +667,9 @@ void prolong_add(Handle& H, Level& L, const T* ec, T* x) {
 }
 
 // Algorithm 1: one V-cycle from level l for right-hand side f, result in x.
+// init_done: level l's zero-start smoother init was written with f (fused).
 template <typename T>
-void vcycle(Handle& H, size_t l, const T* f, T* x) {
+void vcycle(Handle& H, size_t l, const T* f, T* x, bool init_done = false) {
     Level& L = H.levels[l];
     if (l + 1 == H.levels.size()) {
         H.bytes += 8.0 * H.nc * H.nc + 2.0 * sizeof(T) * H.nc;
@@ -654,15 +677,21 @@ void vcycle(Handle& H, size_t l, const T* f, T* x) {
         return;
     }
     Level& C = H.levels[l + 1];
-    smooth<T>(H, L, f, x, true);
+    smooth<T>(H, L, f, x, true, nullptr, nullptr, init_done);
     residual<T>(H, L, f, x, LV<T>::t(L));
-    restrict_to<T>(H, L, LV<T>::t(L), LV<T>::f(C));
-    vcycle<T>(H, l + 1, LV<T>::f(C), LV<T>::x(C));
+    const bool fuse = fused_init_ok(H) && l + 2 < H.levels.size();
+    if (fuse)
+        restrict_cheb0<T>(H, L, C, LV<T>::t(L));
+    else
+        restrict_to<T>(H, L, LV<T>::t(L), LV<T>::f(C));
+    vcycle<T>(H, l + 1, LV<T>::f(C), LV<T>::x(C), fuse);
     prolong_add<T>(H, L, LV<T>::x(C), x);
     smooth<T>(H, L, f, x, false, LV<T>::t(L), LV<T>::x(C));
 }
 
-void precondition(Handle& H, const double* r, double* z) {
+// z = V-cycle(r).  init_done (FP64 only): the fine level's smoother init was
+// fused into the CG update.
+void precondition(Handle& H, const double* r, double* z, bool init_done = false) {
     if (H.opts.precision == GIAMG_PREC_MIXED) {
         Level& L = H.levels[0];
         H.bytes += 24.0 * L.n;   // two conversions at the cycle boundary
@@ -670,7 +699,7 @@ void precondition(Handle& H, const double* r, double* z) {
         vcycle<float>(H, 0, L.f32.get(), L.x32.get());
         launch_convert<float, double>(L.n, L.x32.get(), z, H.stream);
     } else {
-        vcycle<double>(H, 0, r, z);
+        vcycle<double>(H, 0, r, z, init_done);
     }
 }
 
@@ -745,6 +774,10 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             // The iterate lives in the handle's x (copied in and out), so the
             // graph's pointers never change.
             const bool graph = H.opts.graph_launch != 0;
+            // FP64 with the Chebyshev smoother (degree >= 2): the fine
+            // level's smoother init rides on the CG update (bitwise the same
+            // vectors)
+            const bool fused = !flexible && fused_init_ok(H) && H.levels.size() > 1;
             double* xi = H.x.get();
             H.bytes += 16.0 * n;
             launch_copy<double>(n, x, xi, s);
@@ -756,12 +789,20 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 H.bytes += (flexible ? 56.0 : 48.0) * n;
                 run_spmv(H, SPMV_DOT, a);
                 launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, st, FIN_ALPHA, H.scal.get());
-                launch_pcg_update(n, xi, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
-                                  H.q.get(), H.scal.get(), H.partial.get(), st);
+                if (fused) {   // the update also writes level 0's Chebyshev r_0, d_0
+                    Level& F = H.levels[0];
+                    H.bytes += 24.0 * n;
+                    launch_pcg_update_cheb0(n, xi, H.r.get(), H.p.get(), H.q.get(), H.scal.get(),
+                                            H.partial.get(), F.dinv.get(), F.r.get(), F.d0.get(),
+                                            cheb_coef(H, F).inv_theta, st);
+                } else {
+                    launch_pcg_update(n, xi, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
+                                      H.q.get(), H.scal.get(), H.partial.get(), st);
+                }
                 launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, st, FIN_CONV,
                               H.scal.get(), H.ctl.get());
                 const double b1 = H.bytes;
-                precondition(H, H.r.get(), H.z.get());
+                precondition(H, H.r.get(), H.z.get(), fused);
                 if (flexible) {
                     H.bytes += 24.0 * n;
                     launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), st);
