@@ -118,6 +118,12 @@ typedef struct giamg_opts {
                               than the blocked, staged form, for the small coarse levels
                               (same rows, bit for bit; CG dot partials over other
                               blocks).  0: never.  Default 2000000 */
+    int32_t  keep_boundary; /* 1: the coarse p-levels keep the constrained nodes (the fine
+                              identity rows enter the Galerkin products as P_B^T P_B): the
+                              reading under which 2^3 elements at p = 8 give the coarsest
+                              level of Table 1, 27 rows / 343 nonzeros.  Default 0: coarse
+                              levels hold the free nodes only */
+    int32_t  pad2;
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */

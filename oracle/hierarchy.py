@@ -58,6 +58,7 @@ class Options:
     cheb_hi: float = 1.1
     basis: str = "nodal"            # or "modal" (appendix basis, injection P)
     schedule: Optional[List[int]] = None   # coarse orders after p (default q = p / spf(p))
+    keep_boundary: bool = False     # coarse p-levels keep the constrained nodes (see build)
 
 
 @dataclass
@@ -72,7 +73,13 @@ def build(coords, l2g, p, lam, opts: Options = None) -> Hierarchy:
     n = coords.shape[0]
     A, cons = assembly.assemble(coords, l2g, p, lam, bc=opts.bc, pin=opts.pin, basis=opts.basis)
     H = Hierarchy(opts=opts, constrained=cons)
-    free = ~cons
+    # The paper says boundary nodes need care but not how (Section 2.2.2).
+    # Default reading: coarse levels hold the free nodes only (P has empty
+    # rows for constrained fine nodes).  keep_boundary: every node passes to
+    # the coarse levels, the fine identity rows entering the Galerkin product
+    # as P_B^T P_B; on 2^3 elements at p = 8 this gives Table 1's coarsest
+    # level of 27 rows and 343 nonzeros.
+    free = np.ones(n, dtype=bool) if opts.keep_boundary else ~cons
     cur_l2g = l2g
     orders = ptransfer.p_schedule(p, opts.schedule)
     level = Level(A=A, kind="p", order=p, l2g=l2g)

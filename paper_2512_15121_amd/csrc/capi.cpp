@@ -89,6 +89,8 @@ void giamg_default_opts(giamg_opts* o) {
     o->row_groups = 0;
     o->pad = 0;
     o->lean_max_nnz = 2000000;
+    o->keep_boundary = 0;
+    o->pad2 = 0;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -125,6 +127,7 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
                       "unknown batch_kernel");
         GIAMG_REQUIRE(o.row_groups == 0 || o.row_groups == 1, "row_groups must be 0 or 1");
         GIAMG_REQUIRE(o.lean_max_nnz >= 0, "lean_max_nnz must be >= 0");
+        GIAMG_REQUIRE(o.keep_boundary == 0 || o.keep_boundary == 1, "keep_boundary must be 0 or 1");
         {
             int prev = p;
             for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {

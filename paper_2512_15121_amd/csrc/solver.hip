@@ -282,7 +282,8 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     A0 = HostCSR();
     // p-levels
     std::vector<uint8_t> free_mask(n);
-    for (int64_t i = 0; i < n; ++i) free_mask[i] = !H.constrained[i];
+    // keep_boundary: constrained fine nodes pass to the coarse levels too
+    for (int64_t i = 0; i < n; ++i) free_mask[i] = o.keep_boundary ? 1 : !H.constrained[i];
     int order = H.porder;
     const bool explicit_schedule = o.schedule[0] != 0;
     for (int step = 0; order > 1 && (int)H.levels.size() < o.max_levels; ++step) {

@@ -44,7 +44,8 @@ class _Opts(ctypes.Structure):
                 ("graph_launch", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32),
                 ("row_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("lean_max_nnz", ctypes.c_int64)]
+                ("lean_max_nnz", ctypes.c_int64), ("keep_boundary", ctypes.c_int32),
+                ("pad2", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -99,6 +100,7 @@ class Options:
     batch_kernel: str = "auto"      # block-product shape of solve_batch: auto, lanes, wave, group
     row_groups: bool = False        # grouped product form where rows share column lists
     lean_max_nnz: int = 2000000     # row-direct kernel for operators up to this many nonzeros
+    keep_boundary: bool = False     # coarse p-levels keep the constrained nodes
 
     def _c(self) -> _Opts:
         d = asdict(self)
@@ -112,6 +114,8 @@ class Options:
         d["graph_launch"] = int(d["graph_launch"])
         d["row_groups"] = int(d["row_groups"])
         d["pad"] = 0
+        d["pad2"] = 0
+        d["keep_boundary"] = int(d["keep_boundary"])
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]

@@ -76,6 +76,30 @@ def test_table1_coarsest_level_pin():
     assert A.shape == (crow, crow) and A.nnz == cnnz
 
 
+def test_table1_hierarchy_with_boundary_kept():
+    """The whole p-hierarchy on Table 1's mesh: with the constrained nodes
+    kept on the coarse levels, p = 8 -> 4 -> 2 -> 1 gives 4 levels whose
+    coarsest has 27 rows and 343 nonzeros, as printed; the default reading
+    (free nodes only) leaves 1 row there."""
+    from oracle import hierarchy
+    rows = [l for l in open(os.path.join(GOLDEN, "table1_giamg_hierarchy.txt"))
+            if l.strip() and not l.startswith("#")]
+    order, nel, levels, crow, cnnz = map(int, rows[0].split())
+    m = synth.hex_mesh(nel, order, perturb=0.1, seed=3)
+    opts = hierarchy.Options(smoother="chebyshev", degree=3, keep_boundary=True)
+    H = hierarchy.build(m.coords, m.l2g, order, 1.0, opts)
+    assert len(H.levels) == levels and [lv.order for lv in H.levels] == [8, 4, 2, 1]
+    assert [lv.A.shape[0] for lv in H.levels] == [(nel * q + 1) ** 3 for q in (8, 4, 2, 1)]
+    assert H.levels[-1].A.shape == (crow, crow) and H.levels[-1].A.nnz == cnnz
+    # every coarse operator is symmetric positive definite
+    for lv in H.levels[1:]:
+        D = lv.A.toarray()
+        assert np.max(np.abs(D - D.T)) <= 1e-13 * np.max(np.abs(D))
+        assert np.linalg.eigvalsh(D).min() > 0
+    H0 = hierarchy.build(m.coords, m.l2g, order, 1.0, hierarchy.Options(smoother="chebyshev", degree=3))
+    assert H0.levels[-1].A.shape == (1, 1)
+
+
 @pytest.mark.parametrize("n,p,lam", [(2, 1, 1.0), (3, 2, 0.5), (2, 3, 10.0)])
 def test_kronecker_sum_uniform(n, p, lam):
     m = synth.hex_mesh(n, p)
