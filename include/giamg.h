@@ -129,6 +129,26 @@ typedef struct giamg_opts {
 /* Fill *opts with the defaults listed above. */
 void giamg_default_opts(giamg_opts* opts);
 
+/*
+ * giamg_set_allocator -- route the library's device memory through the
+ * caller's allocator (e.g. the caching allocator of a framework that owns
+ * the device memory of the process).
+ *
+ * alloc(bytes, stream, ctx) returns device memory of at least `bytes` bytes
+ * (256-byte aligned) or NULL; `stream` is the hipStream_t of the handle
+ * whose call allocates (NULL = the null stream).  release(ptr, ctx) returns
+ * a block; the library first synchronises the block's stream, so a block
+ * comes back only when no work of the library on that stream uses it.  Both
+ * may be called from the library's own threads (the server's loop and
+ * setup worker).  alloc == NULL restores hipMalloc / hipFree.  The
+ * registration is process-wide and applies to allocations made after it;
+ * every block is released through the allocator it came from.  Returns
+ * GIAMG_OK, or GIAMG_EINVAL when exactly one of alloc and release is NULL.
+ */
+typedef void* (*giamg_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*giamg_release_fn)(void* ptr, void* ctx);
+int giamg_set_allocator(giamg_alloc_fn alloc, giamg_release_fn release, void* ctx);
+
 typedef struct giamg_s* giamg_handle;   /* opaque, owned by the library */
 
 typedef struct giamg_info {

@@ -1012,6 +1012,7 @@ void tune_all(Handle& H, BatchState& B, int k) {
 }  // namespace
 
 int solve_batch(Handle& H, const double* Bm, double* X, int32_t k, double tol, giamg_info* infos) {
+    AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(k <= MAX_K, "at most 1024 right-hand sides per call");
     ensure_state(H, k);
     BatchState& B = *H.batch;
@@ -1160,6 +1161,7 @@ struct Session {
 };
 
 Session* session_create(Handle& H, int k, double tol) {
+    AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(k >= 1 && k <= MAX_K, "slots must be in [1, 1024]");
     std::unique_ptr<Session> S(new Session());
     S->H = &H;

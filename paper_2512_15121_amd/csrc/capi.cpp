@@ -35,6 +35,52 @@ std::string& last_error() {
     thread_local std::string msg;
     return msg;
 }
+
+// ---- device memory (allocator registration) --------------------------------
+namespace {
+std::mutex& allocator_mutex() {
+    static std::mutex m;
+    return m;
+}
+Allocator& allocator_slot() {
+    static Allocator a;
+    return a;
+}
+thread_local hipStream_t t_alloc_stream = nullptr;
+}  // namespace
+
+Allocator registered_allocator() {
+    std::lock_guard<std::mutex> lock(allocator_mutex());
+    return allocator_slot();
+}
+
+hipStream_t alloc_stream() { return t_alloc_stream; }
+AllocStreamScope::AllocStreamScope(hipStream_t s) : prev_(t_alloc_stream) { t_alloc_stream = s; }
+AllocStreamScope::~AllocStreamScope() { t_alloc_stream = prev_; }
+
+void* device_alloc(size_t bytes, Allocator& a, hipStream_t& s) {
+    a = registered_allocator();
+    s = t_alloc_stream;
+    void* p = nullptr;
+    if (a.alloc != nullptr) {
+        p = a.alloc(bytes, reinterpret_cast<void*>(s), a.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p == nullptr)
+        throw Error(GIAMG_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+}
+
+void device_release(void* p, const Allocator& a, hipStream_t s) {
+    if (a.release != nullptr) {
+        (void)hipStreamSynchronize(s);
+        a.release(p, a.ctx);
+    } else {
+        (void)hipFree(p);
+    }
+}
 }  // namespace giamg
 
 namespace {
@@ -65,6 +111,16 @@ int bind_device(giamg_s* h) {
 }  // namespace
 
 extern "C" {
+
+int giamg_set_allocator(giamg_alloc_fn alloc, giamg_release_fn release, void* ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) {
+        giamg::last_error() = "alloc and release must both be set or both be NULL";
+        return GIAMG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(giamg::allocator_mutex());
+    giamg::allocator_slot() = giamg::Allocator{alloc, release, alloc ? ctx : nullptr};
+    return GIAMG_OK;
+}
 
 void giamg_default_opts(giamg_opts* o) {
     if (!o) return;

@@ -36,35 +36,64 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ---- device memory ----------------------------------------------------------
+// Device allocations go through the allocator registered with
+// giamg_set_allocator, or hipMalloc / hipFree when none is.  A buffer keeps
+// the allocator it came from (changing the registration later does not
+// affect it) and the stream it was allocated for: the stream of the handle
+// whose call allocates (AllocStreamScope), else the null stream.
+struct Allocator {
+    giamg_alloc_fn alloc = nullptr;     // null: hipMalloc / hipFree
+    giamg_release_fn release = nullptr;
+    void* ctx = nullptr;
+};
+Allocator registered_allocator();
+hipStream_t alloc_stream();
+class AllocStreamScope {
+public:
+    explicit AllocStreamScope(hipStream_t s);
+    ~AllocStreamScope();
+    AllocStreamScope(const AllocStreamScope&) = delete;
+    AllocStreamScope& operator=(const AllocStreamScope&) = delete;
+private:
+    hipStream_t prev_;
+};
+// Throws GIAMG_ENOMEM on failure; `a` and `s` receive the allocator and
+// stream to hand back to device_release.
+void* device_alloc(size_t bytes, Allocator& a, hipStream_t& s);
+void device_release(void* p, const Allocator& a, hipStream_t s);
+
 // Owning device buffer; allocation failures raise GIAMG_ENOMEM.
 template <typename T>
 struct DevBuf {
     T* ptr = nullptr;
     size_t n = 0;
+    Allocator owner;
+    hipStream_t stream = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n) { o.ptr = nullptr; o.n = 0; }
+    DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n), owner(o.owner), stream(o.stream) {
+        o.ptr = nullptr;
+        o.n = 0;
+    }
     DevBuf& operator=(DevBuf&& o) noexcept {
-        if (this != &o) { release(); ptr = o.ptr; n = o.n; o.ptr = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            ptr = o.ptr; n = o.n; owner = o.owner; stream = o.stream;
+            o.ptr = nullptr; o.n = 0;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
-        n = count;
         if (count == 0) return;
-        if (hipMalloc(reinterpret_cast<void**>(&ptr), count * sizeof(T)) != hipSuccess) {
-            ptr = nullptr;
-            n = 0;
-            (void)hipGetLastError();
-            throw Error(GIAMG_ENOMEM, "device allocation of " +
-                                          std::to_string(count * sizeof(T)) + " bytes failed");
-        }
+        ptr = static_cast<T*>(device_alloc(count * sizeof(T), owner, stream));
+        n = count;
     }
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) device_release(ptr, owner, stream);
         ptr = nullptr;
         n = 0;
     }

@@ -249,6 +249,7 @@ void alloc_level_vectors(Level& L, bool mixed) {
 }  // namespace
 
 void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
+    AllocStreamScope alloc_scope(H.stream);
     const giamg_opts& o = H.opts;
     const bool mixed = o.precision == GIAMG_PREC_MIXED;
     const int64_t n = H.n_nodes, ne = H.n_elem;
@@ -724,6 +725,7 @@ void fetch_scalars(Handle& H) {
 // CG preconditioned by the V-cycle
 // ---------------------------------------------------------------------------
 int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
+    AllocStreamScope alloc_scope(H.stream);
     const int64_t n = H.n_nodes;
     const Level& L0 = H.levels[0];
     const bool flexible = H.opts.precision == GIAMG_PREC_MIXED;
@@ -976,6 +978,7 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
 }  // namespace
 
 void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes) {
+    AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
     GIAMG_REQUIRE(reps >= 1, "reps must be >= 1");
     if (kernel & GIAMG_OP_FP32) {
@@ -1029,6 +1032,7 @@ void apply_t(Handle& H, int op, size_t l, const T* a, const T* b, T* out) {
 }  // namespace
 
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out) {
+    AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
     if (op & GIAMG_OP_FP32) {
         GIAMG_REQUIRE(H.opts.precision == GIAMG_PREC_MIXED, "FP32 operators exist only in mixed mode");

@@ -136,7 +136,11 @@ _lib = None
 
 P = ctypes.c_void_p
 I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _SIGNATURES = {
+    "giamg_set_allocator": (I32, [ALLOC_FN, RELEASE_FN, P]),
     "giamg_default_opts": (None, [ctypes.POINTER(_Opts)]),
     "giamg_setup": (I32, [P, I64, P, I64, I32, F64, ctypes.POINTER(_Opts), P, ctypes.POINTER(P)]),
     "giamg_free": (None, [P]),
@@ -191,6 +195,45 @@ def library() -> ctypes.CDLL:
             fn.argtypes = args
         _lib = lib
     return _lib
+
+
+_allocator_refs = None   # the registered callbacks, kept alive while registered
+
+
+def set_allocator(alloc=None, release=None):
+    """Route the library's device memory through alloc(bytes, stream) -> int
+    and release(ptr) (Python callables; stream is the hipStream_t as an int,
+    0 for the null stream).  With no arguments hipMalloc / hipFree return.
+    Blocks allocated before a change go back through the allocator they
+    came from."""
+    global _allocator_refs
+    lib = library()
+    if alloc is None and release is None:
+        _check(lib.giamg_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:   # reported to the library as an allocation failure
+            return None
+
+    def _release(ptr, ctx):
+        release(int(ptr))
+
+    refs = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+    _check(lib.giamg_set_allocator(refs[0], refs[1], None))
+    # keep the previous callbacks alive too: blocks they allocated are
+    # released through them
+    _allocator_refs = (refs, _allocator_refs)
+
+
+def use_torch_allocator(device=0):
+    """Take the library's device memory from torch's caching allocator on
+    `device` (the stream of the allocating handle is passed along)."""
+    import torch
+    set_allocator(lambda n, s: torch.cuda.caching_allocator_alloc(n, device, s),
+                  lambda p: torch.cuda.caching_allocator_delete(p))
 
 
 def _check(rc):

@@ -151,3 +151,12 @@ def test_lean_threshold_default_and_validation():
                          ctypes.byref(h))
     assert rc == giamg.EINVAL and b"lean_max_nnz" in lib.giamg_last_error()
     assert not h.value
+
+
+def test_set_allocator_validation_without_device_work():
+    from paper_2512_15121_amd import giamg
+    lib = giamg.library()
+    rc = lib.giamg_set_allocator(giamg.ALLOC_FN(lambda n, s, c: None), giamg.RELEASE_FN(), None)
+    assert rc == giamg.EINVAL and b"both" in lib.giamg_last_error()
+    giamg.set_allocator(lambda n, s: 0, lambda p: None)   # registering touches no device
+    giamg.set_allocator()
