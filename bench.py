@@ -12,7 +12,8 @@ CG from x = 0 to the tolerance); the hierarchy is built once before timing
 
 Prints one JSON line.  Options: --gpus (1 only), --steps, --warmup,
 --workload {helmholtz16_p4,helmholtz32_p4}, --no-cpu-baseline, --no-mixed, --no-modal, --no-batched,
---serving {small,medium,full,off}.
+--serving {small,medium,full,off}; diagnostic runs (their own JSON line):
+--study, --batched-only, --pmc-probe.
 """
 import argparse
 import numpy as np
@@ -331,6 +332,9 @@ def main():
                     help="only run the parameter studies at p = 5 (Chebyshev degree x "
                          "p-schedule x basis) and print them as one JSON line")
     ap.add_argument("--serving", default="small", choices=["small", "medium", "full", "off"])
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched leg (64 right-hand sides, 20^3 p = 3) and print "
+                         "it as one JSON line (for kernel traces of the block products)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch a 1 GiB copy (3x) and the fine Chebyshev step (5x), "
                          "for hardware-counter runs")
@@ -347,6 +351,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.study:
         print(json.dumps({"study": study(torch, Solver, Options)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(torch, Solver, Options)}), flush=True)
         return
     mesh, b, lam, w = problem(args.workload)
     if args.pmc_probe:
