@@ -277,8 +277,8 @@ int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out) {
         out->nnz_R = L.R.nnz;
         out->lam_hat = L.lam_hat;
         out->nnz_AP = L.AP.nnz;
-        out->staged_nnz_A = L.A.nnz_staged;
-        out->runs_A = L.A.nruns;
+        out->staged_nnz_A = L.A.blk.nnz_staged;
+        out->runs_A = L.A.blk.nruns;
         out->groups_A = L.A.gnblk > 0 ? L.A.ggroups : 0;
         out->group_entries_A = L.A.gnblk > 0 ? L.A.gentries : 0;
         out->lean_A = L.A.lean ? 1 : 0;

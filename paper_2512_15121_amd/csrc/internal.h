@@ -109,24 +109,42 @@ struct HostCSR {
     int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
 };
 
+// Row blocks of the streaming product for one capacity (nonzeros per block):
+// bounds, descriptors and the staged-gather tables (per row block, the
+// distinct columns its nonzeros touch, as runs of consecutive columns that
+// the product loads into LDS first).
+struct RowBlocks {
+    int cap = 0;
+    DevBuf<int64_t> rblk;     // [nblk + 1] first row of each block
+    DevBuf<int64_t> bdesc;    // [4 * nblk] BlockDesc records
+    int64_t nblk = 0;
+    DevBuf<int32_t> run_ptr;  // [nblk + 1] offsets into runs; a block with 0 runs gathers directly
+    DevBuf<int32_t> runs;     // [2 * nruns] (first column, LDS slot | length << 16)
+    DevBuf<uint16_t> slot;    // [nnz] LDS slot of each nonzero's column within its block
+    int64_t nruns = 0, nnz_staged = 0;
+    void release_staging() {
+        run_ptr.release();
+        runs.release();
+        slot.release();
+        nruns = nnz_staged = 0;
+    }
+    int64_t device_bytes() const {
+        return (int64_t)(rblk.n + bdesc.n) * 8 + (int64_t)(run_ptr.n + runs.n) * 4 + (int64_t)slot.n * 2;
+    }
+};
+
 // Device CSR: int64 row pointers, int32 ascending columns, FP64 values and an
-// optional FP32 copy of the values sharing the same index arrays.
+// optional FP32 copy of the values sharing the same index arrays.  The FP32
+// products use blocks of twice the nonzeros (the same LDS bytes).
 struct DevCSR {
     int64_t nrows = 0, ncols = 0, nnz = 0;
     DevBuf<int64_t> rp;
     DevBuf<int32_t> ci;
     DevBuf<double> val;
     DevBuf<float> val32;
-    DevBuf<int64_t> rblk;   // row blocks of the streaming product kernel
-    DevBuf<int64_t> bdesc;  // [4 * nblk] BlockDesc records of those blocks
-    int64_t nblk = 0;
-    int lanes = 16;
-    // Staged gathers: per row block, the distinct columns its nonzeros touch,
-    // as runs of consecutive columns that the product loads into LDS first.
-    DevBuf<int32_t> run_ptr;  // [nblk + 1] offsets into runs; a block with 0 runs gathers directly
-    DevBuf<int32_t> runs;     // [2 * nruns] (first column, LDS slot | length << 16)
-    DevBuf<uint16_t> slot;    // [nnz] LDS slot of each nonzero's column within its block
-    int64_t nruns = 0, nnz_staged = 0;
+    int lanes = 16;           // lanes per row of the row sums (mean row length)
+    RowBlocks blk;            // FP64 products: SPMV_CAP nonzeros per block
+    RowBlocks blk32;          // FP32 products: SPMV_CAP32 per block (built with val32)
     // Grouped form: rows with identical column lists share one list of LDS
     // slots (a group, at most 8 rows); a block holds groups of one size g and
     // stores its values as g planes (plane i: row i of every group, entry by
@@ -151,8 +169,10 @@ struct DevCSR {
         grun_ptr.release(); gruns.release(); gval.release(); gval32.release();
     }
 };
-// Build the row blocks of d from a host copy of its row pointers.
+// Build the FP64 row blocks of d (and its lanes) from a host copy of its row
+// pointers; setup_row_blocks32 builds the FP32 ones.
 void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
+void setup_row_blocks32(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
 
 // ---- the hierarchy ----------------------------------------------------------
 struct BatchState;                 // batched-solve workspace (batch.hip)

@@ -22,7 +22,10 @@ enum SpmvMode : int {
 
 // Nonzeros one block stages in LDS; rows longer than this get a block each.
 constexpr int SPMV_CAP = 4096;
+constexpr int SPMV_CAP32 = 8192;   // FP32 products: the same LDS bytes per block
 constexpr int SPMV_THREADS = 512;
+template <typename T>
+constexpr int spmv_cap() { return sizeof(T) == 4 ? SPMV_CAP32 : SPMV_CAP; }
 // Lean form (small operators): threads per block; a block holds
 // LEAN_THREADS / L rows.
 constexpr int LEAN_THREADS = 256;
@@ -95,14 +98,14 @@ struct SpmvArgs {
 template <typename T>
 void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s);
 // Greedy row blocking of a CSR operator: consecutive rows while their
-// nonzeros fit SPMV_CAP; the reduction width follows the mean row length.
-void make_row_blocks(const int64_t* rp, int64_t n, std::vector<int64_t>& blocks, int& lanes);
+// nonzeros fit cap; the reduction width follows the mean row length.
+void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, std::vector<int64_t>& blocks, int& lanes);
 // Staged-gather tables of d (run_ptr, runs, slot) from its device CSR and
 // row blocks; rp is the host copy of the row pointers.  Blocks whose columns
 // span more than STAGE_SPAN or form more than SPMV_THREADS runs, and
 // long-row blocks, keep direct gathers.
 constexpr int64_t STAGE_SPAN = 262144;
-void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s);
+void build_staging(const DevCSR& d, RowBlocks& b, const std::vector<int64_t>& rp, hipStream_t s);
 // Grouped form of d (groups.cpp): rows with identical column lists in groups
 // of at most GROUP_ROWS, blocks of one group size, every block staged.  rp and
 // ci are host copies of d's pattern.  Returns false (and leaves d without the

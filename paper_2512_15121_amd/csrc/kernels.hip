@@ -65,13 +65,13 @@ __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-void make_row_blocks(const int64_t* rp, int64_t n, std::vector<int64_t>& blocks, int& lanes) {
+void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, std::vector<int64_t>& blocks, int& lanes) {
     blocks.clear();
     blocks.push_back(0);
     int64_t acc = 0, rows = 0;
     for (int64_t r = 0; r < n; ++r) {
         const int64_t len = rp[r + 1] - rp[r];
-        if (rows > 0 && (acc + len > SPMV_CAP || rows == SPMV_MAX_ROWS)) {
+        if (rows > 0 && (acc + len > cap || rows == SPMV_MAX_ROWS)) {
             blocks.push_back(r);
             acc = 0;
             rows = 0;
@@ -208,7 +208,7 @@ __device__ __forceinline__ void stage_runs(const T* __restrict__ v, int2 dsc, in
 template <typename T>
 __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, int64_t base, int n,
                                                int nruns, T* prod) {
-    constexpr int PER = SPMV_CAP / SPMV_THREADS;
+    constexpr int PER = spmv_cap<T>() / SPMV_THREADS;
     constexpr int NW = SPMV_THREADS / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + run0;
@@ -250,7 +250,7 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
 // Direct: column ids and values first, then the gathers.  n > 0.
 template <typename T>
 __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t base, int n, T* prod) {
-    constexpr int PER = SPMV_CAP / SPMV_THREADS;
+    constexpr int PER = spmv_cap<T>() / SPMV_THREADS;
     const int tid = threadIdx.x;
     const int32_t* __restrict__ ci = a.ci + base;
     const T* __restrict__ val = a.val + base;
@@ -274,7 +274,8 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 }
 
 // Streaming CSR product.  A block owns a run of at most SPMV_THREADS whole
-// rows whose nonzeros (at most SPMV_CAP = 8 per thread) are contiguous, and
+// rows whose nonzeros (at most spmv_cap<T>(): 8 FP64 or 16 FP32 values per
+// thread, 32 KB of LDS either way) are contiguous, and
 // reads where they start from one 32-byte descriptor, so the value stream
 // waits on one load only:
 //  0. thread t prefetches the row-local operands of row r0 + t and the end
@@ -295,13 +296,14 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 // 0 direct everywhere; 1 staged in every block with nonzeros; 2 per block
 // (the run count decides).  Forms 0 and 1 keep the other form's code out of
 // the kernel, so nothing ahead of the value stream waits on loads.  A row
-// longer than SPMV_CAP (forms 0 and 2 only) has a block of its own, summed
+// longer than the capacity (forms 0 and 2 only) has a block of its own, summed
 // straight from memory by the whole block.
 template <typename T, int MODE, int L, int STAGE>
 __global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
 spmv_stream_kernel(SpmvArgs<T> a) {
     if (stopped(a.stop)) return;
-    __shared__ T prod[SPMV_CAP];
+    constexpr int CAP = spmv_cap<T>();
+    __shared__ T prod[CAP];
     __shared__ T rowsum[SPMV_THREADS];
     __shared__ int rowoff[SPMV_THREADS + 1];
     double* red = reinterpret_cast<double*>(prod);   // reused once products are consumed
@@ -311,7 +313,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     const int64_t r0 = B.r0, base = B.base, cnt = B.n;
     double dot = 0.0, dot2 = 0.0;
     if constexpr (STAGE != 1) {
-        if (cnt > SPMV_CAP) {
+        if (cnt > CAP) {
             // one long row: block-wide strided sum, fixed-order tree
             const int32_t* __restrict__ ci = a.ci + base;
             const T* __restrict__ val = a.val + base;
@@ -612,7 +614,7 @@ __device__ int stage_exscan(int v, int* sc, int tid, int& total) {
 template <bool FILL>
 __global__ void __launch_bounds__(STAGE_THREADS) stage_kernel(const int64_t* __restrict__ rp,
                                                              const int32_t* __restrict__ ci,
-                                                             const int64_t* __restrict__ rblk,
+                                                             const int64_t* __restrict__ rblk, int cap,
                                                              int32_t* counts, const int32_t* run_ptr,
                                                              int32_t* runs, uint16_t* slot) {
     __shared__ unsigned long long bm[STAGE_WORDS];
@@ -625,7 +627,7 @@ __global__ void __launch_bounds__(STAGE_THREADS) stage_kernel(const int64_t* __r
     const int64_t r0 = rblk[b], r1 = rblk[b + 1];
     const int64_t base = rp[r0];
     const int64_t cnt = rp[r1] - base;
-    if (cnt == 0 || cnt > SPMV_CAP) {
+    if (cnt == 0 || cnt > cap) {
         if (!FILL && tid == 0) counts[b] = 0;
         return;
     }
@@ -711,46 +713,42 @@ __global__ void __launch_bounds__(STAGE_THREADS) stage_kernel(const int64_t* __r
     }
 }
 
-void build_staging(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
-    d.run_ptr.release();
-    d.runs.release();
-    d.slot.release();
-    d.nruns = 0;
-    d.nnz_staged = 0;
-    if (d.nblk <= 0 || d.nnz <= 0) return;
-    GIAMG_REQUIRE(d.nblk < (int64_t(1) << 31), "too many row blocks");
-    DevBuf<int32_t> counts(d.nblk);
-    stage_kernel<false><<<(unsigned)d.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), d.rblk.get(),
+void build_staging(const DevCSR& d, RowBlocks& B, const std::vector<int64_t>& rp, hipStream_t s) {
+    B.release_staging();
+    if (B.nblk <= 0 || d.nnz <= 0) return;
+    GIAMG_REQUIRE(B.nblk < (int64_t(1) << 31), "too many row blocks");
+    DevBuf<int32_t> counts(B.nblk);
+    stage_kernel<false><<<(unsigned)B.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), B.rblk.get(), B.cap,
                                                                   counts.get(), nullptr, nullptr, nullptr);
     GIAMG_HIP(hipGetLastError());
-    std::vector<int32_t> hc(d.nblk);
-    std::vector<int64_t> hb(d.nblk + 1);
-    GIAMG_HIP(hipMemcpyAsync(hc.data(), counts.get(), d.nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GIAMG_HIP(hipMemcpyAsync(hb.data(), d.rblk.get(), (d.nblk + 1) * sizeof(int64_t),
+    std::vector<int32_t> hc(B.nblk);
+    std::vector<int64_t> hb(B.nblk + 1);
+    GIAMG_HIP(hipMemcpyAsync(hc.data(), counts.get(), B.nblk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipMemcpyAsync(hb.data(), B.rblk.get(), (B.nblk + 1) * sizeof(int64_t),
                              hipMemcpyDeviceToHost, s));
     GIAMG_HIP(hipStreamSynchronize(s));
-    std::vector<int32_t> ptr(d.nblk + 1, 0);
+    std::vector<int32_t> ptr(B.nblk + 1, 0);
     int64_t total = 0, staged = 0;
-    for (int64_t b = 0; b < d.nblk; ++b) {
+    for (int64_t b = 0; b < B.nblk; ++b) {
         ptr[b] = (int32_t)total;
         total += hc[b];
         if (hc[b] > 0) staged += rp[hb[b + 1]] - rp[hb[b]];
         if (total >= (int64_t(1) << 31)) return;   // tables too large: direct gathers throughout
     }
-    ptr[d.nblk] = (int32_t)total;
+    ptr[B.nblk] = (int32_t)total;
     if (total == 0) return;
-    d.run_ptr.alloc(d.nblk + 1);
-    d.runs.alloc(2 * total);
-    d.slot.alloc(d.nnz);
-    GIAMG_HIP(hipMemcpyAsync(d.run_ptr.get(), ptr.data(), ptr.size() * sizeof(int32_t),
+    B.run_ptr.alloc(B.nblk + 1);
+    B.runs.alloc(2 * total);
+    B.slot.alloc(d.nnz);
+    GIAMG_HIP(hipMemcpyAsync(B.run_ptr.get(), ptr.data(), ptr.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, s));
-    stage_kernel<true><<<(unsigned)d.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), d.rblk.get(),
-                                                                 nullptr, d.run_ptr.get(), d.runs.get(),
-                                                                 d.slot.get());
+    stage_kernel<true><<<(unsigned)B.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), B.rblk.get(), B.cap,
+                                                                 nullptr, B.run_ptr.get(), B.runs.get(),
+                                                                 B.slot.get());
     GIAMG_HIP(hipGetLastError());
     GIAMG_HIP(hipStreamSynchronize(s));
-    d.nruns = total;
-    d.nnz_staged = staged;
+    B.nruns = total;
+    B.nnz_staged = staged;
 }
 
 template <typename T, int MODE, int L, int STAGE>
@@ -820,7 +818,8 @@ void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
     SpmvArgs<T> a = args;
     if (a.stop == nullptr) a.stop = g_stop;
     if (a.n <= 0 || a.nblk <= 0) return;
-    if (a.rblk == nullptr || a.bdesc == nullptr) throw Error(GIAMG_EINVAL, "operator without row blocks");
+    if (!a.lean && a.gblk == nullptr && (a.rblk == nullptr || a.bdesc == nullptr))
+        throw Error(GIAMG_EINVAL, "operator without row blocks");
     switch (mode) {
         case SPMV_PLAIN: launch_spmv_mode<T, SPMV_PLAIN>(a, s); break;
         case SPMV_RESID: launch_spmv_mode<T, SPMV_RESID>(a, s); break;

@@ -38,37 +38,52 @@ Handle::~Handle() {
     if (gstream) (void)hipStreamDestroy(gstream);
 }
 
-void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
+namespace {
+// Row blocks of capacity cap, their staging tables and descriptors.
+void build_row_blocks(const DevCSR& d, RowBlocks& B, int cap, const std::vector<int64_t>& rp,
+                      hipStream_t s, int* lanes) {
     std::vector<int64_t> blocks;
-    make_row_blocks(rp.data(), d.nrows, blocks, d.lanes);
-    d.nblk = (int64_t)blocks.size() - 1;
-    d.rblk.alloc(blocks.size());
-    GIAMG_HIP(hipMemcpyAsync(d.rblk.get(), blocks.data(), blocks.size() * sizeof(int64_t),
+    int l = 16;
+    make_row_blocks(rp.data(), d.nrows, cap, blocks, l);
+    if (lanes) *lanes = l;
+    B.cap = cap;
+    B.nblk = (int64_t)blocks.size() - 1;
+    B.rblk.alloc(blocks.size());
+    GIAMG_HIP(hipMemcpyAsync(B.rblk.get(), blocks.data(), blocks.size() * sizeof(int64_t),
                              hipMemcpyHostToDevice, s));
     GIAMG_HIP(hipStreamSynchronize(s));
-    build_staging(d, rp, s);
+    build_staging(d, B, rp, s);
     // block descriptors (run fields from the staging tables, if any)
     std::vector<int32_t> run_ptr;
-    if (d.run_ptr.get() != nullptr) {
-        run_ptr.resize((size_t)d.nblk + 1);
-        GIAMG_HIP(hipMemcpyAsync(run_ptr.data(), d.run_ptr.get(), run_ptr.size() * sizeof(int32_t),
+    if (B.run_ptr.get() != nullptr) {
+        run_ptr.resize((size_t)B.nblk + 1);
+        GIAMG_HIP(hipMemcpyAsync(run_ptr.data(), B.run_ptr.get(), run_ptr.size() * sizeof(int32_t),
                                  hipMemcpyDeviceToHost, s));
         GIAMG_HIP(hipStreamSynchronize(s));
     }
-    std::vector<BlockDesc> desc((size_t)std::max<int64_t>(d.nblk, 1));
-    for (int64_t b = 0; b < d.nblk; ++b) {
-        BlockDesc& B = desc[b];
-        B.r0 = blocks[b];
-        B.base = rp[blocks[b]];
-        B.nrows = (int32_t)(blocks[b + 1] - blocks[b]);
-        B.n = (int32_t)(rp[blocks[b + 1]] - B.base);
-        B.run0 = run_ptr.empty() ? 0 : run_ptr[b];
-        B.nruns = run_ptr.empty() ? 0 : run_ptr[b + 1] - run_ptr[b];
+    std::vector<BlockDesc> desc((size_t)std::max<int64_t>(B.nblk, 1));
+    for (int64_t b = 0; b < B.nblk; ++b) {
+        BlockDesc& D = desc[b];
+        D.r0 = blocks[b];
+        D.base = rp[blocks[b]];
+        D.nrows = (int32_t)(blocks[b + 1] - blocks[b]);
+        D.n = (int32_t)(rp[blocks[b + 1]] - D.base);
+        D.run0 = run_ptr.empty() ? 0 : run_ptr[b];
+        D.nruns = run_ptr.empty() ? 0 : run_ptr[b + 1] - run_ptr[b];
     }
-    d.bdesc.alloc(4 * desc.size());
-    GIAMG_HIP(hipMemcpyAsync(d.bdesc.get(), desc.data(), desc.size() * sizeof(BlockDesc),
+    B.bdesc.alloc(4 * desc.size());
+    GIAMG_HIP(hipMemcpyAsync(B.bdesc.get(), desc.data(), desc.size() * sizeof(BlockDesc),
                              hipMemcpyHostToDevice, s));
     GIAMG_HIP(hipStreamSynchronize(s));
+}
+}  // namespace
+
+void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
+    build_row_blocks(d, d.blk, SPMV_CAP, rp, s, &d.lanes);
+}
+
+void setup_row_blocks32(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
+    build_row_blocks(d, d.blk32, SPMV_CAP32, rp, s, nullptr);
 }
 
 void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
@@ -84,8 +99,11 @@ void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
         GIAMG_HIP(hipMemcpyAsync(d.ci.get(), h.ci.data(), d.nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
         GIAMG_HIP(hipMemcpyAsync(d.val.get(), h.val.data(), d.nnz * sizeof(double), hipMemcpyHostToDevice, s));
     }
-    if (make32) make_fp32_values(d, s);
     setup_row_blocks(d, h.rp, s);
+    if (make32) {
+        make_fp32_values(d, s);
+        setup_row_blocks32(d, h.rp, s);
+    }
 }
 
 void download_csr(const DevCSR& d, HostCSR& h, hipStream_t s) {
@@ -111,15 +129,19 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     SpmvArgs<T> a;
     a.rp = M.rp.get(); a.ci = M.ci.get(); a.val = val; a.n = M.nrows;
     a.nnz = M.nnz; a.ncols = M.ncols;
-    a.rblk = M.rblk.get(); a.nblk = M.nblk; a.lanes = M.lanes;
-    a.bdesc = reinterpret_cast<const BlockDesc*>(M.bdesc.get());
-    a.run_ptr = M.run_ptr.get(); a.runs = M.runs.get(); a.slot = M.slot.get();
-    a.nnz_staged = M.nnz_staged; a.nruns = M.nruns;
+    // FP32 products use the blocks of capacity SPMV_CAP32 (spmv_cap<float>)
+    const RowBlocks& B = sizeof(T) == sizeof(double) ? M.blk : M.blk32;
+    a.rblk = B.rblk.get(); a.nblk = B.nblk; a.lanes = M.lanes;
+    a.bdesc = reinterpret_cast<const BlockDesc*>(B.bdesc.get());
+    a.run_ptr = B.run_ptr.get(); a.runs = B.runs.get(); a.slot = B.slot.get();
+    a.nnz_staged = B.nnz_staged; a.nruns = B.nruns;
     if (M.lean) {
         a.lean = true;
         a.nblk = M.lean_nblk;
         return a;
     }
+    if (sizeof(T) != sizeof(double) && M.gnblk == 0 && M.nrows > 0 && M.blk32.nblk == 0)
+        throw Error(GIAMG_EINVAL, "FP32 product on an operator without FP32 row blocks");
     const T* gval = nullptr;
     if constexpr (sizeof(T) == sizeof(double)) gval = M.gval.get(); else gval = M.gval32.get();
     if (M.gnblk > 0 && gval != nullptr) {
@@ -133,7 +155,7 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
 
 // Blocks of the product form args_of picks for FP64 values (the number of
 // block partials its DOT and RINIT epilogues write).
-int64_t product_blocks(const DevCSR& M) { return M.lean ? M.lean_nblk : M.gnblk > 0 ? M.gnblk : M.nblk; }
+int64_t product_blocks(const DevCSR& M) { return M.lean ? M.lean_nblk : M.gnblk > 0 ? M.gnblk : M.blk.nblk; }
 
 // Lean form for the operators with at most max_nnz nonzeros and no row longer
 // than SPMV_CAP (their staging tables are released).
@@ -153,10 +175,8 @@ void assign_lean_forms(Handle& H, int64_t max_nnz) {
             const int64_t rpb = LEAN_THREADS / M->lanes;
             M->lean = true;
             M->lean_nblk = (M->nrows + rpb - 1) / rpb;
-            M->run_ptr.release();
-            M->runs.release();
-            M->slot.release();
-            M->nruns = M->nnz_staged = 0;
+            M->blk.release_staging();
+            M->blk32.release_staging();
         }
 }
 
@@ -177,10 +197,8 @@ void build_grouped_forms(Handle& H, bool mixed) {
             GIAMG_HIP(hipStreamSynchronize(H.stream));
             if (!build_grouping(*M, rp, ci, H.stream)) continue;
             if (mixed) make_fp32_group_values(*M, H.stream);
-            M->run_ptr.release();
-            M->runs.release();
-            M->slot.release();
-            M->nruns = M->nnz_staged = 0;
+            M->blk.release_staging();
+            M->blk32.release_staging();
         }
     }
     GIAMG_HIP(hipStreamSynchronize(H.stream));
@@ -190,6 +208,18 @@ void make_fp32_values(DevCSR& d, hipStream_t s) {
     d.val32.alloc(d.nnz);
     launch_convert<double, float>(d.nnz, d.val.get(), d.val32.get(), s);
 }
+
+namespace {
+// FP32 values and, for operators in the CSR form, the FP32 row blocks.
+void make_fp32_operator(DevCSR& d, hipStream_t s) {
+    make_fp32_values(d, s);
+    if (d.lean || d.gnblk > 0 || d.nrows <= 0) return;
+    std::vector<int64_t> rp((size_t)d.nrows + 1);
+    GIAMG_HIP(hipMemcpyAsync(rp.data(), d.rp.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GIAMG_HIP(hipStreamSynchronize(s));
+    setup_row_blocks32(d, rp, s);
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // setup
@@ -378,7 +408,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     for (auto& L : H.levels) {
         maxn = std::max(maxn, L.n);
         for (const DevCSR* M : {&L.A, &L.P, &L.R, &L.AP})
-            maxblk = std::max({maxblk, M->nblk, M->gnblk, M->lean_nblk});
+            maxblk = std::max({maxblk, M->blk.nblk, M->blk32.nblk, M->gnblk, M->lean_nblk});
     }
     H.partial_cap = std::max<int64_t>(2 * maxblk, 2 * vec_blocks(maxn)) + 16;
     H.partial.alloc(H.partial_cap);
@@ -392,9 +422,9 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     for (size_t l = 0; l < H.levels.size(); ++l) {
         Level& L = H.levels[l];
         alloc_level_vectors(L, mixed);
-        if (mixed) make_fp32_values(L.A, H.stream);
+        if (mixed) make_fp32_operator(L.A, H.stream);
         if (l + 1 == H.levels.size()) break;
-        if (mixed) make_fp32_values(L.AP, H.stream);
+        if (mixed) make_fp32_operator(L.AP, H.stream);
         L.dinv.alloc(L.n);
         DevBuf<int> bad(1);
         GIAMG_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), H.stream));
@@ -418,10 +448,8 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     if (o.direct_gathers) {
         for (auto& L : H.levels)
             for (DevCSR* M : {&L.A, &L.P, &L.R, &L.AP}) {
-                M->run_ptr.release();
-                M->runs.release();
-                M->slot.release();
-                M->nruns = M->nnz_staged = 0;
+                M->blk.release_staging();
+                M->blk32.release_staging();
             }
     }
     if (!H.ev0) GIAMG_HIP(hipEventCreate(&H.ev0));
@@ -435,8 +463,8 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
 
 int64_t handle_device_bytes(const Handle& H) {
     auto csr = [](const DevCSR& m) {
-        return (int64_t)(m.rp.n + m.rblk.n + m.bdesc.n) * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 +
-               (int64_t)m.val32.n * 4 + (int64_t)(m.run_ptr.n + m.runs.n) * 4 + (int64_t)m.slot.n * 2 +
+        return (int64_t)m.rp.n * 8 + (int64_t)m.ci.n * 4 + (int64_t)m.val.n * 8 + (int64_t)m.val32.n * 4 +
+               m.blk.device_bytes() + m.blk32.device_bytes() +
                (int64_t)m.gblk.n * 8 + (int64_t)(m.grows.n + m.ggrp.n + m.grun_ptr.n + m.gruns.n) * 4 +
                (int64_t)m.gslot.n * 2 + (int64_t)m.gval.n * 8 + (int64_t)m.gval32.n * 4;
     };
