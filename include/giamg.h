@@ -180,7 +180,8 @@ typedef struct giamg_info {
  * p        order, 1 <= p <= 10.   lambda >= 0 (lambda = 0 needs at least one
  *          constrained node).
  * opts     NULL for defaults.
- * stream   hipStream_t for all work of this handle (NULL = default stream).
+ * stream   hipStream_t for all work of this handle (NULL = default stream); it
+ *          must stay valid until giamg_free.
  * out      receives the handle; left untouched on error.
  *
  * Discretisation: tensor Lagrange basis on Gauss-Lobatto-Legendre points
