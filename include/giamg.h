@@ -196,7 +196,8 @@ int giamg_setup(const double* coords, int64_t n_nodes,
                 double lambda, const giamg_opts* opts, void* stream,
                 giamg_handle* out);
 
-/* Release every resource of the handle (NULL is ignored). */
+/* Release every resource of the handle (NULL is ignored).  Free the
+ * handle's sessions (giamg_session_free) first: they use its hierarchy. */
 void giamg_free(giamg_handle h);
 
 /*
@@ -345,7 +346,8 @@ int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t
                           int32_t* l2g_next, int64_t* n_coarse, giamg_hcsr* P_out);
 
 /* Smoothed-aggregation transfer of Section 2.5 for a CSR operator (host
- * arrays, ascending columns): writes agg int32 [n], returns P. */
+ * arrays, ascending columns; row_ptr[0] = 0 and non-decreasing, columns in
+ * [0, n), else GIAMG_EINVAL): writes agg int32 [n], returns P. */
 int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const double* val,
                          int64_t n, uint64_t seed, int32_t* agg, int64_t* n_agg,
                          giamg_hcsr* P_out);

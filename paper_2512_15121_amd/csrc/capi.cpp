@@ -451,7 +451,8 @@ int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t
     return guarded([&]() -> int {
         GIAMG_REQUIRE(l2g && free_mask && l2g_next && n_coarse && P_out, "null argument");
         GIAMG_REQUIRE(basis == GIAMG_BASIS_NODAL || basis == GIAMG_BASIS_MODAL, "unknown basis");
-        GIAMG_REQUIRE(p >= 1 && q >= 1 && q < p, "need 1 <= q < p");
+        GIAMG_REQUIRE(p <= 10 && q >= 1 && q < p, "need 1 <= q < p <= 10");
+        GIAMG_REQUIRE(n_elem > 0 && n_fine > 0, "n_elem and n_fine must be positive");
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         std::vector<int32_t> g(l2g, l2g + n_elem * nl);
         for (auto v : g) GIAMG_REQUIRE(v >= -1 && v < n_fine, "l2g entry out of range");
@@ -468,6 +469,10 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
                          uint64_t seed, int32_t* agg, int64_t* n_agg, giamg_hcsr* P_out) {
     return guarded([&]() -> int {
         GIAMG_REQUIRE(row_ptr && col && val && agg && n_agg && P_out && n > 0, "null argument");
+        GIAMG_REQUIRE(n < (int64_t(1) << 31) - 1, "n exceeds the int32 index range");
+        GIAMG_REQUIRE(row_ptr[0] == 0, "row_ptr[0] must be 0");
+        for (int64_t i = 0; i < n; ++i)
+            GIAMG_REQUIRE(row_ptr[i + 1] >= row_ptr[i], "row_ptr must be non-decreasing");
         giamg::HostCSR A;
         A.nrows = A.ncols = n;
         A.rp.assign(row_ptr, row_ptr + n + 1);

@@ -160,3 +160,32 @@ def test_set_allocator_validation_without_device_work():
     assert rc == giamg.EINVAL and b"both" in lib.giamg_last_error()
     giamg.set_allocator(lambda n, s: 0, lambda p: None)   # registering touches no device
     giamg.set_allocator()
+
+
+def test_host_stages_reject_malformed_input():
+    """The host-stage entry points check sizes and the CSR row pointer before
+    reading the arrays they describe."""
+    from paper_2512_15121_amd import giamg
+    import numpy as np
+    lib = giamg.library()
+    out = ctypes.c_void_p()
+    n_agg = ctypes.c_int64()
+    agg = np.zeros(2, dtype=np.int32)
+    col = np.array([0, 1, 0, 1], dtype=np.int32)
+    val = np.ones(4)
+    for rp, word in (([1, 2, 4], b"row_ptr[0]"), ([0, 3, 2], b"non-decreasing")):
+        rp = np.array(rp, dtype=np.int64)
+        rc = lib.giamg_host_aggregate(giamg._ptr(rp), giamg._ptr(col), giamg._ptr(val), 2, 0,
+                                      giamg._ptr(agg), ctypes.byref(n_agg), ctypes.byref(out))
+        assert rc == giamg.EINVAL and word in lib.giamg_last_error()
+        assert not out.value
+    l2g = np.arange(27, dtype=np.int32)
+    free = np.ones(27, dtype=np.uint8)
+    nxt = np.zeros(8, dtype=np.int32)
+    n_c = ctypes.c_int64()
+    for n_elem, p, n_fine in ((0, 2, 27), (1, 2, 0), (1, 11, 27)):
+        rc = lib.giamg_host_p_transfer(giamg._ptr(l2g), n_elem, p, 1, n_fine, giamg._ptr(free),
+                                       giamg.BASIS["nodal"], giamg._ptr(nxt), ctypes.byref(n_c),
+                                       ctypes.byref(out))
+        assert rc == giamg.EINVAL, (n_elem, p, n_fine)
+        assert not out.value
