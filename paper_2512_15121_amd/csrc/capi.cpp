@@ -83,6 +83,59 @@ void device_release(void* p, const Allocator& a, hipStream_t s) {
 }
 }  // namespace giamg
 
+namespace giamg {
+void check_setup_args(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
+                      int32_t p, double lambda, const giamg_opts& o) {
+    GIAMG_REQUIRE(coords != nullptr && l2g != nullptr, "coords and l2g must be non-null");
+    GIAMG_REQUIRE(n_nodes > 0 && n_elem > 0, "n_nodes and n_elem must be positive");
+    GIAMG_REQUIRE(n_nodes < (int64_t(1) << 31) - 1, "n_nodes exceeds the int32 index range");
+    GIAMG_REQUIRE(p >= 1 && p <= 10, "order p must be in [1, 10]");
+    GIAMG_REQUIRE(std::isfinite(lambda) && lambda >= 0.0, "lambda must be finite and >= 0");
+    GIAMG_REQUIRE(o.smoother == GIAMG_SMOOTHER_CHEBYSHEV || o.smoother == GIAMG_SMOOTHER_JACOBI,
+                  "unknown smoother");
+    GIAMG_REQUIRE(o.degree >= 1 && o.degree <= 16, "degree must be in [1, 16]");
+    GIAMG_REQUIRE(o.omega > 0.0 && o.omega < 2.0, "omega must be in (0, 2)");
+    GIAMG_REQUIRE(o.coarse_max >= 1 && o.max_levels >= 1 && o.max_levels <= 32,
+                  "bad coarse_max / max_levels");
+    GIAMG_REQUIRE(o.bc == GIAMG_BC_DIRICHLET || o.bc == GIAMG_BC_PIN, "unknown bc");
+    GIAMG_REQUIRE(o.bc != GIAMG_BC_PIN || (o.pin_node >= 0 && o.pin_node < n_nodes),
+                  "pin_node out of range");
+    GIAMG_REQUIRE(o.precision == GIAMG_PREC_FP64 || o.precision == GIAMG_PREC_MIXED,
+                  "unknown precision");
+    GIAMG_REQUIRE(o.maxit >= 0, "maxit must be >= 0");
+    GIAMG_REQUIRE(o.power_iters >= 1, "power_iters must be >= 1");
+    GIAMG_REQUIRE(o.cheb_lo > 0.0 && o.cheb_hi > o.cheb_lo, "need 0 < cheb_lo < cheb_hi");
+    GIAMG_REQUIRE(o.direct_gathers == 0 || o.direct_gathers == 1, "direct_gathers must be 0 or 1");
+    GIAMG_REQUIRE(o.graph_launch == 0 || o.graph_launch == 1, "graph_launch must be 0 or 1");
+    GIAMG_REQUIRE(o.basis == GIAMG_BASIS_NODAL || o.basis == GIAMG_BASIS_MODAL, "unknown basis");
+    GIAMG_REQUIRE(o.batch_kernel >= GIAMG_BATCH_AUTO && o.batch_kernel <= GIAMG_BATCH_GROUP,
+                  "unknown batch_kernel");
+    GIAMG_REQUIRE(o.row_groups == 0 || o.row_groups == 1, "row_groups must be 0 or 1");
+    GIAMG_REQUIRE(o.lean_max_nnz >= 0, "lean_max_nnz must be >= 0");
+    GIAMG_REQUIRE(o.keep_boundary == 0 || o.keep_boundary == 1, "keep_boundary must be 0 or 1");
+    {
+        int prev = p;
+        for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
+            GIAMG_REQUIRE(o.schedule[i] >= 1 && o.schedule[i] < prev,
+                          "schedule must decrease from p and stay >= 1");
+            prev = o.schedule[i];
+        }
+    }
+    const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
+    for (int64_t i = 0; i < n_elem * nl; ++i)
+        GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");
+    for (int64_t e = 0; e < n_elem; ++e) {
+        const int32_t* g = l2g + e * nl;
+        for (int c = 0; c < 8; ++c) {
+            int i = ((c >> 2) & 1) * p, j = ((c >> 1) & 1) * p, k = (c & 1) * p;
+            const double* x = coords + (int64_t)g[((p + 1) * i + j) * (p + 1) + k] * 3;
+            GIAMG_REQUIRE(std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]),
+                          "non-finite corner coordinate");
+        }
+    }
+}
+}  // namespace giamg
+
 namespace {
 #define g_last_error (::giamg::last_error())
 
@@ -154,56 +207,10 @@ int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64
                 giamg_handle* out) {
     return guarded([&]() -> int {
         GIAMG_REQUIRE(out != nullptr, "out is null");
-        GIAMG_REQUIRE(coords != nullptr && l2g != nullptr, "coords and l2g must be non-null");
-        GIAMG_REQUIRE(n_nodes > 0 && n_elem > 0, "n_nodes and n_elem must be positive");
-        GIAMG_REQUIRE(n_nodes < (int64_t(1) << 31) - 1, "n_nodes exceeds the int32 index range");
-        GIAMG_REQUIRE(p >= 1 && p <= 10, "order p must be in [1, 10]");
-        GIAMG_REQUIRE(std::isfinite(lambda) && lambda >= 0.0, "lambda must be finite and >= 0");
         giamg_opts o;
         giamg_default_opts(&o);
         if (opts) o = *opts;
-        GIAMG_REQUIRE(o.smoother == GIAMG_SMOOTHER_CHEBYSHEV || o.smoother == GIAMG_SMOOTHER_JACOBI,
-                      "unknown smoother");
-        GIAMG_REQUIRE(o.degree >= 1 && o.degree <= 16, "degree must be in [1, 16]");
-        GIAMG_REQUIRE(o.omega > 0.0 && o.omega < 2.0, "omega must be in (0, 2)");
-        GIAMG_REQUIRE(o.coarse_max >= 1 && o.max_levels >= 1 && o.max_levels <= 32,
-                      "bad coarse_max / max_levels");
-        GIAMG_REQUIRE(o.bc == GIAMG_BC_DIRICHLET || o.bc == GIAMG_BC_PIN, "unknown bc");
-        GIAMG_REQUIRE(o.bc != GIAMG_BC_PIN || (o.pin_node >= 0 && o.pin_node < n_nodes),
-                      "pin_node out of range");
-        GIAMG_REQUIRE(o.precision == GIAMG_PREC_FP64 || o.precision == GIAMG_PREC_MIXED,
-                      "unknown precision");
-        GIAMG_REQUIRE(o.maxit >= 0, "maxit must be >= 0");
-        GIAMG_REQUIRE(o.power_iters >= 1, "power_iters must be >= 1");
-        GIAMG_REQUIRE(o.cheb_lo > 0.0 && o.cheb_hi > o.cheb_lo, "need 0 < cheb_lo < cheb_hi");
-        GIAMG_REQUIRE(o.direct_gathers == 0 || o.direct_gathers == 1, "direct_gathers must be 0 or 1");
-        GIAMG_REQUIRE(o.graph_launch == 0 || o.graph_launch == 1, "graph_launch must be 0 or 1");
-        GIAMG_REQUIRE(o.basis == GIAMG_BASIS_NODAL || o.basis == GIAMG_BASIS_MODAL, "unknown basis");
-        GIAMG_REQUIRE(o.batch_kernel >= GIAMG_BATCH_AUTO && o.batch_kernel <= GIAMG_BATCH_GROUP,
-                      "unknown batch_kernel");
-        GIAMG_REQUIRE(o.row_groups == 0 || o.row_groups == 1, "row_groups must be 0 or 1");
-        GIAMG_REQUIRE(o.lean_max_nnz >= 0, "lean_max_nnz must be >= 0");
-        GIAMG_REQUIRE(o.keep_boundary == 0 || o.keep_boundary == 1, "keep_boundary must be 0 or 1");
-        {
-            int prev = p;
-            for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
-                GIAMG_REQUIRE(o.schedule[i] >= 1 && o.schedule[i] < prev,
-                              "schedule must decrease from p and stay >= 1");
-                prev = o.schedule[i];
-            }
-        }
-        const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
-        for (int64_t i = 0; i < n_elem * nl; ++i)
-            GIAMG_REQUIRE(l2g[i] >= 0 && l2g[i] < n_nodes, "l2g entry out of range");
-        for (int64_t e = 0; e < n_elem; ++e) {
-            const int32_t* g = l2g + e * nl;
-            for (int c = 0; c < 8; ++c) {
-                int i = ((c >> 2) & 1) * p, j = ((c >> 1) & 1) * p, k = (c & 1) * p;
-                const double* x = coords + (int64_t)g[((p + 1) * i + j) * (p + 1) + k] * 3;
-                GIAMG_REQUIRE(std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]),
-                              "non-finite corner coordinate");
-            }
-        }
+        giamg::check_setup_args(coords, n_nodes, l2g, n_elem, p, lambda, o);
         auto* h = new giamg_s();
         try {
             GIAMG_HIP(hipGetDevice(&h->device));

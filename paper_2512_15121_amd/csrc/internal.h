@@ -266,6 +266,10 @@ HostCSR transpose(const HostCSR& M);
 bool spd_inverse(const std::vector<double>& A, int64_t n, std::vector<double>& inv);
 
 uint64_t splitmix64(uint64_t seed, uint64_t i);
+// Checks of a mesh and options before a hierarchy is built (giamg_setup and
+// registered server problems): throws Error(GIAMG_EINVAL, ...) on failure.
+void check_setup_args(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
+                      int32_t p, double lambda, const giamg_opts& o);
 // Held while a HIP graph is captured, and by threads of the library that
 // could otherwise issue synchronising calls during another thread's capture.
 std::mutex& capture_mutex();

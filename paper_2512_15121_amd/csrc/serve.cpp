@@ -103,6 +103,8 @@ struct Server {
     bool stop = false;
     int dead = 0;            // error code once the loop has died
     std::string dead_msg;
+    int worker_dead = 0;     // error code once the setup worker has died
+    std::string worker_msg;
     std::thread loop, setup;
 
     // Device bytes of a problem's group: measured after its first setup,
@@ -171,6 +173,14 @@ struct Server {
         }
     }
 
+    // the setup worker died outside a setup: the loop ends every request
+    void worker_died(int code, const std::string& msg) {
+        std::lock_guard<std::mutex> lk(mu);
+        worker_dead = code;
+        worker_msg = "setup worker: " + msg;
+        cv_work.notify_all();
+    }
+
     // the loop died: every unfinished request ends with `code`
     void fail_all(int code, const std::string& msg) {
         std::lock_guard<std::mutex> lk(mu);
@@ -226,6 +236,7 @@ struct Server {
             bool progress = false;
             std::unique_lock<std::mutex> lk(mu);
             if (stop) break;
+            if (worker_dead) throw Error(worker_dead, worker_msg);
             // finished setups become resident groups
             while (!setup_done.empty()) {
                 std::unique_ptr<Group> g = std::move(setup_done.back());
@@ -407,7 +418,13 @@ int giamg_server_create(const giamg_server_opts* o, giamg_server* out) {
             }
         });
         s->srv.setup = std::thread([s] {
-            try { s->srv.setup_main(); } catch (...) {}
+            try {
+                s->srv.setup_main();
+            } catch (const giamg::Error& e) {
+                s->srv.worker_died(e.code, e.what());
+            } catch (const std::exception& e) {
+                s->srv.worker_died(GIAMG_EHIP, e.what());
+            }
         });
         *out = s;
         return GIAMG_OK;
@@ -418,20 +435,18 @@ int giamg_server_add_problem(giamg_server s, const double* coords, int64_t n_nod
                              int64_t n_elem, int32_t p, double lambda, const giamg_opts* opts,
                              int32_t* problem) {
     return sguard([&]() -> int {
-        GIAMG_REQUIRE(s && coords && l2g && problem && n_nodes > 0 && n_elem > 0 && p >= 1 && p <= 10 &&
-                          lambda >= 0.0,
-                      "bad problem");
+        GIAMG_REQUIRE(s && problem, "null argument");
         giamg::Problem P;
+        giamg_default_opts(&P.opts);
+        if (opts) P.opts = *opts;
+        giamg::check_setup_args(coords, n_nodes, l2g, n_elem, p, lambda, P.opts);
         const int64_t nl = (int64_t)(p + 1) * (p + 1) * (p + 1);
         P.coords.assign(coords, coords + n_nodes * 3);
         P.l2g.assign(l2g, l2g + n_elem * nl);
-        for (int32_t v : P.l2g) GIAMG_REQUIRE(v >= 0 && v < n_nodes, "l2g entry out of range");
         P.n_nodes = n_nodes;
         P.n_elem = n_elem;
         P.p = p;
         P.lambda = lambda;
-        giamg_default_opts(&P.opts);
-        if (opts) P.opts = *opts;
         std::lock_guard<std::mutex> lk(s->srv.mu);
         s->srv.problems.push_back(std::move(P));
         *problem = (int32_t)s->srv.problems.size() - 1;
@@ -469,6 +484,7 @@ int giamg_server_wait(giamg_server s, int64_t request, giamg_info* info, double*
         GIAMG_REQUIRE(it != s->srv.requests.end(), "unknown request");
         s->srv.cv_done.wait(lk, [&] { return it->second.finished || s->srv.stop; });
         giamg::Request& r = it->second;
+        if (!r.finished) throw giamg::Error(GIAMG_EINVAL, "server stopped before the request finished");
         if (info) *info = r.info;
         if (latency_ms)
             *latency_ms = std::chrono::duration<double, std::milli>(r.done - r.submit).count();

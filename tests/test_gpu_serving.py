@@ -150,3 +150,25 @@ def test_server_queues_more_requests_than_slots(torch_dev):
     for (x, info, lat), b in zip(res, bs):
         xa, ia = _alone(torch, dev, m, p, lam, b)
         assert info.status == 0 and np.array_equal(x, xa)
+
+
+def test_server_rejects_invalid_problem(torch_dev):
+    """A registered problem passes the same mesh and option checks as
+    giamg_setup, at registration (not later on the setup worker)."""
+    from paper_2512_15121_amd import Server, Options, GiamgError, giamg
+    m = synth.hex_mesh(2, 2, perturb=0.1, seed=3)
+    srv = Server(hbm_budget=1 << 30, slots=2, chunk=2, tol=1e-10)
+    bad_l2g = m.l2g.copy()
+    bad_l2g[0, 0] = m.n_nodes
+    cases = [(m.l2g, 2, 0.0, Options(degree=0), "degree"),
+             (m.l2g, 2, float("inf"), Options(), "lambda"),
+             (bad_l2g, 2, 0.0, Options(), "l2g"),
+             (m.l2g, 2, 0.0, Options(schedule=[2]), "schedule")]
+    for l2g, p, lam, opts, word in cases:
+        with pytest.raises(GiamgError) as e:
+            srv.add_problem(m.coords, l2g, p, lam, opts)
+        assert e.value.code == giamg.EINVAL and word in str(e.value), word
+    pid = srv.add_problem(m.coords, m.l2g, 2, 0.0, Options())
+    x, info, _ = srv.wait(srv.submit(pid, synth.normal_rhs(m.n_nodes, 5)))
+    assert info.status == 0 and np.isfinite(x).all()
+    srv.close()
