@@ -285,7 +285,9 @@ int giamg_constrained(giamg_handle h, uint8_t* mask);
  *   GIAMG_OP_COARSE      out = A_l^-1 a               (coarsest level only)
  *   GIAMG_OP_VCYCLE      out = V-cycle from level l applied to a
  * Add GIAMG_OP_FP32 to run the FP32 operators of a mixed-precision handle
- * on float vectors.  Synchronises the stream.
+ * on float vectors.  Vectors are sized by the level they live on; a and out
+ * must be non-NULL, b only for the residual (else GIAMG_EINVAL).
+ * Synchronises the stream.
  */
 #define GIAMG_OP_SPMV         0
 #define GIAMG_OP_RESIDUAL     1
@@ -354,7 +356,7 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
 
 /*
  * giamg_time_kernel -- time one device kernel of a level in the launch
- * configuration the solve uses: `reps` launches on the handle's stream, each
+ * configuration the solve uses: `reps` (1 to 100000) launches on the handle's stream, each
  * between its own pair of HIP events (contents of the level's work vectors
  * are overwritten).  kernel:
  *   GIAMG_KERNEL_CHEB_STEP  fused Chebyshev step on A_l (FP64; FP32 with GIAMG_OP_FP32)

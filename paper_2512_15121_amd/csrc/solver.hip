@@ -1008,7 +1008,7 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
 void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes) {
     AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
-    GIAMG_REQUIRE(reps >= 1, "reps must be >= 1");
+    GIAMG_REQUIRE(reps >= 1 && reps <= 100000, "reps must be in [1, 100000]");
     if (kernel & GIAMG_OP_FP32) {
         GIAMG_REQUIRE(H.opts.precision == GIAMG_PREC_MIXED, "FP32 operators exist only in mixed mode");
         time_kernel_t<float>(H, kernel & ~GIAMG_OP_FP32, level, reps, ms, bytes);
@@ -1062,6 +1062,9 @@ void apply_t(Handle& H, int op, size_t l, const T* a, const T* b, T* out) {
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out) {
     AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
+    GIAMG_REQUIRE(a != nullptr, "a is null");
+    GIAMG_REQUIRE(b != nullptr || (op & ~GIAMG_OP_FP32) != GIAMG_OP_RESIDUAL,
+                  "b is null (the residual needs x)");
     if (op & GIAMG_OP_FP32) {
         GIAMG_REQUIRE(H.opts.precision == GIAMG_PREC_MIXED, "FP32 operators exist only in mixed mode");
         apply_t<float>(H, op & ~GIAMG_OP_FP32, level, (const float*)a, (const float*)b, (float*)out);
