@@ -152,18 +152,27 @@ __device__ __forceinline__ void epilogue_store(const SpmvArgs<T>& a, int64_t row
 template <int MODE>
 constexpr bool has_partials() { return MODE == SPMV_DOT || MODE == SPMV_RINIT; }
 
-// Fixed-order block sum of two values per thread; red holds 2*NT.
+// Fixed-order block sums of two values per thread, returned in a and b to
+// every thread: each wave adds its lanes by a butterfly (every lane ends with
+// the same bits, addition being commutative), then every thread adds the
+// waves' sums in wave order.  One barrier; red holds 2 * NT / WAVE doubles
+// and may be reused after a further barrier.
 template <int NT = SPMV_THREADS>
-__device__ __forceinline__ void block_sum2(double* red, int tid, double a, double b) {
-    red[tid] = a;
-    red[NT + tid] = b;
+__device__ __forceinline__ void block_sum2(double* red, int tid, double& a, double& b) {
+    constexpr int NW = NT / WAVE;
+    a = group_sum<WAVE>(a);
+    b = group_sum<WAVE>(b);
+    if (tid % WAVE == 0) {
+        red[tid / WAVE] = a;
+        red[NW + tid / WAVE] = b;
+    }
     __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-        if (tid < o) {
-            red[tid] += red[tid + o];
-            red[NT + tid] += red[NT + tid + o];
-        }
-        __syncthreads();
+    a = red[0];
+    b = red[NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        a += red[w];
+        b += red[NW + w];
     }
 }
 
@@ -314,7 +323,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     double dot = 0.0, dot2 = 0.0;
     if constexpr (STAGE != 1) {
         if (cnt > CAP) {
-            // one long row: block-wide strided sum, fixed-order tree
+            // one long row: block-wide strided sum, fixed-order block sum
             const int32_t* __restrict__ ci = a.ci + base;
             const T* __restrict__ val = a.val + base;
             const T* __restrict__ v = a.v;
@@ -329,9 +338,9 @@ spmv_stream_kernel(SpmvArgs<T> a) {
                 acc1 += a1 * v[c1];
             }
             if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
-            block_sum2(red, tid, (double)(acc0 + acc1), 0.0);
-            const T y = (T)red[0];
-            __syncthreads();
+            double s = (double)(acc0 + acc1), unused = 0.0;
+            block_sum2(red, tid, s, unused);
+            const T y = (T)s;
             if (tid == 0) {
                 epilogue_store<T, MODE>(a, r0, y, in, dot, dot2);
                 if constexpr (has_partials<MODE>()) {
@@ -385,8 +394,8 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     if constexpr (has_partials<MODE>()) {
         block_sum2(red, tid, dot, dot2);
         if (tid == 0) {
-            a.partial[lb] = red[0];
-            if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = red[SPMV_THREADS];
+            a.partial[lb] = dot;
+            if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
         }
     }
 }
@@ -504,8 +513,8 @@ spmv_group_kernel(SpmvArgs<T> a) {
     if constexpr (has_partials<MODE>()) {
         block_sum2(red, tid, dot, dot2);
         if (tid == 0) {
-            a.partial[lb] = red[0];
-            if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = red[SPMV_THREADS];
+            a.partial[lb] = dot;
+            if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
         }
     }
 }
@@ -557,11 +566,11 @@ __global__ void __launch_bounds__(LEAN_THREADS) spmv_lean_kernel(SpmvArgs<T> a) 
     double dot = 0.0, dot2 = 0.0;
     if (live && gl == 0) epilogue_store<T, MODE>(a, row, acc, in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
-        __shared__ double red[2 * LEAN_THREADS];
+        __shared__ double red[2 * LEAN_THREADS / WAVE];
         block_sum2<LEAN_THREADS>(red, tid, dot, dot2);
         if (tid == 0) {
-            a.partial[blockIdx.x] = red[0];
-            if (MODE == SPMV_RINIT) a.partial[a.nblk + blockIdx.x] = red[LEAN_THREADS];
+            a.partial[blockIdx.x] = dot;
+            if (MODE == SPMV_RINIT) a.partial[a.nblk + blockIdx.x] = dot2;
         }
     }
 }
@@ -995,16 +1004,18 @@ int64_t vec_blocks(int64_t n) {
     return std::max<int64_t>(1, std::min<int64_t>(b, VEC_MAX_BLOCKS));
 }
 
+// Fixed-order block sum returned to every thread: a butterfly inside each
+// wave, then the waves' sums in wave order (sh holds NT / WAVE doubles; the
+// trailing barrier lets the caller reuse it at once).
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-    sh[threadIdx.x] = v;
+    constexpr int NW = NT / WAVE;
+    v = group_sum<WAVE>(v);
+    if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = v;
     __syncthreads();
+    double r = sh[0];
 #pragma unroll
-    for (int o = NT / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    for (int w = 1; w < NW; ++w) r += sh[w];
     __syncthreads();
     return r;
 }
