@@ -354,6 +354,12 @@ static unsigned bgrid(int64_t total) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
 }
 
+// ---- per-column CG state ------------------------------------------------------
+struct ColState {
+    double bb, rr, rz, pq, alpha, beta, rznew, zrold;
+    int active, iters, status, init;   // init: column being (re)started
+};
+
 // ---- column dot products with a fixed row partition ---------------------------
 // partial[(c*nb + b)] = sum over rows of block b (in order) of a[i][c] * b[i][c]
 __global__ void __launch_bounds__(256) bdot_partial_kernel(int64_t n, int k, const double* __restrict__ a,
@@ -376,28 +382,67 @@ __global__ void __launch_bounds__(256) bdot_partial_kernel(int64_t n, int k, con
         partial[col * nb + blockIdx.x] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
-// out[c * ostride] = fixed-order sum of partial[c*nb + 0..nb)
-__global__ void __launch_bounds__(256) bdot_reduce_kernel(int64_t nb, const double* __restrict__ partial,
-                                                          double* __restrict__ out, const int* run) {
+// The same partials for two dots that share b: a.b into partial, a2.b into
+// partial2 (each sum in the order of bdot_partial_kernel, so the same bits).
+__global__ void __launch_bounds__(256) bdot2_partial_kernel(int64_t n, int k, const double* __restrict__ a,
+                                                            const double* __restrict__ a2,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ partial,
+                                                            double* __restrict__ partial2, int64_t nb,
+                                                            const int* run) {
     if (run && *run == 0) return;
-    __shared__ double sh[256];
-    const int64_t c = blockIdx.x;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < nb; i += 256) s += partial[c * nb + i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
+    __shared__ double sh[2][4][BW];
+    const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+    const int64_t col = (int64_t)blockIdx.y * BW + lane;
+    const int64_t r0 = (int64_t)blockIdx.x * DOT_ROWS + wave * (DOT_ROWS / 4);
+    double s = 0.0, s2 = 0.0;
+    if (col < k) {
+        const int64_t r1 = (r0 + DOT_ROWS / 4 < n) ? r0 + DOT_ROWS / 4 : n;
+        for (int64_t i = r0; i < r1; ++i) {
+            const double bi = b[i * k + col];
+            s += a[i * k + col] * bi;
+            s2 += a2[i * k + col] * bi;
+        }
     }
-    if (threadIdx.x == 0) out[c] = sh[0];
+    sh[0][wave][lane] = s;
+    sh[1][wave][lane] = s2;
+    __syncthreads();
+    if (wave == 0 && col < k) {
+        partial[col * nb + blockIdx.x] = ((sh[0][0][lane] + sh[0][1][lane]) + sh[0][2][lane]) + sh[0][3][lane];
+        partial2[col * nb + blockIdx.x] = ((sh[1][0][lane] + sh[1][1][lane]) + sh[1][2][lane]) + sh[1][3][lane];
+    }
 }
 
-// ---- per-column CG state ------------------------------------------------------
-struct ColState {
-    double bb, rr, rz, pq, alpha, beta, rznew, zrold;
-    int active, iters, status, init;   // init: column being (re)started
-};
+// field `which` of ColState (0 bb, 1 rr, 2 rznew, 3 zrold, 4 pq)
+__device__ __forceinline__ double* state_field(ColState& s, int which) {
+    return which == 0 ? &s.bb : which == 1 ? &s.rr : which == 2 ? &s.rznew : which == 3 ? &s.zrold : &s.pq;
+}
+
+// Column c's dot = fixed-order sum of partial[set][c*nb + 0..nb), stored into
+// field which[set] of its state (only starting columns if only_init); set =
+// blockIdx.y, partial sets nb*k apart.  Each column is summed on its own, so
+// a column's bits do not depend on k.
+__global__ void __launch_bounds__(256) bdot_reduce_kernel(int64_t nb, int k, const double* __restrict__ partial,
+                                                          ColState* st, int which0, int which1, int only_init,
+                                                          const int* run) {
+    if (run && *run == 0) return;
+    __shared__ double sh[256 / BW];
+    const int64_t c = blockIdx.x;
+    const double* __restrict__ p = partial + (int64_t)blockIdx.y * nb * k + c * nb;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += 256) s += p[i];
+#pragma unroll
+    for (int o = BW / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, BW);
+    if (threadIdx.x % BW == 0) sh[threadIdx.x / BW] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+#pragma unroll
+        for (int w = 1; w < 256 / BW; ++w) t += sh[w];
+        if (!(only_init && !st[c].init)) *state_field(st[c], blockIdx.y == 0 ? which0 : which1) = t;
+    }
+}
+
 
 // Starting columns: decide activity from ||b|| and ||r0||; run = any active.
 __global__ void bcg_start_kernel(int k, ColState* st, double tol, int* run) {
@@ -459,21 +504,42 @@ __global__ void bcg_alpha_kernel(int k, ColState* st, const int* run) {
 }
 
 // x += alpha p; r_old = r; r -= alpha q   (active columns only)
-__global__ void bcg_update_kernel(int64_t n, int k, double* __restrict__ x, double* __restrict__ r,
-                                  double* __restrict__ rold, const double* __restrict__ p,
-                                  const double* __restrict__ q, const ColState* __restrict__ st,
-                                  const int* run) {
+// x += alpha p, r_old = r, r -= alpha q for the active columns, and the
+// partials of r.r of every column on the row partition and in the order of
+// bdot_partial_kernel (so the same bits as that kernel run after this one).
+__global__ void __launch_bounds__(256) bcg_update_kernel(int64_t n, int k, double* __restrict__ x,
+                                                         double* __restrict__ r, double* __restrict__ rold,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ q,
+                                                         const ColState* __restrict__ st,
+                                                         double* __restrict__ partial, int64_t nb,
+                                                         const int* run) {
     if (*run == 0) return;
-    const int64_t total = n * k;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const ColState& s = st[i % k];
-        if (!s.active) continue;
-        x[i] += s.alpha * p[i];
-        const double ri = r[i];
-        if (rold) rold[i] = ri;
-        r[i] = ri - s.alpha * q[i];
+    __shared__ double sh[4][BW];
+    const int lane = threadIdx.x % BW, wave = threadIdx.x / BW;
+    const int64_t col = (int64_t)blockIdx.y * BW + lane;
+    const int64_t r0 = (int64_t)blockIdx.x * DOT_ROWS + wave * (DOT_ROWS / 4);
+    double s = 0.0;
+    if (col < k) {
+        const bool active = st[col].active != 0;
+        const double alpha = st[col].alpha;
+        const int64_t r1 = (r0 + DOT_ROWS / 4 < n) ? r0 + DOT_ROWS / 4 : n;
+        for (int64_t i = r0; i < r1; ++i) {
+            const int64_t idx = i * k + col;
+            double rn = r[idx];
+            if (active) {
+                x[idx] += alpha * p[idx];
+                if (rold) rold[idx] = rn;
+                rn = rn - alpha * q[idx];
+                r[idx] = rn;
+            }
+            s += rn * rn;
+        }
     }
+    sh[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && col < k)
+        partial[col * nb + blockIdx.x] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
 __global__ void bcg_check_kernel(int k, ColState* st, double tol, int maxit, int* run) {
@@ -558,18 +624,6 @@ __global__ void bmark_init_kernel(int k, ColState* st, const int* slots, int ns)
     }
 }
 
-// copy a field of the column dots into the state: which = 0 bb, 1 rr, 2 rznew, 3 zrold, 4 pq
-__global__ void bstore_kernel(int k, const double* __restrict__ v, ColState* st, int which,
-                              int only_init, const int* run) {
-    if (run && *run == 0) return;
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-        if (only_init && !st[c].init) continue;
-        double* f = which == 0 ? &st[c].bb : which == 1 ? &st[c].rr : which == 2 ? &st[c].rznew
-                    : which == 3 ? &st[c].zrold : &st[c].pq;
-        *f = v[c];
-    }
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -593,7 +647,7 @@ struct BatchState {
     bool mixed = false;
     std::vector<BatchLevel> lv;
     DevBuf<double> R, Z, P, Q, Rold;
-    DevBuf<double> partial, dots;
+    DevBuf<double> partial;   // [2][k][dot blocks] column-dot partials
     DevBuf<ColState> st;
     DevBuf<int> run;
     std::map<std::string, Tile> tiles;   // tuned tile per operator and precision
@@ -884,15 +938,34 @@ void bprecondition(BatchCtx& c, const double* r, double* z) {
     }
 }
 
+int64_t dot_blocks(int64_t n) { return (n + DOT_ROWS - 1) / DOT_ROWS; }
+
+// reduce `sets` partial sets (from B.partial) into the state fields which0, which1
+void breduce(BatchCtx& c, int sets, int which0, int which1, int only_init) {
+    const int64_t nb = dot_blocks(c.H.n_nodes);
+    bdot_reduce_kernel<<<dim3((unsigned)c.k, (unsigned)sets), 256, 0, c.s()>>>(
+        nb, c.k, c.B.partial.get(), c.B.st.get(), which0, which1, only_init, c.run);
+}
+
 // column dots a.b into the state field `which` (only starting columns if only_init)
 void bdots(BatchCtx& c, const double* a, const double* b, int which, int only_init = 0) {
     const int64_t n = c.H.n_nodes;
-    const int64_t nb = (n + DOT_ROWS - 1) / DOT_ROWS;
+    const int64_t nb = dot_blocks(n);
     if (c.count_bytes) c.H.bytes += 16.0 * n * c.k;
     bdot_partial_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
         n, c.k, a, b, c.B.partial.get(), nb, c.run);
-    bdot_reduce_kernel<<<(unsigned)c.k, 256, 0, c.s()>>>(nb, c.B.partial.get(), c.B.dots.get(), c.run);
-    bstore_kernel<<<1, 256, 0, c.s()>>>(c.k, c.B.dots.get(), c.B.st.get(), which, only_init, c.run);
+    breduce(c, 1, which, which, only_init);
+}
+
+// a.b into `which` and a2.b into `which2`, reading b once
+void bdots2(BatchCtx& c, const double* a, const double* a2, const double* b, int which, int which2) {
+    const int64_t n = c.H.n_nodes;
+    const int64_t nb = dot_blocks(n);
+    if (c.count_bytes) c.H.bytes += 24.0 * n * c.k;
+    double* part = c.B.partial.get();
+    bdot2_partial_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
+        n, c.k, a, a2, b, part, part + nb * c.k, nb, c.run);
+    breduce(c, 2, which, which2, 0);
 }
 
 void bproduct_A0(BatchCtx& c, int mode, const double* v, const double* f, double* y, double rowvecs) {
@@ -913,14 +986,17 @@ void iteration(BatchCtx& c, double* X, double tol) {
     bdots(c, B.P.get(), B.Q.get(), 4);
     bcg_alpha_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), c.run);
     if (c.count_bytes) H.bytes += (B.mixed ? 56.0 : 48.0) * total;
-    bcg_update_kernel<<<bgrid(total), 256, 0, c.s()>>>(H.n_nodes, c.k, X, B.R.get(),
-                                                       B.mixed ? B.Rold.get() : nullptr, B.P.get(),
-                                                       B.Q.get(), B.st.get(), c.run);
-    bdots(c, B.R.get(), B.R.get(), 1);
+    const int64_t nb = dot_blocks(H.n_nodes);
+    bcg_update_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
+        H.n_nodes, c.k, X, B.R.get(), B.mixed ? B.Rold.get() : nullptr, B.P.get(), B.Q.get(), B.st.get(),
+        B.partial.get(), nb, c.run);
+    breduce(c, 1, 1, 1, 0);   // r.r
     bcg_check_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), tol, maxit, B.run.get());
     bprecondition(c, B.R.get(), B.Z.get());
-    bdots(c, B.R.get(), B.Z.get(), 2);
-    if (B.mixed) bdots(c, B.Rold.get(), B.Z.get(), 3);
+    if (B.mixed)
+        bdots2(c, B.R.get(), B.Rold.get(), B.Z.get(), 2, 3);
+    else
+        bdots(c, B.R.get(), B.Z.get(), 2);
     bcg_beta_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), B.mixed ? 1 : 0, c.run);
     if (c.count_bytes) H.bytes += 24.0 * total;
     bcg_direction_kernel<<<bgrid(total), 256, 0, c.s()>>>(H.n_nodes, c.k, B.Z.get(), B.P.get(), B.st.get(), 0,
@@ -946,8 +1022,7 @@ std::unique_ptr<BatchState> make_state(Handle& H, int k) {
     B->R.alloc(tot); B->Z.alloc(tot); B->P.alloc(tot); B->Q.alloc(tot);
     if (B->mixed) B->Rold.alloc(tot);
     const int64_t nb = (H.n_nodes + DOT_ROWS - 1) / DOT_ROWS;
-    B->partial.alloc((size_t)nb * k);
-    B->dots.alloc(k);
+    B->partial.alloc((size_t)nb * k * 2);
     B->st.alloc(k);
     B->run.alloc(1);
     // the caller's stream may be the legacy default stream, which cannot be
