@@ -362,8 +362,10 @@ struct ColState {
 
 // ---- column dot products with a fixed row partition ---------------------------
 // partial[(c*nb + b)] = sum over rows of block b (in order) of a[i][c] * b[i][c]
+// (b FP64, or FP32 widened exactly)
+template <typename TB>
 __global__ void __launch_bounds__(256) bdot_partial_kernel(int64_t n, int k, const double* __restrict__ a,
-                                                           const double* __restrict__ b,
+                                                           const TB* __restrict__ b,
                                                            double* __restrict__ partial, int64_t nb,
                                                            const int* run) {
     if (run && *run == 0) return;
@@ -374,7 +376,7 @@ __global__ void __launch_bounds__(256) bdot_partial_kernel(int64_t n, int k, con
     double s = 0.0;
     if (col < k) {
         const int64_t r1 = (r0 + DOT_ROWS / 4 < n) ? r0 + DOT_ROWS / 4 : n;
-        for (int64_t i = r0; i < r1; ++i) s += a[i * k + col] * b[i * k + col];
+        for (int64_t i = r0; i < r1; ++i) s += a[i * k + col] * (double)b[i * k + col];
     }
     sh[wave][lane] = s;
     __syncthreads();
@@ -384,9 +386,10 @@ __global__ void __launch_bounds__(256) bdot_partial_kernel(int64_t n, int k, con
 
 // The same partials for two dots that share b: a.b into partial, a2.b into
 // partial2 (each sum in the order of bdot_partial_kernel, so the same bits).
+template <typename TB>
 __global__ void __launch_bounds__(256) bdot2_partial_kernel(int64_t n, int k, const double* __restrict__ a,
                                                             const double* __restrict__ a2,
-                                                            const double* __restrict__ b,
+                                                            const TB* __restrict__ b,
                                                             double* __restrict__ partial,
                                                             double* __restrict__ partial2, int64_t nb,
                                                             const int* run) {
@@ -399,7 +402,7 @@ __global__ void __launch_bounds__(256) bdot2_partial_kernel(int64_t n, int k, co
     if (col < k) {
         const int64_t r1 = (r0 + DOT_ROWS / 4 < n) ? r0 + DOT_ROWS / 4 : n;
         for (int64_t i = r0; i < r1; ++i) {
-            const double bi = b[i * k + col];
+            const double bi = (double)b[i * k + col];
             s += a[i * k + col] * bi;
             s2 += a2[i * k + col] * bi;
         }
@@ -507,11 +510,13 @@ __global__ void bcg_alpha_kernel(int k, ColState* st, const int* run) {
 // x += alpha p, r_old = r, r -= alpha q for the active columns, and the
 // partials of r.r of every column on the row partition and in the order of
 // bdot_partial_kernel (so the same bits as that kernel run after this one).
+// r32 (mixed precision): every column's r rounded to FP32, the V-cycle input.
 __global__ void __launch_bounds__(256) bcg_update_kernel(int64_t n, int k, double* __restrict__ x,
                                                          double* __restrict__ r, double* __restrict__ rold,
                                                          const double* __restrict__ p,
                                                          const double* __restrict__ q,
                                                          const ColState* __restrict__ st,
+                                                         float* __restrict__ r32,
                                                          double* __restrict__ partial, int64_t nb,
                                                          const int* run) {
     if (*run == 0) return;
@@ -533,6 +538,7 @@ __global__ void __launch_bounds__(256) bcg_update_kernel(int64_t n, int k, doubl
                 rn = rn - alpha * q[idx];
                 r[idx] = rn;
             }
+            if (r32) r32[idx] = (float)rn;
             s += rn * rn;
         }
     }
@@ -584,8 +590,10 @@ __global__ void bcg_beta_kernel(int k, ColState* st, int flexible, const int* ru
     }
 }
 
-// p = z + beta p (first: p = z), active columns only
-__global__ void bcg_direction_kernel(int64_t n, int k, const double* __restrict__ z, double* __restrict__ p,
+// p = z + beta p (first: p = z), active columns only; z FP64, or the FP32
+// V-cycle output widened exactly
+template <typename TZ>
+__global__ void bcg_direction_kernel(int64_t n, int k, const TZ* __restrict__ z, double* __restrict__ p,
                                      const ColState* __restrict__ st, int first, const int* run) {
     if (*run == 0) return;
     const int64_t total = n * k;
@@ -593,7 +601,8 @@ __global__ void bcg_direction_kernel(int64_t n, int k, const double* __restrict_
          i += (int64_t)gridDim.x * blockDim.x) {
         const ColState& s = st[i % k];
         if (!s.active || (first && !s.init)) continue;
-        p[i] = first ? z[i] : z[i] + s.beta * p[i];
+        const double zi = (double)z[i];
+        p[i] = first ? zi : zi + s.beta * p[i];
     }
 }
 
@@ -925,17 +934,40 @@ void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
     bsmooth<T>(c, l, f, x, false, BL<T>::t(W), BL<T>::x(WC));
 }
 
-void bprecondition(BatchCtx& c, const double* r, double* z) {
+// z = V(r).  Mixed precision: the FP32 V-cycle runs on level 0's f32 block
+// (r rounded; r32_ready: the CG update already wrote it) and z stays in FP32
+// in level 0's x32 block, which the dots and the direction update read
+// (widened exactly, so the same values as an FP64 copy).
+void bprecondition(BatchCtx& c, const double* r, bool r32_ready) {
     const int64_t total = c.H.n_nodes * (int64_t)c.k;
     if (c.B.mixed) {
         BatchLevel& W = c.B.lv[0];
-        if (c.count_bytes) c.H.bytes += 24.0 * total;
-        bconvert_kernel<double, float><<<bgrid(total), 256, 0, c.s()>>>(total, r, W.f32.get(), 0, c.run);
+        if (!r32_ready) {
+            if (c.count_bytes) c.H.bytes += 12.0 * total;
+            bconvert_kernel<double, float><<<bgrid(total), 256, 0, c.s()>>>(total, r, W.f32.get(), 0, c.run);
+        }
         bvcycle<float>(c, 0, W.f32.get(), W.x32.get());
-        bconvert_kernel<float, double><<<bgrid(total), 256, 0, c.s()>>>(total, W.x32.get(), z, 0, c.run);
     } else {
-        bvcycle<double>(c, 0, r, z);
+        bvcycle<double>(c, 0, r, c.B.Z.get());
     }
+}
+
+// f(z) with z of the last preconditioner application: FP64 B.Z, or FP32
+// level-0 x32 in mixed precision
+template <typename F>
+void with_z(BatchCtx& c, F&& f) {
+    if (c.B.mixed)
+        f(static_cast<const float*>(c.B.lv[0].x32.get()));
+    else
+        f(static_cast<const double*>(c.B.Z.get()));
+}
+
+template <typename TZ>
+void bdirection(BatchCtx& c, const TZ* z, int first) {
+    const int64_t total = c.H.n_nodes * (int64_t)c.k;
+    if (c.count_bytes) c.H.bytes += (16.0 + sizeof(TZ)) * total;
+    bcg_direction_kernel<TZ><<<bgrid(total), 256, 0, c.s()>>>(c.H.n_nodes, c.k, z, c.B.P.get(), c.B.st.get(),
+                                                              first, c.run);
 }
 
 int64_t dot_blocks(int64_t n) { return (n + DOT_ROWS - 1) / DOT_ROWS; }
@@ -948,22 +980,24 @@ void breduce(BatchCtx& c, int sets, int which0, int which1, int only_init) {
 }
 
 // column dots a.b into the state field `which` (only starting columns if only_init)
-void bdots(BatchCtx& c, const double* a, const double* b, int which, int only_init = 0) {
+template <typename TB>
+void bdots(BatchCtx& c, const double* a, const TB* b, int which, int only_init = 0) {
     const int64_t n = c.H.n_nodes;
     const int64_t nb = dot_blocks(n);
-    if (c.count_bytes) c.H.bytes += 16.0 * n * c.k;
-    bdot_partial_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
+    if (c.count_bytes) c.H.bytes += (8.0 + sizeof(TB)) * n * c.k;
+    bdot_partial_kernel<TB><<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
         n, c.k, a, b, c.B.partial.get(), nb, c.run);
     breduce(c, 1, which, which, only_init);
 }
 
 // a.b into `which` and a2.b into `which2`, reading b once
-void bdots2(BatchCtx& c, const double* a, const double* a2, const double* b, int which, int which2) {
+template <typename TB>
+void bdots2(BatchCtx& c, const double* a, const double* a2, const TB* b, int which, int which2) {
     const int64_t n = c.H.n_nodes;
     const int64_t nb = dot_blocks(n);
-    if (c.count_bytes) c.H.bytes += 24.0 * n * c.k;
+    if (c.count_bytes) c.H.bytes += (16.0 + sizeof(TB)) * n * c.k;
     double* part = c.B.partial.get();
-    bdot2_partial_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
+    bdot2_partial_kernel<TB><<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
         n, c.k, a, a2, b, part, part + nb * c.k, nb, c.run);
     breduce(c, 2, which, which2, 0);
 }
@@ -985,22 +1019,22 @@ void iteration(BatchCtx& c, double* X, double tol) {
     bproduct_A0(c, SPMV_PLAIN, B.P.get(), nullptr, B.Q.get(), 1);
     bdots(c, B.P.get(), B.Q.get(), 4);
     bcg_alpha_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), c.run);
-    if (c.count_bytes) H.bytes += (B.mixed ? 56.0 : 48.0) * total;
+    if (c.count_bytes) H.bytes += (B.mixed ? 60.0 : 48.0) * total;
     const int64_t nb = dot_blocks(H.n_nodes);
     bcg_update_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
         H.n_nodes, c.k, X, B.R.get(), B.mixed ? B.Rold.get() : nullptr, B.P.get(), B.Q.get(), B.st.get(),
-        B.partial.get(), nb, c.run);
+        B.mixed ? B.lv[0].f32.get() : nullptr, B.partial.get(), nb, c.run);
     breduce(c, 1, 1, 1, 0);   // r.r
     bcg_check_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), tol, maxit, B.run.get());
-    bprecondition(c, B.R.get(), B.Z.get());
-    if (B.mixed)
-        bdots2(c, B.R.get(), B.Rold.get(), B.Z.get(), 2, 3);
-    else
-        bdots(c, B.R.get(), B.Z.get(), 2);
-    bcg_beta_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), B.mixed ? 1 : 0, c.run);
-    if (c.count_bytes) H.bytes += 24.0 * total;
-    bcg_direction_kernel<<<bgrid(total), 256, 0, c.s()>>>(H.n_nodes, c.k, B.Z.get(), B.P.get(), B.st.get(), 0,
-                                                          c.run);
+    bprecondition(c, B.R.get(), true);
+    with_z(c, [&](auto z) {
+        if (B.mixed)
+            bdots2(c, B.R.get(), B.Rold.get(), z, 2, 3);
+        else
+            bdots(c, B.R.get(), z, 2);
+        bcg_beta_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), B.mixed ? 1 : 0, c.run);
+        bdirection(c, z, 0);
+    });
     GIAMG_HIP(hipGetLastError());
 }
 
@@ -1019,7 +1053,8 @@ std::unique_ptr<BatchState> make_state(Handle& H, int k) {
         B->lv.push_back(std::move(W));
     }
     const size_t tot = (size_t)H.n_nodes * k;
-    B->R.alloc(tot); B->Z.alloc(tot); B->P.alloc(tot); B->Q.alloc(tot);
+    B->R.alloc(tot); B->P.alloc(tot); B->Q.alloc(tot);
+    if (!B->mixed) B->Z.alloc(tot);   // mixed precision: z stays in level 0's x32
     if (B->mixed) B->Rold.alloc(tot);
     const int64_t nb = (H.n_nodes + DOT_ROWS - 1) / DOT_ROWS;
     B->partial.alloc((size_t)nb * k * 2);
@@ -1055,10 +1090,11 @@ void start_columns(BatchCtx& c, const double* Bm, double* X, double tol) {
     bdots(c, B.R.get(), B.R.get(), 1, 1);
     bcg_start_kernel<<<1, cb, 0, s>>>(k, B.st.get(), tol, B.run.get());
     bzero_cols_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, X, B.st.get());
-    bprecondition(c, B.R.get(), B.Z.get());
-    bdots(c, B.R.get(), B.Z.get(), 2, 1);
-    bcg_direction_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, B.Z.get(), B.P.get(), B.st.get(), 1,
-                                                      B.run.get());
+    bprecondition(c, B.R.get(), false);
+    with_z(c, [&](auto z) {
+        bdots(c, B.R.get(), z, 2, 1);
+        bdirection(c, z, 1);
+    });
     bcg_start_finish_kernel<<<1, cb, 0, s>>>(k, B.st.get());
     GIAMG_HIP(hipGetLastError());
 }
@@ -1254,7 +1290,7 @@ Session* session_create(Handle& H, int k, double tol) {
     GIAMG_HIP(hipMemsetAsync(S->Bm.get(), 0, tot * sizeof(double), s));
     GIAMG_HIP(hipMemsetAsync(S->X.get(), 0, tot * sizeof(double), s));
     for (DevBuf<double>* v : {&B.R, &B.Z, &B.P, &B.Q})
-        GIAMG_HIP(hipMemsetAsync(v->get(), 0, tot * sizeof(double), s));
+        if (v->get()) GIAMG_HIP(hipMemsetAsync(v->get(), 0, tot * sizeof(double), s));
     bclear_state_kernel<<<1, 256, 0, s>>>(k, B.st.get());
     GIAMG_HIP(hipMemsetAsync(B.run.get(), 0, sizeof(int), s));
     tune_all(H, B, k);
