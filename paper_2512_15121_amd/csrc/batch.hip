@@ -337,15 +337,32 @@ __global__ void bconvert_kernel(int64_t total, const Tin* __restrict__ a, Tout* 
         b[i] = accumulate ? (Tout)(b[i] + (Tout)a[i]) : (Tout)a[i];
 }
 
-// Y = inv F for the dense coarsest inverse, FP64 accumulation.
+// Y = inv F for the dense coarsest inverse, FP64 accumulation, one row per
+// wave.  Each row sums over j in ascending order; the loads of COARSE_U
+// consecutive terms are issued before their multiply-adds, so the loop is
+// not one L2 round trip per term.
+constexpr int COARSE_U = 8;
 template <typename T>
-__global__ void bcoarse_kernel(int64_t n, int k, const double* __restrict__ inv, const T* __restrict__ f,
-                               T* __restrict__ y, const int* run) {
+__global__ void __launch_bounds__(BW) bcoarse_kernel(int64_t n, int k, const double* __restrict__ inv,
+                                                     const T* __restrict__ f, T* __restrict__ y,
+                                                     const int* run) {
     if (run && *run == 0) return;
     const int64_t row = blockIdx.x;
+    const double* __restrict__ ir = inv + row * n;
     for (int64_t col = threadIdx.x; col < k; col += blockDim.x) {
         double acc = 0.0;
-        for (int64_t j = 0; j < n; ++j) acc += inv[row * n + j] * (double)f[j * k + col];
+        int64_t j = 0;
+        for (; j + COARSE_U <= n; j += COARSE_U) {
+            double fv[COARSE_U], iv[COARSE_U];
+#pragma unroll
+            for (int u = 0; u < COARSE_U; ++u) {
+                fv[u] = (double)f[(j + u) * k + col];
+                iv[u] = ir[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < COARSE_U; ++u) acc += iv[u] * fv[u];
+        }
+        for (; j < n; ++j) acc += ir[j] * (double)f[j * k + col];
         y[row * k + col] = (T)acc;
     }
 }
@@ -908,7 +925,8 @@ void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
     const int k = c.k;
     if (l + 1 == H.levels.size()) {
         if (c.count_bytes) H.bytes += 8.0 * H.nc * H.nc + 2.0 * sizeof(T) * H.nc * k;
-        if (H.nc > 0) bcoarse_kernel<T><<<(unsigned)H.nc, 64, 0, c.s()>>>(H.nc, k, H.coarse_inv.get(), f, x, c.run);
+        if (H.nc > 0)
+            bcoarse_kernel<T><<<(unsigned)H.nc, BW, 0, c.s()>>>(H.nc, k, H.coarse_inv.get(), f, x, c.run);
         return;
     }
     BatchLevel& W = c.B.lv[l];
