@@ -140,8 +140,11 @@ void launch_fill(int64_t n, double v, double* x, hipStream_t s);
 
 // reductions: block partials then a single-block finalize
 int64_t vec_blocks(int64_t n);
-void launch_dot_partial(int64_t n, const double* a, const double* b, double* partial, hipStream_t s);
-void launch_dot2_partial(int64_t n, const double* a, const double* b, const double* c,
+// b: double, or float (widened exactly)
+template <typename TB>
+void launch_dot_partial(int64_t n, const double* a, const TB* b, double* partial, hipStream_t s);
+template <typename TB>
+void launch_dot2_partial(int64_t n, const double* a, const TB* b, const double* c,
                          double* partial, hipStream_t s);  // a.b and c.b
 // CG scalar finalisations applied after a reduction (see ScalarSlot)
 enum FinishKind : int {
@@ -177,7 +180,14 @@ void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const doub
 void launch_pcg_update_cheb0(int64_t n, double* x, double* r, const double* p, const double* q,
                              const double* scal, double* partial, const double* dinv, double* cr,
                              double* cd, double inv_theta, hipStream_t s);
-void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s);
+// The flexible-CG update (r_old = r) that also writes r_new in FP32 to f32
+// and, with dinv32 non-null, the fine level's FP32 Chebyshev init (cr, cd).
+void launch_pcg_update_mixed(int64_t n, double* x, double* r, double* rold, const double* p,
+                             const double* q, const double* scal, double* partial, float* f32,
+                             const float* dinv32, float* cr, float* cd, float inv_theta, hipStream_t s);
+// p = z + beta p; z double, or float (widened exactly)
+template <typename TZ>
+void launch_pcg_direction(int64_t n, const TZ* z, double* p, const double* scal, hipStream_t s);
 void launch_power_start(int64_t n, double* v, hipStream_t s);
 void launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
 

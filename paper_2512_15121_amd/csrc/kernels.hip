@@ -1020,8 +1020,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+// b FP64, or the FP32 output of a mixed-precision V-cycle widened exactly
+template <typename TB>
 __global__ void __launch_bounds__(VEC_THREADS) dot_partial_kernel(int64_t n, const double* __restrict__ a,
-                                                                  const double* __restrict__ b,
+                                                                  const TB* __restrict__ b,
                                                                   double* __restrict__ partial,
                                                                   const int* stop) {
     if (stopped(stop)) return;
@@ -1029,18 +1031,21 @@ __global__ void __launch_bounds__(VEC_THREADS) dot_partial_kernel(int64_t n, con
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * VEC_THREADS)
-        s += a[i] * b[i];
+        s += a[i] * (double)b[i];
     s = block_sum<VEC_THREADS>(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
-void launch_dot_partial(int64_t n, const double* a, const double* b, double* partial,
-                        hipStream_t s) {
-    dot_partial_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, partial, g_stop);
+template <typename TB>
+void launch_dot_partial(int64_t n, const double* a, const TB* b, double* partial, hipStream_t s) {
+    dot_partial_kernel<TB><<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, partial, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
+template void launch_dot_partial<double>(int64_t, const double*, const double*, double*, hipStream_t);
+template void launch_dot_partial<float>(int64_t, const double*, const float*, double*, hipStream_t);
 
+template <typename TB>
 __global__ void __launch_bounds__(VEC_THREADS) dot2_partial_kernel(int64_t n, const double* __restrict__ a,
-                                                                   const double* __restrict__ b,
+                                                                   const TB* __restrict__ b,
                                                                    const double* __restrict__ c,
                                                                    double* __restrict__ partial,
                                                                    const int* stop) {
@@ -1049,8 +1054,9 @@ __global__ void __launch_bounds__(VEC_THREADS) dot2_partial_kernel(int64_t n, co
     double s0 = 0.0, s1 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * VEC_THREADS) {
-        s0 += a[i] * b[i];
-        s1 += c[i] * b[i];
+        const double bi = (double)b[i];
+        s0 += a[i] * bi;
+        s1 += c[i] * bi;
     }
     s0 = block_sum<VEC_THREADS>(s0, sh);
     s1 = block_sum<VEC_THREADS>(s1, sh);
@@ -1059,11 +1065,16 @@ __global__ void __launch_bounds__(VEC_THREADS) dot2_partial_kernel(int64_t n, co
         partial[gridDim.x + blockIdx.x] = s1;
     }
 }
-void launch_dot2_partial(int64_t n, const double* a, const double* b, const double* c,
-                         double* partial, hipStream_t s) {
-    dot2_partial_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, c, partial, g_stop);
+template <typename TB>
+void launch_dot2_partial(int64_t n, const double* a, const TB* b, const double* c, double* partial,
+                         hipStream_t s) {
+    dot2_partial_kernel<TB><<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, a, b, c, partial, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
+template void launch_dot2_partial<double>(int64_t, const double*, const double*, const double*, double*,
+                                          hipStream_t);
+template void launch_dot2_partial<float>(int64_t, const double*, const float*, const double*, double*,
+                                         hipStream_t);
 
 // out[c] = sum_{i<m} partial[c*stride + i] for c < ncomp, fixed order; then
 // thread 0 applies the CG scalar update `fin` to the scalar block.
@@ -1169,6 +1180,46 @@ void launch_pcg_update(int64_t n, double* x, double* r, double* rold, const doub
     GIAMG_HIP(hipGetLastError());
 }
 
+// The flexible-CG update of a mixed-precision solve: also r_new rounded to
+// FP32 (f32, the V-cycle input), and with dinv32 set the fine level's FP32
+// zero-start Chebyshev init (cr = dinv32 f32, cd = cr inv_theta: the
+// operations of cheb_init0_kernel<float>, so the same bits).
+__global__ void __launch_bounds__(VEC_THREADS) pcg_update_mixed_kernel(
+    int64_t n, double* __restrict__ x, double* __restrict__ r, double* __restrict__ rold,
+    const double* __restrict__ p, const double* __restrict__ q, const double* __restrict__ scal,
+    double* __restrict__ partial, float* __restrict__ f32, const float* __restrict__ dinv32,
+    float* __restrict__ cr, float* __restrict__ cd, float inv_theta, const int* stop) {
+    if (stopped(stop)) return;
+    __shared__ double sh[VEC_THREADS];
+    const double alpha = scal[S_ALPHA];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * VEC_THREADS) {
+        x[i] += alpha * p[i];
+        const double ri = r[i];
+        rold[i] = ri;
+        const double rn = ri - alpha * q[i];
+        r[i] = rn;
+        s += rn * rn;
+        const float fi = (float)rn;
+        f32[i] = fi;
+        if (dinv32) {
+            const float res = dinv32[i] * fi;
+            cr[i] = res;
+            cd[i] = res * inv_theta;
+        }
+    }
+    s = block_sum<VEC_THREADS>(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+void launch_pcg_update_mixed(int64_t n, double* x, double* r, double* rold, const double* p,
+                             const double* q, const double* scal, double* partial, float* f32,
+                             const float* dinv32, float* cr, float* cd, float inv_theta, hipStream_t s) {
+    pcg_update_mixed_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(
+        n, x, r, rold, p, q, scal, partial, f32, dinv32, cr, cd, inv_theta, g_stop);
+    GIAMG_HIP(hipGetLastError());
+}
+
 __global__ void __launch_bounds__(VEC_THREADS) pcg_update_cheb0_kernel(
     int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, const double* __restrict__ scal, double* __restrict__ partial,
@@ -1199,18 +1250,22 @@ void launch_pcg_update_cheb0(int64_t n, double* x, double* r, const double* p, c
     GIAMG_HIP(hipGetLastError());
 }
 
-__global__ void pcg_direction_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+template <typename TZ>
+__global__ void pcg_direction_kernel(int64_t n, const TZ* __restrict__ z, double* __restrict__ p,
                                      const double* __restrict__ scal, const int* stop) {
     if (stopped(stop)) return;
     const double beta = scal[S_BETA];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
+        p[i] = (double)z[i] + beta * p[i];
 }
-void launch_pcg_direction(int64_t n, const double* z, double* p, const double* scal, hipStream_t s) {
-    pcg_direction_kernel<<<vgrid(n), VEC_THREADS, 0, s>>>(n, z, p, scal, g_stop);
+template <typename TZ>
+void launch_pcg_direction(int64_t n, const TZ* z, double* p, const double* scal, hipStream_t s) {
+    pcg_direction_kernel<TZ><<<vgrid(n), VEC_THREADS, 0, s>>>(n, z, p, scal, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
+template void launch_pcg_direction<double>(int64_t, const double*, double*, const double*, hipStream_t);
+template void launch_pcg_direction<float>(int64_t, const float*, double*, const double*, hipStream_t);
 
 // power-iteration start vector v_i = 2 u(h(i)) - 1, h = SplitMix64 stream of
 // seed 0, u = top 53 bits scaled to [0, 1)

@@ -719,19 +719,25 @@ void vcycle(Handle& H, size_t l, const T* f, T* x, bool init_done = false) {
     smooth<T>(H, L, f, x, false, LV<T>::t(L), LV<T>::x(C));
 }
 
-// z = V-cycle(r).  init_done (FP64 only): the fine level's smoother init was
-// fused into the CG update.
-void precondition(Handle& H, const double* r, double* z, bool init_done = false) {
+// z = V-cycle(r).  init_done: the fine level's smoother init was fused into
+// the CG update.  Mixed precision: the FP32 cycle runs from level 0's f32
+// (r rounded; r32_ready: the CG update wrote it) and z stays in FP32 in
+// level 0's x32 (zvec32), read by the dots and the direction update widened
+// exactly; z is not written.
+void precondition(Handle& H, const double* r, double* z, bool init_done = false, bool r32_ready = false) {
     if (H.opts.precision == GIAMG_PREC_MIXED) {
         Level& L = H.levels[0];
-        H.bytes += 24.0 * L.n;   // two conversions at the cycle boundary
-        launch_convert<double, float>(L.n, r, L.f32.get(), H.stream);
-        vcycle<float>(H, 0, L.f32.get(), L.x32.get());
-        launch_convert<float, double>(L.n, L.x32.get(), z, H.stream);
+        if (!r32_ready) {
+            H.bytes += 12.0 * L.n;
+            launch_convert<double, float>(L.n, r, L.f32.get(), H.stream);
+        }
+        vcycle<float>(H, 0, L.f32.get(), L.x32.get(), init_done);
     } else {
         vcycle<double>(H, 0, r, z, init_done);
     }
 }
+
+const float* zvec32(Handle& H) { return H.levels[0].x32.get(); }
 
 // Points the handle's stream at another one for the scope (graph capture).
 struct StreamSwap {
@@ -790,11 +796,19 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             H.host_ctl[3] = 0;
             GIAMG_HIP(hipMemcpyAsync(H.ctl.get(), H.host_ctl, C_COUNT * sizeof(int), hipMemcpyHostToDevice, s));
             precondition(H, H.r.get(), H.z.get());
-            H.bytes += 32.0 * n;
-            launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
-            launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
-                          H.scal.get());
-            launch_copy<double>(n, H.z.get(), H.p.get(), s);
+            if (flexible) {
+                H.bytes += 32.0 * n;
+                launch_dot_partial(n, H.r.get(), zvec32(H), H.partial.get(), s);
+                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
+                              H.scal.get());
+                launch_convert<float, double>(n, zvec32(H), H.p.get(), s);
+            } else {
+                H.bytes += 32.0 * n;
+                launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
+                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
+                              H.scal.get());
+                launch_copy<double>(n, H.z.get(), H.p.get(), s);
+            }
             // Iterations are queued in chunks without reading anything back:
             // the reduction that closes an iteration sets the device stop
             // flag, after which every queued kernel returns at once.  The
@@ -805,10 +819,10 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             // The iterate lives in the handle's x (copied in and out), so the
             // graph's pointers never change.
             const bool graph = H.opts.graph_launch != 0;
-            // FP64 with the Chebyshev smoother (degree >= 2): the fine
-            // level's smoother init rides on the CG update (bitwise the same
-            // vectors)
-            const bool fused = !flexible && fused_init_ok(H) && H.levels.size() > 1;
+            // Chebyshev smoother of degree >= 2: the fine level's smoother
+            // init rides on the CG update (bitwise the same vectors; FP32 in
+            // mixed precision)
+            const bool fused = fused_init_ok(H) && H.levels.size() > 1;
             double* xi = H.x.get();
             H.bytes += 16.0 * n;
             launch_copy<double>(n, x, xi, s);
@@ -820,7 +834,14 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 H.bytes += (flexible ? 56.0 : 48.0) * n;
                 run_spmv(H, SPMV_DOT, a);
                 launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, st, FIN_ALPHA, H.scal.get());
-                if (fused) {   // the update also writes level 0's Chebyshev r_0, d_0
+                if (flexible) {   // also r in FP32 (and level 0's FP32 Chebyshev r_0, d_0)
+                    Level& F = H.levels[0];
+                    H.bytes += (fused ? 16.0 : 4.0) * n;
+                    launch_pcg_update_mixed(n, xi, H.r.get(), H.rold.get(), H.p.get(), H.q.get(),
+                                            H.scal.get(), H.partial.get(), F.f32.get(),
+                                            fused ? F.dinv32.get() : nullptr, F.r32.get(), F.d032.get(),
+                                            (float)cheb_coef(H, F).inv_theta, st);
+                } else if (fused) {   // the update also writes level 0's Chebyshev r_0, d_0
                     Level& F = H.levels[0];
                     H.bytes += 24.0 * n;
                     launch_pcg_update_cheb0(n, xi, H.r.get(), H.p.get(), H.q.get(), H.scal.get(),
@@ -833,20 +854,22 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, st, FIN_CONV,
                               H.scal.get(), H.ctl.get());
                 const double b1 = H.bytes;
-                precondition(H, H.r.get(), H.z.get(), fused);
+                precondition(H, H.r.get(), H.z.get(), fused, flexible);
                 if (flexible) {
-                    H.bytes += 24.0 * n;
-                    launch_dot2_partial(n, H.r.get(), H.z.get(), H.rold.get(), H.partial.get(), st);
+                    H.bytes += 20.0 * n;
+                    launch_dot2_partial(n, H.r.get(), zvec32(H), H.rold.get(), H.partial.get(), st);
                     launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, st, FIN_BETA_FLEX,
                                   H.scal.get());
+                    H.bytes += 20.0 * n;
+                    launch_pcg_direction(n, zvec32(H), H.p.get(), H.scal.get(), st);
                 } else {
                     H.bytes += 16.0 * n;
                     launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), st);
                     launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, st, FIN_BETA,
                                   H.scal.get());
+                    H.bytes += 24.0 * n;
+                    launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), st);
                 }
-                H.bytes += 24.0 * n;
-                launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), st);
                 H.it_part1 = b1 - b0;
                 H.it_part2 = H.bytes - b1;
             };
