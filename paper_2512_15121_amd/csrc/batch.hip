@@ -528,12 +528,18 @@ __global__ void bcg_alpha_kernel(int k, ColState* st, const int* run) {
 // partials of r.r of every column on the row partition and in the order of
 // bdot_partial_kernel (so the same bits as that kernel run after this one).
 // r32 (mixed precision): every column's r rounded to FP32, the V-cycle input.
+// dinvc set: also level 0's zero-start Chebyshev init of the next V-cycle
+// (cr = dinvc f, cd = cr inv_theta with f the V-cycle input in TC: the
+// operations of bcheb_init0_kernel<TC>, so the same bits).
+template <typename TC>
 __global__ void __launch_bounds__(256) bcg_update_kernel(int64_t n, int k, double* __restrict__ x,
                                                          double* __restrict__ r, double* __restrict__ rold,
                                                          const double* __restrict__ p,
                                                          const double* __restrict__ q,
                                                          const ColState* __restrict__ st,
                                                          float* __restrict__ r32,
+                                                         const TC* __restrict__ dinvc, TC* __restrict__ cr,
+                                                         TC* __restrict__ cd, TC inv_theta,
                                                          double* __restrict__ partial, int64_t nb,
                                                          const int* run) {
     if (*run == 0) return;
@@ -556,6 +562,11 @@ __global__ void __launch_bounds__(256) bcg_update_kernel(int64_t n, int k, doubl
                 r[idx] = rn;
             }
             if (r32) r32[idx] = (float)rn;
+            if (dinvc) {
+                const TC res = dinvc[i] * (TC)rn;
+                cr[idx] = res;
+                cd[idx] = res * inv_theta;
+            }
             s += rn * rn;
         }
     }
@@ -857,7 +868,7 @@ Tile tile_for(BatchCtx& c, const DevCSR& M, const std::string& key) {
 // t = f - A x' and e: its first product is t - (A P) e.
 template <typename T>
 void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start, const T* t = nullptr,
-             const T* e = nullptr) {
+             const T* e = nullptr, bool init_done = false) {
     Handle& H = c.H;
     Level& L = H.levels[l];
     BatchLevel& W = c.B.lv[l];
@@ -891,9 +902,11 @@ void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start, const T* 
     T* r = BL<T>::r(W);
     T* d[2] = {BL<T>::d0(W), BL<T>::d1(W)};
     if (zero_start) {
-        if (c.count_bytes) H.bytes += (deg == 1 ? 5.0 : 4.0) * sizeof(T) * total;
-        bcheb_init0_kernel<T><<<bgrid(total), 256, 0, c.s()>>>(L.n, k, f, BL<T>::dinv(L), r, d[0], x,
-                                                                (T)(1.0 / theta), deg == 1, c.run);
+        if (!init_done) {
+            if (c.count_bytes) H.bytes += (deg == 1 ? 5.0 : 4.0) * sizeof(T) * total;
+            bcheb_init0_kernel<T><<<bgrid(total), 256, 0, c.s()>>>(L.n, k, f, BL<T>::dinv(L), r, d[0], x,
+                                                                    (T)(1.0 / theta), deg == 1, c.run);
+        }
     } else {
         const bool ap = e != nullptr;
         const DevCSR& M = ap ? L.AP : L.A;
@@ -918,8 +931,9 @@ void bsmooth(BatchCtx& c, size_t l, const T* f, T* x, bool zero_start, const T* 
     }
 }
 
+// init_done: level l's zero-start smoother init was written with f (fused).
 template <typename T>
-void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
+void bvcycle(BatchCtx& c, size_t l, const T* f, T* x, bool init_done = false) {
     Handle& H = c.H;
     Level& L = H.levels[l];
     const int k = c.k;
@@ -932,7 +946,7 @@ void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
     BatchLevel& W = c.B.lv[l];
     BatchLevel& WC = c.B.lv[l + 1];
     const std::string sl = std::to_string(l);
-    bsmooth<T>(c, l, f, x, true);
+    bsmooth<T>(c, l, f, x, true, nullptr, nullptr, init_done);
     {
         SpmmArgs<T> a = bargs<T>(L.A, BL<T>::A(L), k, c.run);
         a.v = x; a.f = f; a.y = BL<T>::t(W);
@@ -956,7 +970,8 @@ void bvcycle(BatchCtx& c, size_t l, const T* f, T* x) {
 // (r rounded; r32_ready: the CG update already wrote it) and z stays in FP32
 // in level 0's x32 block, which the dots and the direction update read
 // (widened exactly, so the same values as an FP64 copy).
-void bprecondition(BatchCtx& c, const double* r, bool r32_ready) {
+// init_done: the CG update also wrote level 0's smoother init.
+void bprecondition(BatchCtx& c, const double* r, bool r32_ready, bool init_done) {
     const int64_t total = c.H.n_nodes * (int64_t)c.k;
     if (c.B.mixed) {
         BatchLevel& W = c.B.lv[0];
@@ -964,10 +979,22 @@ void bprecondition(BatchCtx& c, const double* r, bool r32_ready) {
             if (c.count_bytes) c.H.bytes += 12.0 * total;
             bconvert_kernel<double, float><<<bgrid(total), 256, 0, c.s()>>>(total, r, W.f32.get(), 0, c.run);
         }
-        bvcycle<float>(c, 0, W.f32.get(), W.x32.get());
+        bvcycle<float>(c, 0, W.f32.get(), W.x32.get(), init_done);
     } else {
-        bvcycle<double>(c, 0, r, c.B.Z.get());
+        bvcycle<double>(c, 0, r, c.B.Z.get(), init_done);
     }
+}
+
+// The zero-start Chebyshev init of level 0 can ride on the CG update
+// (Chebyshev smoother of degree >= 2, a hierarchy of two levels or more).
+bool bfused_init(const Handle& H) {
+    return H.opts.smoother == GIAMG_SMOOTHER_CHEBYSHEV && H.opts.degree >= 2 && H.levels.size() > 1;
+}
+
+// 1 / theta of a level's Chebyshev interval (as bsmooth computes it)
+double binv_theta(const Handle& H, const Level& L) {
+    const double lo = H.opts.cheb_lo * L.lam_hat, hi = H.opts.cheb_hi * L.lam_hat;
+    return 1.0 / (0.5 * (hi + lo));
 }
 
 // f(z) with z of the last preconditioner application: FP64 B.Z, or FP32
@@ -1039,12 +1066,26 @@ void iteration(BatchCtx& c, double* X, double tol) {
     bcg_alpha_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), c.run);
     if (c.count_bytes) H.bytes += (B.mixed ? 60.0 : 48.0) * total;
     const int64_t nb = dot_blocks(H.n_nodes);
-    bcg_update_kernel<<<dim3((unsigned)nb, (unsigned)((c.k + BW - 1) / BW)), 256, 0, c.s()>>>(
-        H.n_nodes, c.k, X, B.R.get(), B.mixed ? B.Rold.get() : nullptr, B.P.get(), B.Q.get(), B.st.get(),
-        B.mixed ? B.lv[0].f32.get() : nullptr, B.partial.get(), nb, c.run);
+    const bool fuse = bfused_init(H);
+    const dim3 ug((unsigned)nb, (unsigned)((c.k + BW - 1) / BW));
+    Level& L0 = H.levels[0];
+    BatchLevel& W0 = B.lv[0];
+    const double it0 = binv_theta(H, L0);
+    if (B.mixed) {
+        if (c.count_bytes && fuse) H.bytes += 8.0 * total;
+        bcg_update_kernel<float><<<ug, 256, 0, c.s()>>>(
+            H.n_nodes, c.k, X, B.R.get(), B.Rold.get(), B.P.get(), B.Q.get(), B.st.get(), W0.f32.get(),
+            fuse ? L0.dinv32.get() : nullptr, W0.r32.get(), W0.d032.get(), (float)it0, B.partial.get(), nb,
+            c.run);
+    } else {
+        if (c.count_bytes && fuse) H.bytes += 16.0 * total;
+        bcg_update_kernel<double><<<ug, 256, 0, c.s()>>>(
+            H.n_nodes, c.k, X, B.R.get(), nullptr, B.P.get(), B.Q.get(), B.st.get(), nullptr,
+            fuse ? L0.dinv.get() : nullptr, W0.r.get(), W0.d0.get(), it0, B.partial.get(), nb, c.run);
+    }
     breduce(c, 1, 1, 1, 0);   // r.r
     bcg_check_kernel<<<1, cb, 0, c.s()>>>(c.k, B.st.get(), tol, maxit, B.run.get());
-    bprecondition(c, B.R.get(), true);
+    bprecondition(c, B.R.get(), true, fuse);
     with_z(c, [&](auto z) {
         if (B.mixed)
             bdots2(c, B.R.get(), B.Rold.get(), z, 2, 3);
@@ -1108,7 +1149,7 @@ void start_columns(BatchCtx& c, const double* Bm, double* X, double tol) {
     bdots(c, B.R.get(), B.R.get(), 1, 1);
     bcg_start_kernel<<<1, cb, 0, s>>>(k, B.st.get(), tol, B.run.get());
     bzero_cols_kernel<<<bgrid(total), 256, 0, s>>>(H.n_nodes, k, X, B.st.get());
-    bprecondition(c, B.R.get(), false);
+    bprecondition(c, B.R.get(), false, false);
     with_z(c, [&](auto z) {
         bdots(c, B.R.get(), z, 2, 1);
         bdirection(c, z, 1);
