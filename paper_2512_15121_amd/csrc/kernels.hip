@@ -80,8 +80,12 @@ void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, std::vector<int6
         ++rows;
     }
     if (n > 0) blocks.push_back(n);
+    // 16 lanes only for rows long enough that a block's rows fit one pass of
+    // the row sums with 16 lanes each (a block of 4096 nonzeros in rows of 34,
+    // the fine A P operator at p = 4, needs four passes with 16 lanes and one
+    // with 4)
     const double mean = n > 0 ? (double)rp[n] / (double)n : 0.0;
-    lanes = mean > 24 ? 16 : mean > 6 ? 4 : 1;
+    lanes = mean > 48 ? 16 : mean > 6 ? 4 : 1;
 }
 
 // Row-local operands of an epilogue, loaded before the row sum is known.
