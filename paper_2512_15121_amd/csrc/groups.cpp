@@ -2,8 +2,8 @@
 //
 // Rows with identical column lists are grouped (at most GROUP_ROWS rows per
 // group); a block holds groups of one size g, at most 8 / g entries per
-// thread of the product kernel and at most SPMV_THREADS rows, with its
-// distinct columns in at most SPMV_THREADS runs of consecutive ids (staged
+// thread of the product kernel and at most GROUP_THREADS rows, with its
+// distinct columns in at most GROUP_THREADS runs of consecutive ids (staged
 // in LDS by the kernel).  Blocks are ordered by their first row, so the
 // XCD-contiguous block ranges of the kernel still cover contiguous parts of
 // the mesh.  Values are reordered on the device into the planes of each
@@ -18,10 +18,10 @@ namespace giamg {
 
 namespace {
 
-constexpr int MAX_RUNS = SPMV_THREADS;   // one run descriptor per lane of a block
+constexpr int MAX_RUNS = GROUP_THREADS;   // one run descriptor per lane of a block
 constexpr int RUN_LEN = 64;              // entries a wave copies with one load
 
-int64_t max_entries(int g) { return (int64_t)SPMV_THREADS * (SPMV_CAP / SPMV_THREADS / g); }
+int64_t max_entries(int g) { return (int64_t)GROUP_THREADS * (GROUP_CAP / GROUP_THREADS / g); }
 
 // largest group size whose block can hold a group of m entries (0: none)
 int group_cap(int64_t m) {
@@ -121,7 +121,7 @@ bool build_grouping(DevCSR& d, const std::vector<int64_t>& rp, const std::vector
     if (n <= 0 || d.nnz <= 0 || (int64_t)rp.size() != n + 1 || (int64_t)ci.size() != d.nnz) return false;
     if (d.nnz >= (int64_t(1) << 31)) return false;
     for (int64_t r = 0; r < n; ++r)
-        if (rp[r + 1] - rp[r] > SPMV_CAP) return false;   // long rows: CSR form
+        if (rp[r + 1] - rp[r] > GROUP_CAP) return false;   // long rows: CSR form
 
     // 1. classes of rows with identical column lists, split into groups
     std::vector<Group> groups;
@@ -163,7 +163,7 @@ bool build_grouping(DevCSR& d, const std::vector<int64_t>& rp, const std::vector
         int64_t E = 0;
         int R = 0;
         while (q1 < groups.size() && groups[q1].g == g && E + groups[q1].m <= max_entries(g) &&
-               R + g <= SPMV_THREADS) {
+               R + g <= GROUP_THREADS) {
             E += groups[q1].m;
             R += g;
             ++q1;

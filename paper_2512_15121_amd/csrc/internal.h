@@ -114,7 +114,8 @@ struct HostCSR {
 // distinct columns its nonzeros touch, as runs of consecutive columns that
 // the product loads into LDS first).
 struct RowBlocks {
-    int cap = 0;
+    int cap = 0;              // nonzeros per block at most
+    int threads = 0;          // threads of the product kernel: rows and staged runs per block at most
     DevBuf<int64_t> rblk;     // [nblk + 1] first row of each block
     DevBuf<int64_t> bdesc;    // [4 * nblk] BlockDesc records
     int64_t nblk = 0;
@@ -143,8 +144,8 @@ struct DevCSR {
     DevBuf<double> val;
     DevBuf<float> val32;
     int lanes = 16;           // lanes per row of the row sums (mean row length)
-    RowBlocks blk;            // FP64 products: SPMV_CAP nonzeros per block
-    RowBlocks blk32;          // FP32 products: SPMV_CAP32 per block (built with val32)
+    RowBlocks blk;            // FP64 products: 8192 nonzeros and 1024 rows per block at most
+    RowBlocks blk32;          // FP32 products: 8192 nonzeros and 512 rows per block at most (val32)
     // Grouped form: rows with identical column lists share one list of LDS
     // slots (a group, at most 8 rows); a block holds groups of one size g and
     // stores its values as g planes (plane i: row i of every group, entry by
@@ -159,7 +160,7 @@ struct DevCSR {
     DevBuf<double> gval;      // [nnz]
     DevBuf<float> gval32;     // [nnz] (mixed precision)
     // Lean form: small operators (at most giamg_opts.lean_max_nnz nonzeros,
-    // no row longer than SPMV_CAP) run a kernel that reads rows straight from
+    // no row longer than 8192) run a kernel that reads rows straight from
     // memory in blocks of LEAN_THREADS / lanes rows; no staging tables.
     bool lean = false;
     int64_t lean_nblk = 0;

@@ -20,12 +20,20 @@ enum SpmvMode : int {
                          // init: y = A v, r = dinv y, x = r / theta (x holds d_0)
 };
 
-// Nonzeros one block stages in LDS; rows longer than this get a block each.
-constexpr int SPMV_CAP = 4096;
-constexpr int SPMV_CAP32 = 8192;   // FP32 products: the same LDS bytes per block
-constexpr int SPMV_THREADS = 512;
+// Row blocks of the streaming product: at most spmv_cap<T>() nonzeros (the
+// LDS products) and spmv_threads<T>() rows per block of as many threads.
+// FP64: 1024 threads, 8 nonzeros each; FP32: 512 threads, 16 each (the
+// shapes measured fastest per precision).  Rows longer than the cap get a
+// block each.
+constexpr int SPMV_CAP = 8192;
+constexpr int SPMV_CAP32 = 8192;
 template <typename T>
 constexpr int spmv_cap() { return sizeof(T) == 4 ? SPMV_CAP32 : SPMV_CAP; }
+template <typename T>
+constexpr int spmv_threads() { return sizeof(T) == 4 ? 512 : 1024; }
+// The grouped form (opt-in) keeps blocks of 512 threads and 4096 entries.
+constexpr int GROUP_THREADS = 512;
+constexpr int GROUP_CAP = 4096;
 // Lean form (small operators): threads per block; a block holds
 // LEAN_THREADS / L rows.
 constexpr int LEAN_THREADS = 256;
@@ -69,6 +77,7 @@ struct SpmvArgs {
     const int64_t* rblk = nullptr;   // row-block boundaries (nblk + 1 entries)
     const BlockDesc* bdesc = nullptr;  // per row block (nblk entries)
     int64_t nblk = 0;
+    int block_cap = 0, block_threads = 0;   // shape the row blocks were built for
     int lanes = 16;                  // lanes that reduce one row (16, 4 or 1)
     const int* stop = nullptr;       // device stop flag (null: the thread's StopScope flag)
     // host only: events the dispatch itself records at kernel start and end
@@ -99,10 +108,11 @@ template <typename T>
 void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s);
 // Greedy row blocking of a CSR operator: consecutive rows while their
 // nonzeros fit cap; the reduction width follows the mean row length.
-void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, std::vector<int64_t>& blocks, int& lanes);
+void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, int64_t max_rows, std::vector<int64_t>& blocks,
+                     int& lanes);
 // Staged-gather tables of d (run_ptr, runs, slot) from its device CSR and
 // row blocks; rp is the host copy of the row pointers.  Blocks whose columns
-// span more than STAGE_SPAN or form more than SPMV_THREADS runs, and
+// span more than STAGE_SPAN or form more than b.threads runs, and
 // long-row blocks, keep direct gathers.
 constexpr int64_t STAGE_SPAN = 262144;
 void build_staging(const DevCSR& d, RowBlocks& b, const std::vector<int64_t>& rp, hipStream_t s);

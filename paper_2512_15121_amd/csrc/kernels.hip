@@ -25,7 +25,6 @@ constexpr int WAVE = 64;
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_MAX_BLOCKS = 2048;
 constexpr int RED_THREADS = 1024;
-constexpr int64_t SPMV_MAX_ROWS = SPMV_THREADS;   // rows per block
 
 // Device stop flag handed to every kernel launched by this thread while a
 // StopScope is open (null otherwise): a kernel whose flag reads nonzero
@@ -65,13 +64,14 @@ __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, std::vector<int64_t>& blocks, int& lanes) {
+void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, int64_t max_rows, std::vector<int64_t>& blocks,
+                     int& lanes) {
     blocks.clear();
     blocks.push_back(0);
     int64_t acc = 0, rows = 0;
     for (int64_t r = 0; r < n; ++r) {
         const int64_t len = rp[r + 1] - rp[r];
-        if (rows > 0 && (acc + len > cap || rows == SPMV_MAX_ROWS)) {
+        if (rows > 0 && (acc + len > cap || rows == max_rows)) {
             blocks.push_back(r);
             acc = 0;
             rows = 0;
@@ -80,10 +80,10 @@ void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, std::vector<int6
         ++rows;
     }
     if (n > 0) blocks.push_back(n);
-    // 16 lanes only for rows long enough that a block's rows fit one pass of
-    // the row sums with 16 lanes each (a block of 4096 nonzeros in rows of 34,
-    // the fine A P operator at p = 4, needs four passes with 16 lanes and one
-    // with 4)
+    // 16 lanes only for long rows: a block's rows should take few passes of
+    // the row sums (an FP64 block of 8192 nonzeros in rows of 34, the fine
+    // A P operator at p = 4, needs four passes of 1024 threads with 16 lanes
+    // per row and one with 4)
     const double mean = n > 0 ? (double)rp[n] / (double)n : 0.0;
     lanes = mean > 48 ? 16 : mean > 6 ? 4 : 1;
 }
@@ -161,7 +161,7 @@ constexpr bool has_partials() { return MODE == SPMV_DOT || MODE == SPMV_RINIT; }
 // the same bits, addition being commutative), then every thread adds the
 // waves' sums in wave order.  One barrier; red holds 2 * NT / WAVE doubles
 // and may be reused after a further barrier.
-template <int NT = SPMV_THREADS>
+template <int NT>
 __device__ __forceinline__ void block_sum2(double* red, int tid, double& a, double& b) {
     constexpr int NW = NT / WAVE;
     a = group_sum<WAVE>(a);
@@ -221,12 +221,13 @@ __device__ __forceinline__ void stage_runs(const T* __restrict__ v, int2 dsc, in
 template <typename T>
 __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, int64_t base, int n,
                                                int nruns, T* prod) {
-    constexpr int PER = spmv_cap<T>() / SPMV_THREADS;
-    constexpr int NW = SPMV_THREADS / WAVE;
+    constexpr int NT = spmv_threads<T>();
+    constexpr int PER = spmv_cap<T>() / NT;
+    constexpr int NW = NT / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.runs) + run0;
     // runs w, w + NW, ... of this wave; a staged block has at most
-    // STAGE_MAX_RUNS = NW * WAVE runs, so one descriptor per lane
+    // NT = NW * WAVE runs, so one descriptor per lane
     const int mine = nruns > w ? (nruns - w + NW - 1) / NW : 0;
     const int2 dsc = runs[min(w + NW * lane, nruns - 1)];
     const uint16_t* __restrict__ sl = a.slot + base;
@@ -238,7 +239,7 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
         // Guarded (lanes past the block's nonzeros issue nothing): measured
         // faster here than clamped loads, and these guards add no waits
         // between the loads.  Unsigned offsets keep scalar-base addressing.
-        const unsigned idx = (unsigned)(tid + k * SPMV_THREADS);
+        const unsigned idx = (unsigned)(tid + k * NT);
         if (idx < (unsigned)n) {
             c[k] = (int)ldnt(sl + idx);
             av[k] = ldnt(val + idx);
@@ -255,7 +256,7 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int idx = tid + k * SPMV_THREADS;
+        const int idx = tid + k * NT;
         if (idx < n) prod[idx] = pr[k];
     }
 }
@@ -263,7 +264,8 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
 // Direct: column ids and values first, then the gathers.  n > 0.
 template <typename T>
 __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t base, int n, T* prod) {
-    constexpr int PER = spmv_cap<T>() / SPMV_THREADS;
+    constexpr int NT = spmv_threads<T>();
+    constexpr int PER = spmv_cap<T>() / NT;
     const int tid = threadIdx.x;
     const int32_t* __restrict__ ci = a.ci + base;
     const T* __restrict__ val = a.val + base;
@@ -272,7 +274,7 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
     T av[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const unsigned idx = min((unsigned)(tid + k * SPMV_THREADS), (unsigned)(n - 1));
+        const unsigned idx = min((unsigned)(tid + k * NT), (unsigned)(n - 1));
         c[k] = ldnt(ci + idx);
         av[k] = ldnt(val + idx);
     }
@@ -281,14 +283,15 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
     for (int k = 0; k < PER; ++k) xv[k] = v[c[k]];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int idx = tid + k * SPMV_THREADS;
+        const int idx = tid + k * NT;
         if (idx < n) prod[idx] = av[k] * xv[k];
     }
 }
 
-// Streaming CSR product.  A block owns a run of at most SPMV_THREADS whole
-// rows whose nonzeros (at most spmv_cap<T>(): 8 FP64 or 16 FP32 values per
-// thread, 32 KB of LDS either way) are contiguous, and
+// Streaming CSR product.  A block of NT = spmv_threads<T>() threads owns a
+// run of at most NT whole rows whose nonzeros (at most spmv_cap<T>(): 8 FP64
+// values per thread of 1024, 64 KB of LDS, or 16 FP32 values per thread of
+// 512, 32 KB) are contiguous, and
 // reads where they start from one 32-byte descriptor, so the value stream
 // waits on one load only:
 //  0. thread t prefetches the row-local operands of row r0 + t and the end
@@ -312,13 +315,14 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 // longer than the capacity (forms 0 and 2 only) has a block of its own, summed
 // straight from memory by the whole block.
 template <typename T, int MODE, int L, int STAGE>
-__global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(spmv_threads<T>()) __attribute__((amdgpu_waves_per_eu(8, 8)))
 spmv_stream_kernel(SpmvArgs<T> a) {
     if (stopped(a.stop)) return;
     constexpr int CAP = spmv_cap<T>();
+    constexpr int NT = spmv_threads<T>();
     __shared__ T prod[CAP];
-    __shared__ T rowsum[SPMV_THREADS];
-    __shared__ int rowoff[SPMV_THREADS + 1];
+    __shared__ T rowsum[NT];
+    __shared__ int rowoff[NT + 1];
     double* red = reinterpret_cast<double*>(prod);   // reused once products are consumed
     const int tid = threadIdx.x;
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -335,15 +339,15 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             if (tid == 0) epilogue_load<T, MODE>(a, r0, in);
             T acc0 = 0, acc1 = 0;
             int64_t i = tid;
-            for (; i + SPMV_THREADS < cnt; i += 2 * SPMV_THREADS) {
-                const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + SPMV_THREADS);
-                const T a0 = ldnt(val + i), a1 = ldnt(val + i + SPMV_THREADS);
+            for (; i + NT < cnt; i += 2 * NT) {
+                const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + NT);
+                const T a0 = ldnt(val + i), a1 = ldnt(val + i + NT);
                 acc0 += a0 * v[c0];
                 acc1 += a1 * v[c1];
             }
             if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
             double s = (double)(acc0 + acc1), unused = 0.0;
-            block_sum2(red, tid, s, unused);
+            block_sum2<NT>(red, tid, s, unused);
             const T y = (T)s;
             if (tid == 0) {
                 epilogue_store<T, MODE>(a, r0, y, in, dot, dot2);
@@ -385,7 +389,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     __syncthreads();
     // 2. row sums, L lanes per row
     const int g = tid / L, gl = tid % L;
-    for (int rr = g; rr < nrows; rr += SPMV_THREADS / L) {
+    for (int rr = g; rr < nrows; rr += NT / L) {
         const int s = rowoff[rr], e = rowoff[rr + 1];
         T acc = 0;
         for (int j = s + gl; j < e; j += L) acc += prod[j];
@@ -396,7 +400,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     // 3. row epilogues
     if (own) epilogue_store<T, MODE>(a, r0 + tid, rowsum[tid], in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
-        block_sum2(red, tid, dot, dot2);
+        block_sum2<NT>(red, tid, dot, dot2);
         if (tid == 0) {
             a.partial[lb] = dot;
             if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
@@ -418,15 +422,15 @@ spmv_stream_kernel(SpmvArgs<T> a) {
 // ---------------------------------------------------------------------------
 
 // Steps 1 and 2 for a block of G-row groups.  Thread t takes entries
-// t + k * SPMV_THREADS (k < 8 / G): per entry one slot and G values (one per
+// t + k * GROUP_THREADS (k < 8 / G): per entry one slot and G values (one per
 // plane), all loads issued before the run copies; products go to LDS plane
 // by plane (prod[i * E + e]); then groups of L lanes sum the rows.
 template <typename T, int L, int G>
 __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, const GBlock& B, int E,
                                             int R, int nruns, T* prod, T* rowsum) {
-    constexpr int KPT = SPMV_CAP / SPMV_THREADS / G;   // entries per thread
-    constexpr int NW = SPMV_THREADS / WAVE;
-    static_assert(KPT >= 1 && KPT * G <= SPMV_CAP / SPMV_THREADS, "entries per thread");
+    constexpr int KPT = GROUP_CAP / GROUP_THREADS / G;   // entries per thread
+    constexpr int NW = GROUP_THREADS / WAVE;
+    static_assert(KPT >= 1 && KPT * G <= GROUP_CAP / GROUP_THREADS, "entries per thread");
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     if (nruns > 0) {   // 0 only for blocks of empty rows (E == 0)
         const int2* __restrict__ runs = reinterpret_cast<const int2*>(a.gruns) + a.grun_ptr[lb];
@@ -438,7 +442,7 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
         T av[KPT][G];
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
-            const unsigned idx = (unsigned)(tid + k * SPMV_THREADS);
+            const unsigned idx = (unsigned)(tid + k * GROUP_THREADS);
             if (idx < (unsigned)E) {
                 c[k] = (int)ldnt(sl + idx);
 #pragma unroll
@@ -461,7 +465,7 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
-            const int idx = tid + k * SPMV_THREADS;
+            const int idx = tid + k * GROUP_THREADS;
             if (idx < E) {
 #pragma unroll
                 for (int i = 0; i < G; ++i) prod[i * E + idx] = pr[k][i];
@@ -470,7 +474,7 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
     }
     __syncthreads();
     const int gi = tid / L, gl = tid % L;
-    for (int rr = gi; rr < R; rr += SPMV_THREADS / L) {
+    for (int rr = gi; rr < R; rr += GROUP_THREADS / L) {
         const int q = rr / G, i = rr - q * G;
         const uint32_t gq = a.ggrp[B.q0 + q];
         const int s = i * E + (int)(gq >> 16), e = s + (int)(gq & 0xffffu);
@@ -484,11 +488,11 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
 // Product over the grouped form: block lb (XCD-remapped as in the CSR form)
 // owns R = G * groups rows listed in grows; thread t finishes row t.
 template <typename T, int MODE, int L>
-__global__ void __launch_bounds__(SPMV_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(GROUP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
 spmv_group_kernel(SpmvArgs<T> a) {
     if (stopped(a.stop)) return;
-    __shared__ T prod[SPMV_CAP];
-    __shared__ T rowsum[SPMV_THREADS];
+    __shared__ T prod[GROUP_CAP];
+    __shared__ T rowsum[GROUP_THREADS];
     double* red = reinterpret_cast<double*>(prod);
     const int tid = threadIdx.x;
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -515,7 +519,7 @@ spmv_group_kernel(SpmvArgs<T> a) {
     __syncthreads();
     if (tid < R) epilogue_store<T, MODE>(a, row, rowsum[tid], in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
-        block_sum2(red, tid, dot, dot2);
+        block_sum2<GROUP_THREADS>(red, tid, dot, dot2);
         if (tid == 0) {
             a.partial[lb] = dot;
             if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
@@ -532,7 +536,7 @@ spmv_group_kernel(SpmvArgs<T> a) {
 // positions gl, gl + L, ... in order, each product rounded before it is
 // added (as the LDS products of the CSR form are), and the L lanes combine
 // by the same butterfly: rows equal the CSR form's bit for bit (operators
-// with rows longer than SPMV_CAP keep the CSR form).
+// with rows longer than spmv_cap<T>() keep the CSR form).
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int L>
 __global__ void __launch_bounds__(LEAN_THREADS) spmv_lean_kernel(SpmvArgs<T> a) {
@@ -598,13 +602,12 @@ void launch_gather_values(int64_t n, const int64_t* idx, const double* x, double
 // consecutive set bits inside one word, so it holds at most 64 columns; the
 // LDS slot of a column is its rank among the set bits.  Pass 1 counts the
 // runs of each block, pass 2 writes the runs and the slot of every nonzero.
-// Blocks with more than STAGE_MAX_RUNS runs (scattered columns) are left to
+// Blocks with more than max_runs runs (one run descriptor per lane of the
+// product kernel's block; scattered columns) are left to
 // direct gathers, as are blocks spanning more than STAGE_SPAN columns.
 // ---------------------------------------------------------------------------
 constexpr int STAGE_THREADS = 512;
 constexpr int STAGE_WORDS = (int)(STAGE_SPAN / 64);
-constexpr int STAGE_MAX_RUNS = SPMV_THREADS;   // one run descriptor per lane of the block
-static_assert(STAGE_MAX_RUNS == (SPMV_THREADS / WAVE) * WAVE, "descriptor lanes");
 constexpr int STAGE_WPT = STAGE_WORDS / STAGE_THREADS;
 static_assert(STAGE_WORDS % STAGE_THREADS == 0, "bitmap words per thread");
 
@@ -628,6 +631,7 @@ template <bool FILL>
 __global__ void __launch_bounds__(STAGE_THREADS) stage_kernel(const int64_t* __restrict__ rp,
                                                              const int32_t* __restrict__ ci,
                                                              const int64_t* __restrict__ rblk, int cap,
+                                                             int max_runs,
                                                              int32_t* counts, const int32_t* run_ptr,
                                                              int32_t* runs, uint16_t* slot) {
     __shared__ unsigned long long bm[STAGE_WORDS];
@@ -690,10 +694,10 @@ __global__ void __launch_bounds__(STAGE_THREADS) stage_kernel(const int64_t* __r
     int tot_runs = 0, tot_cols = 0;
     int rex = stage_exscan(rc, sc, tid, tot_runs);
     if (!FILL) {
-        if (tid == 0) counts[b] = tot_runs <= STAGE_MAX_RUNS ? tot_runs : 0;
+        if (tid == 0) counts[b] = tot_runs <= max_runs ? tot_runs : 0;
         return;
     }
-    if (tot_runs > STAGE_MAX_RUNS) return;   // scattered columns: direct gathers
+    if (tot_runs > max_runs) return;   // scattered columns: direct gathers
     int uex = stage_exscan(pc, sc, tid, tot_cols);
     for (int w = w0; w < w1; ++w) {
         const unsigned long long x = bm[w];
@@ -731,8 +735,10 @@ void build_staging(const DevCSR& d, RowBlocks& B, const std::vector<int64_t>& rp
     if (B.nblk <= 0 || d.nnz <= 0) return;
     GIAMG_REQUIRE(B.nblk < (int64_t(1) << 31), "too many row blocks");
     DevBuf<int32_t> counts(B.nblk);
+    GIAMG_REQUIRE(B.threads > 0 && B.threads % WAVE == 0, "row blocks without a thread count");
     stage_kernel<false><<<(unsigned)B.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), B.rblk.get(), B.cap,
-                                                                  counts.get(), nullptr, nullptr, nullptr);
+                                                                  B.threads, counts.get(), nullptr, nullptr,
+                                                                  nullptr);
     GIAMG_HIP(hipGetLastError());
     std::vector<int32_t> hc(B.nblk);
     std::vector<int64_t> hb(B.nblk + 1);
@@ -756,8 +762,8 @@ void build_staging(const DevCSR& d, RowBlocks& B, const std::vector<int64_t>& rp
     GIAMG_HIP(hipMemcpyAsync(B.run_ptr.get(), ptr.data(), ptr.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, s));
     stage_kernel<true><<<(unsigned)B.nblk, STAGE_THREADS, 0, s>>>(d.rp.get(), d.ci.get(), B.rblk.get(), B.cap,
-                                                                 nullptr, B.run_ptr.get(), B.runs.get(),
-                                                                 B.slot.get());
+                                                                 B.threads, nullptr, B.run_ptr.get(),
+                                                                 B.runs.get(), B.slot.get());
     GIAMG_HIP(hipGetLastError());
     GIAMG_HIP(hipStreamSynchronize(s));
     B.nruns = total;
@@ -766,7 +772,7 @@ void build_staging(const DevCSR& d, RowBlocks& B, const std::vector<int64_t>& rp
 
 template <typename T, int MODE, int L, int STAGE>
 void launch_spmv_kernel(const SpmvArgs<T>& a, hipStream_t s) {
-    const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
+    const dim3 grid((unsigned)a.nblk), block(spmv_threads<T>());
     if (a.ev_start != nullptr)   // timing: the dispatch records the events itself
         hipExtLaunchKernelGGL(spmv_stream_kernel<T, MODE, L, STAGE>, grid, block, 0, s, a.ev_start,
                               a.ev_stop, 0, a);
@@ -776,7 +782,7 @@ void launch_spmv_kernel(const SpmvArgs<T>& a, hipStream_t s) {
 
 template <typename T, int MODE, int L>
 void launch_group_kernel(const SpmvArgs<T>& a, hipStream_t s) {
-    const dim3 grid((unsigned)a.nblk), block(SPMV_THREADS);
+    const dim3 grid((unsigned)a.nblk), block(GROUP_THREADS);
     if (a.ev_start != nullptr)
         hipExtLaunchKernelGGL(spmv_group_kernel<T, MODE, L>, grid, block, 0, s, a.ev_start, a.ev_stop, 0, a);
     else
@@ -831,8 +837,12 @@ void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
     SpmvArgs<T> a = args;
     if (a.stop == nullptr) a.stop = g_stop;
     if (a.n <= 0 || a.nblk <= 0) return;
-    if (!a.lean && a.gblk == nullptr && (a.rblk == nullptr || a.bdesc == nullptr))
-        throw Error(GIAMG_EINVAL, "operator without row blocks");
+    if (!a.lean && a.gblk == nullptr) {
+        if (a.rblk == nullptr || a.bdesc == nullptr) throw Error(GIAMG_EINVAL, "operator without row blocks");
+        // the kernel's LDS arrays hold spmv_cap<T>() products and spmv_threads<T>() rows
+        if (a.block_cap != spmv_cap<T>() || a.block_threads != spmv_threads<T>())
+            throw Error(GIAMG_EINVAL, "row blocks built for another block shape");
+    }
     switch (mode) {
         case SPMV_PLAIN: launch_spmv_mode<T, SPMV_PLAIN>(a, s); break;
         case SPMV_RESID: launch_spmv_mode<T, SPMV_RESID>(a, s); break;

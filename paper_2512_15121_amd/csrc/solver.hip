@@ -40,13 +40,14 @@ Handle::~Handle() {
 
 namespace {
 // Row blocks of capacity cap, their staging tables and descriptors.
-void build_row_blocks(const DevCSR& d, RowBlocks& B, int cap, const std::vector<int64_t>& rp,
+void build_row_blocks(const DevCSR& d, RowBlocks& B, int cap, int threads, const std::vector<int64_t>& rp,
                       hipStream_t s, int* lanes) {
     std::vector<int64_t> blocks;
     int l = 16;
-    make_row_blocks(rp.data(), d.nrows, cap, blocks, l);
+    make_row_blocks(rp.data(), d.nrows, cap, threads, blocks, l);
     if (lanes) *lanes = l;
     B.cap = cap;
+    B.threads = threads;
     B.nblk = (int64_t)blocks.size() - 1;
     B.rblk.alloc(blocks.size());
     GIAMG_HIP(hipMemcpyAsync(B.rblk.get(), blocks.data(), blocks.size() * sizeof(int64_t),
@@ -79,11 +80,11 @@ void build_row_blocks(const DevCSR& d, RowBlocks& B, int cap, const std::vector<
 }  // namespace
 
 void setup_row_blocks(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
-    build_row_blocks(d, d.blk, SPMV_CAP, rp, s, &d.lanes);
+    build_row_blocks(d, d.blk, spmv_cap<double>(), spmv_threads<double>(), rp, s, &d.lanes);
 }
 
 void setup_row_blocks32(DevCSR& d, const std::vector<int64_t>& rp, hipStream_t s) {
-    build_row_blocks(d, d.blk32, SPMV_CAP32, rp, s, nullptr);
+    build_row_blocks(d, d.blk32, spmv_cap<float>(), spmv_threads<float>(), rp, s, nullptr);
 }
 
 void upload_csr(const HostCSR& h, DevCSR& d, hipStream_t s, bool make32) {
@@ -132,6 +133,7 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
     // FP32 products use the blocks of capacity SPMV_CAP32 (spmv_cap<float>)
     const RowBlocks& B = sizeof(T) == sizeof(double) ? M.blk : M.blk32;
     a.rblk = B.rblk.get(); a.nblk = B.nblk; a.lanes = M.lanes;
+    a.block_cap = B.cap; a.block_threads = B.threads;
     a.bdesc = reinterpret_cast<const BlockDesc*>(B.bdesc.get());
     a.run_ptr = B.run_ptr.get(); a.runs = B.runs.get(); a.slot = B.slot.get();
     a.nnz_staged = B.nnz_staged; a.nruns = B.nruns;
@@ -158,7 +160,7 @@ SpmvArgs<T> args_of(const DevCSR& M, const T* val) {
 int64_t product_blocks(const DevCSR& M) { return M.lean ? M.lean_nblk : M.gnblk > 0 ? M.gnblk : M.blk.nblk; }
 
 // Lean form for the operators with at most max_nnz nonzeros and no row longer
-// than SPMV_CAP (their staging tables are released).
+// than spmv_cap<double>() (their staging tables are released).
 void assign_lean_forms(Handle& H, int64_t max_nnz) {
     for (Level& L : H.levels)
         for (DevCSR* M : {&L.A, &L.AP, &L.P, &L.R}) {
@@ -171,7 +173,7 @@ void assign_lean_forms(Handle& H, int64_t max_nnz) {
             GIAMG_HIP(hipStreamSynchronize(H.stream));
             int64_t maxlen = 0;
             for (int64_t r = 0; r < M->nrows; ++r) maxlen = std::max(maxlen, rp[r + 1] - rp[r]);
-            if (maxlen > SPMV_CAP) continue;
+            if (maxlen > spmv_cap<double>()) continue;
             const int64_t rpb = LEAN_THREADS / M->lanes;
             M->lean = true;
             M->lean_nblk = (M->nrows + rpb - 1) / rpb;
