@@ -49,8 +49,7 @@ CASES = {
     "p5_5cube_by_one": (5, 5, 2.0, "chebyshev", 0.1, 100, "dirichlet", "nodal", (4, 3, 2, 1)),
     "modal_p5_4cube_by_one": (4, 5, 2.0, "chebyshev", 0.1, 100, "dirichlet", "modal", (4, 3, 2, 1)),
     # Table 1's mesh and order with the boundary nodes kept on the coarse
-    # levels (8 -> 4 -> 2 -> 1, coarsest 27 / 343); the centre vertex row
-    # (17^3 nonzeros) is longer than a row block
+    # levels (8 -> 4 -> 2 -> 1, coarsest 27 / 343)
     "p8_2cube_keep_boundary": (2, 8, 1.0, "chebyshev", 0.1, 2000, "dirichlet", "nodal", ()),
 }
 # further options per case (oracle and library take the same names)
@@ -257,9 +256,9 @@ def test_lean_form_rows_bitwise_equal_csr(torch_dev, name):
     (FP64, and FP32 for the mixed hierarchy); solves agree to rounding (the
     CG dot partials of a lean fine level add rows over other blocks)."""
     torch, dev = torch_dev
-    s1 = _solver(name, lean_max_nnz=10 ** 9)   # every operator lean (rows up to 4096)
+    s1 = _solver(name, lean_max_nnz=10 ** 9)   # every operator lean (rows up to 8192)
     s2 = _solver(name, lean_max_nnz=0)
-    fits = _max_row(_case(name)[1].levels[0].A) <= 4096
+    fits = _max_row(_case(name)[1].levels[0].A) <= 8192
     assert s1.level(0)["lean_A"] == fits and not s2.level(0)["lean_A"]
     if fits:
         assert s1.level(0)["staged_nnz_A"] == 0 and s1.level(0)["runs_A"] == 0
@@ -554,3 +553,42 @@ def test_determinism(torch_dev):
         fresh.close()
     assert i3.iters < i1.iters < i4.iters
     s.close()
+
+
+def test_rows_longer_than_a_block(torch_dev):
+    """The centre vertex of a 2^3 mesh of order 10 with one pinned node
+    couples with 21^3 - 1 = 9260 nodes, more than a row block holds (8192
+    nonzeros in FP64 and in FP32): that row gets a block of its own, summed
+    by the whole block.  FP64 and FP32 products of the fine operator against
+    the oracle's (FP64 to 1e-12 of sum |a_ij x_j|; FP32 within the
+    worst-case bound of a 9260-term FP32 sum), and the staged and direct
+    forms bit for bit."""
+    torch, dev = torch_dev
+    from paper_2512_15121_amd import Solver, Options
+    m = synth.hex_mesh(2, 10, perturb=0.1, seed=3)
+    A, _ = assembly.assemble(m.coords, m.l2g, 10, 1.0, bc="pin")
+    A = A.tocsr()
+    n, longest = A.shape[0], _max_row(A)
+    assert longest == 21 ** 3 - 1
+    x = np.random.default_rng(21).standard_normal(n)
+    ref, bound = A @ x, abs(A) @ np.abs(x)
+    xt = _to(torch, dev, x)
+    outs = {}
+    for name, kw in (("mixed", {"precision": "mixed"}), ("direct", {"direct_gathers": 1})):
+        s = Solver(m.coords, m.l2g, 10, 1.0, Options(bc="pin", **kw))
+        y = torch.zeros(n, dtype=torch.float64, device=dev)
+        s.apply("spmv", 0, xt, out=y)
+        outs[name] = y
+        yh = y.cpu().numpy()
+        assert np.all(np.abs(yh - ref) <= 1e-12 * bound), name
+        if name == "mixed":
+            x32 = x.astype(np.float32)
+            A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), A.shape)
+            ref32 = A32 @ x32.astype(np.float64)
+            bound32 = abs(A32) @ np.abs(x32.astype(np.float64))
+            y32 = torch.zeros(n, dtype=torch.float32, device=dev)
+            s.apply("spmv", 0, _to(torch, dev, x32), out=y32, fp32=True)
+            err = np.abs(y32.cpu().numpy().astype(np.float64) - ref32)
+            assert np.all(err <= (longest + 2) * 2.0 ** -24 * bound32)
+        s.close()
+    assert torch.equal(outs["mixed"], outs["direct"])
