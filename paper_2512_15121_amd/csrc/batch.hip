@@ -1436,7 +1436,8 @@ void session_poll(Session* S, int* state, giamg_info* infos) {
 }
 
 // Copy the slot's solution to x (device, n entries) and free the slot.
-void session_retire(Session* S, int slot, double* x) {
+// The same without waiting: x is written in order on the session stream.
+void session_retire_async(Session* S, int slot, double* x) {
     GIAMG_REQUIRE(slot >= 0 && slot < S->k, "slot out of range");
     BatchState& B = *S->B;
     Handle& H = *S->H;
@@ -1446,7 +1447,11 @@ void session_retire(Session* S, int slot, double* x) {
     bgather_kernel<<<bgrid(H.n_nodes), 256, 0, B.stream>>>(H.n_nodes, S->k, slot, S->X.get(), x);
     bfree_slot_kernel<<<1, 64, 0, B.stream>>>(S->k, B.st.get(), slot);
     GIAMG_HIP(hipGetLastError());
-    GIAMG_HIP(hipStreamSynchronize(B.stream));
+}
+
+void session_retire(Session* S, int slot, double* x) {
+    session_retire_async(S, slot, x);
+    GIAMG_HIP(hipStreamSynchronize(S->B->stream));
 }
 
 hipStream_t session_stream(Session* S) { return S->B->stream; }

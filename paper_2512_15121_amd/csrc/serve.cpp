@@ -32,7 +32,7 @@ void session_admit(Session* S, const int* slot, const double* const* b, int coun
 void session_step(Session* S, int iters);
 bool session_ready(Session* S);
 void session_poll(Session* S, int* state, giamg_info* infos);
-void session_retire(Session* S, int slot, double* x);
+void session_retire_async(Session* S, int slot, double* x);
 hipStream_t session_stream(Session* S);
 int64_t session_device_bytes(const Session* S);
 
@@ -76,11 +76,9 @@ struct Group {
     Clock::time_point last_used;
     int64_t bytes = 0;
     DevBuf<double> stage;            // [slots][n] right-hand sides / results
-    double* pinned = nullptr;        // host [n]
     ~Group() {
         if (S) session_destroy(S);
         H.reset();
-        if (pinned) (void)hipHostFree(pinned);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -106,6 +104,28 @@ struct Server {
     int worker_dead = 0;     // error code once the setup worker has died
     std::string worker_msg;
     std::thread loop, setup;
+    // Pinned host staging of the loop thread: the right-hand sides admitted
+    // into, or the solutions harvested from, one group at a time ([slots][n]).
+    double* pinned = nullptr;
+    size_t pinned_n = 0;
+    hipEvent_t copied = nullptr;     // the staging copies of one admission batch are done
+    double* pinned_for(size_t n) {
+        if (n > pinned_n) {
+            if (pinned) GIAMG_HIP(hipHostFree(pinned));
+            pinned = nullptr;
+            pinned_n = 0;
+            GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), n * sizeof(double)));
+            pinned_n = n;
+        }
+        return pinned;
+    }
+    ~Server() {
+        // the groups first: they wait for their streams before freeing
+        groups.clear();
+        setup_done.clear();
+        if (pinned) (void)hipHostFree(pinned);
+        if (copied) (void)hipEventDestroy(copied);
+    }
 
     // Device bytes of a problem's group: measured after its first setup,
     // before that an estimate (mean row length (p+2)^3 on hexahedral meshes;
@@ -147,7 +167,6 @@ struct Server {
                 build_hierarchy(H, P.coords.data(), P.l2g.data());
                 g->S = session_create(H, o.slots, o.tol);
                 g->stage.alloc((size_t)o.slots * P.n_nodes);
-                GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), P.n_nodes * sizeof(double)));
                 g->slot_req.assign(o.slots, -1);
                 g->bytes = handle_device_bytes(H) + session_device_bytes(g->S) +
                            (int64_t)g->stage.n * 8;
@@ -309,18 +328,24 @@ struct Server {
                 std::vector<int> slots;
                 std::vector<const double*> ptrs;
                 const int64_t n = problems[g.problem].n_nodes;
+                // every right-hand side of the batch through its own stretch
+                // of the pinned staging, one wait for all the copies
+                double* host = pinned_for((size_t)o.slots * n);
                 for (Request* rp : kv.second) {
                     int slot = (int)(std::find(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1) - g.slot_req.begin());
                     g.slot_req[slot] = rp->id;
                     double* dst = g.stage.get() + (size_t)slot * n;
-                    std::memcpy(g.pinned, rp->b.data(), n * sizeof(double));
-                    GIAMG_HIP(hipMemcpyAsync(dst, g.pinned, n * sizeof(double), hipMemcpyHostToDevice,
+                    double* src = host + (size_t)slot * n;
+                    std::memcpy(src, rp->b.data(), n * sizeof(double));
+                    GIAMG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice,
                                              session_stream(g.S)));
-                    GIAMG_HIP(hipStreamSynchronize(session_stream(g.S)));
                     slots.push_back(slot);
                     ptrs.push_back(dst);
                 }
+                if (!copied) GIAMG_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+                GIAMG_HIP(hipEventRecord(copied, session_stream(g.S)));
                 session_admit(g.S, slots.data(), ptrs.data(), (int)slots.size());
+                GIAMG_HIP(hipEventSynchronize(copied));   // the staging is free again
                 g.last_used = Clock::now();
                 progress = true;
             }
@@ -338,19 +363,28 @@ struct Server {
                     infos.assign(o.slots, giamg_info{});
                     session_poll(g.S, state.data(), infos.data());
                     const int64_t n = problems[g.problem].n_nodes;
-                    for (int s = 0; s < o.slots; ++s) {
-                        if (g.slot_req[s] < 0 || state[s]) continue;
-                        double* dev = g.stage.get() + (size_t)s * n;
-                        session_retire(g.S, s, dev);
-                        GIAMG_HIP(hipMemcpyAsync(g.pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost,
-                                                 session_stream(g.S)));
+                    // retire every finished slot and copy the solutions out
+                    // through the pinned staging, one wait for all of them
+                    std::vector<int> done;
+                    for (int s = 0; s < o.slots; ++s)
+                        if (g.slot_req[s] >= 0 && !state[s]) done.push_back(s);
+                    if (!done.empty()) {
+                        double* host = pinned_for((size_t)o.slots * n);
+                        for (int s : done) {
+                            double* dev = g.stage.get() + (size_t)s * n;
+                            session_retire_async(g.S, s, dev);
+                            GIAMG_HIP(hipMemcpyAsync(host + (size_t)s * n, dev, n * sizeof(double),
+                                                     hipMemcpyDeviceToHost, session_stream(g.S)));
+                        }
                         GIAMG_HIP(hipStreamSynchronize(session_stream(g.S)));
                         std::lock_guard<std::mutex> lk2(mu);
-                        Request& r = requests[g.slot_req[s]];
-                        std::memcpy(r.x, g.pinned, n * sizeof(double));
-                        r.info = infos[s];
-                        finish(r, infos[s].status);
-                        g.slot_req[s] = -1;
+                        for (int s : done) {
+                            Request& r = requests[g.slot_req[s]];
+                            std::memcpy(r.x, host + (size_t)s * n, n * sizeof(double));
+                            r.info = infos[s];
+                            finish(r, infos[s].status);
+                            g.slot_req[s] = -1;
+                        }
                         progress = true;
                     }
                     g.last_used = Clock::now();
