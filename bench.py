@@ -37,10 +37,17 @@ KERNEL_SOURCES = ["paper_2512_15121_amd/csrc/kernels.hip", "paper_2512_15121_amd
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources' code: comments and blank lines do not
+    count, so editing a comment does not retire the stored counters."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -113,7 +113,7 @@ typedef struct giamg_opts {
                               slower on gfx950 */
     int32_t  pad;
     int64_t  lean_max_nnz; /* operators with at most this many nonzeros (and no row longer
-                              than 4096) are multiplied by a kernel that reads each row
+                              than 8192) are multiplied by a kernel that reads each row
                               straight from memory: a shorter chain of dependent loads
                               than the blocked, staged form, for the small coarse levels
                               (same rows, bit for bit; CG dot partials over other

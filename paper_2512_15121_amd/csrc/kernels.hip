@@ -3,7 +3,7 @@
 // The solve is HBM-bound sparse work: CSR products of the level operators
 // (Algorithm 1: smoothing, residual, restriction, prolongation), vector
 // updates and dot products of CG.  Design:
-//  * a block streams a contiguous run of up to 4096 nonzeros (whole rows)
+//  * a block streams a contiguous run of up to 8192 nonzeros (whole rows)
 //    with coalesced non-temporal loads, so the cache keeps the gathered
 //    vector, stages the products in LDS and reduces each row with a lane
 //    group sized to the operator's mean row length;
