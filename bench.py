@@ -347,8 +347,9 @@ def main():
                          "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the solve would "
+              "shard by element slabs, one process per GPU, halos exchanged over RCCL)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the CPU oracle, through the C ABI.
 
-Bars (derivations in DESIGN.md, "Tolerances"):
+Bars (each from the rounding of the operation it checks):
 * integer work bit-exact: constrained mask, every level's CSR structure of
   A, P, R and A P, next-level element maps, aggregates;
 * assembled/Galerkin values: max |a - a_o| <= 1e-12 max |a_o| per level

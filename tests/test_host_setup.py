@@ -1,9 +1,9 @@
 """Host-side setup stages of the library against the oracle (CPU only).
 
 Integer work bit-exact: constrained-node masks, CSR structures of A and P,
-next-level element maps, aggregates.  Floating point within the tolerances
-derived in the design doc: assembled values (different summation orders of the
-same quadrature) and transfer values.
+next-level element maps, aggregates.  Floating point within tolerances set
+by the arithmetic: assembled values (the same quadrature summed in another
+order: a few ulps of the largest term) and transfer values.
 """
 import numpy as np
 import pytest
