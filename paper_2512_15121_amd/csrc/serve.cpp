@@ -439,7 +439,8 @@ int giamg_server_create(const giamg_server_opts* o, giamg_server* out) {
         GIAMG_REQUIRE(o->hbm_budget > 0 && o->slots >= 1 && o->slots <= 1024 && o->chunk >= 1 &&
                           o->tol >= 0.0,
                       "bad server options");
-        auto* s = new giamg_server_s();
+        std::unique_ptr<giamg_server_s> own(new giamg_server_s());
+        giamg_server_s* s = own.get();
         s->srv.o = *o;
         GIAMG_HIP(hipGetDevice(&s->srv.device));
         s->srv.loop = std::thread([s] {
@@ -451,16 +452,26 @@ int giamg_server_create(const giamg_server_opts* o, giamg_server* out) {
                 s->srv.fail_all(GIAMG_EHIP, e.what());
             }
         });
-        s->srv.setup = std::thread([s] {
-            try {
-                s->srv.setup_main();
-            } catch (const giamg::Error& e) {
-                s->srv.worker_died(e.code, e.what());
-            } catch (const std::exception& e) {
-                s->srv.worker_died(GIAMG_EHIP, e.what());
+        try {
+            s->srv.setup = std::thread([s] {
+                try {
+                    s->srv.setup_main();
+                } catch (const giamg::Error& e) {
+                    s->srv.worker_died(e.code, e.what());
+                } catch (const std::exception& e) {
+                    s->srv.worker_died(GIAMG_EHIP, e.what());
+                }
+            });
+        } catch (...) {   // no setup worker: stop the loop before the server goes
+            {
+                std::lock_guard<std::mutex> lk(s->srv.mu);
+                s->srv.stop = true;
             }
-        });
-        *out = s;
+            s->srv.cv_work.notify_all();
+            s->srv.loop.join();
+            throw;
+        }
+        *out = own.release();
         return GIAMG_OK;
     });
 }
