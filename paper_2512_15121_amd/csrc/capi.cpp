@@ -515,7 +515,12 @@ int giamg_session_create(giamg_handle h, int32_t slots, double tol, giamg_sessio
         GIAMG_REQUIRE(out != nullptr, "out is null");
         GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
         giamg::Session* S = giamg::session_create(h->h, slots, tol);
-        *out = new giamg_session_s{S, h};
+        try {
+            *out = new giamg_session_s{S, h};
+        } catch (...) {
+            giamg::session_destroy(S);
+            throw;
+        }
         return GIAMG_OK;
     });
 }
