@@ -6,6 +6,13 @@
 * uniform meshes: the 3-D operator equals the Kronecker sum of 1-D operators
   built here from exact polynomial integration (closed-form GLL nodes);
 * perturbed meshes: 1^T M 1 is the volume, K 1 = 0, bitwise symmetry;
+* distorted elements (what pins the inverse Jacobian off the axis-aligned
+  case): the patch test -- a globally linear u lies in the trilinear-mapped
+  Q_p space, so K u vanishes on every row whose basis function vanishes on
+  the boundary, exactly, because |J| J^-T is polynomial in the reference
+  coordinates and p + 2 Gauss points integrate it; invariance of A under a
+  rigid rotation of the mesh; the manufactured-solution rate p + 1 on
+  perturbed meshes;
 * Dirichlet structure and the manufactured-solution convergence rate.
 """
 import math
@@ -23,7 +30,8 @@ from oracle import assembly, ptransfer
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 CLOSED_GLL = {1: [-1.0, 1.0], 2: [-1.0, 0.0, 1.0],
-              3: [-1.0, -1 / math.sqrt(5), 1 / math.sqrt(5), 1.0]}
+              3: [-1.0, -1 / math.sqrt(5), 1 / math.sqrt(5), 1.0],
+              4: [-1.0, -math.sqrt(3 / 7), 0.0, math.sqrt(3 / 7), 1.0]}
 
 
 def _lagrange_polys(nodes):
@@ -180,5 +188,115 @@ def _nodal_error(n, p, lam):
 def test_manufactured_solution_rate(p):
     e1 = _nodal_error(2, p, 1.0)
     e2 = _nodal_error(4, p, 1.0)
+    rate = math.log2(e1 / e2)
+    assert rate > p + 0.6, (e1, e2, rate)
+
+
+def _gll_node_positions(m, p):
+    """Physical position of every node: its element's trilinear map of the
+    eight corners evaluated at the node's closed-form GLL reference point.
+    Shared nodes get the same point from every element that holds them (a
+    trilinear map restricted to a face is fixed by the face's corners);
+    checked."""
+    g = np.array(CLOSED_GLL[p])
+    pos = np.full((m.n_nodes, 3), np.nan)
+    corners = [m.l2g[:, (p + 1) ** 2 * (cx * p) + (p + 1) * (cy * p) + cz * p]
+               for cx in (0, 1) for cy in (0, 1) for cz in (0, 1)]
+    X = np.stack([m.coords[c] for c in corners], axis=1)          # [E, 8, 3]
+    for i in range(p + 1):
+        for j in range(p + 1):
+            for k in range(p + 1):
+                t = (np.array([g[i], g[j], g[k]]) + 1.0) / 2.0
+                w = [((t[0] if cx else 1 - t[0]) * (t[1] if cy else 1 - t[1])
+                      * (t[2] if cz else 1 - t[2]))
+                     for cx in (0, 1) for cy in (0, 1) for cz in (0, 1)]
+                x = np.einsum("c,eca->ea", np.array(w), X)
+                ids = m.l2g[:, (p + 1) ** 2 * i + (p + 1) * j + k]
+                seen = ~np.isnan(pos[ids, 0])
+                assert np.allclose(pos[ids[seen]], x[seen], rtol=0, atol=1e-14)
+                pos[ids] = x
+    assert not np.isnan(pos).any()
+    return pos
+
+
+@pytest.mark.parametrize("p,perturb,seed", [(1, 0.2, 11), (2, 0.15, 12), (3, 0.2, 13),
+                                            (4, 0.1, 14), (4, 0.2, 15)])
+def test_patch_test_distorted(p, perturb, seed):
+    """K u = 0 on the rows of nodes off the boundary for u = a.x + c."""
+    m = synth.hex_mesh(3, p, perturb=perturb, seed=seed)
+    K, _ = assembly.assemble(m.coords, m.l2g, p, 0.0, bc="none")
+    x = _gll_node_positions(m, p)
+    u = x @ np.array([0.7, -1.3, 2.1]) + 0.4
+    Ku = K @ u
+    bnd = assembly.boundary_nodes(m.l2g, p, m.n_nodes)
+    scale = abs(K) @ abs(u)
+    interior = ~bnd
+    assert interior.sum() == (3 * p - 1) ** 3
+    assert np.max(np.abs(Ku[interior]) / scale[interior]) < 1e-13
+    # the boundary rows carry the flux of a and are not zero: the check is
+    # not vacuous
+    assert np.max(np.abs(Ku[bnd]) / scale[bnd]) > 1e-3
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_rotation_invariance_distorted(p):
+    """A rigid motion of the mesh leaves K and M unchanged."""
+    m = synth.hex_mesh(2, p, perturb=0.2, seed=21 + p)
+    th = np.array([0.3, -1.1, 0.7])
+    cx, cy, cz = np.cos(th)
+    sx, sy, sz = np.sin(th)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    Q = Rz @ Ry @ Rx
+    moved = m.coords @ Q.T + np.array([0.5, -2.0, 1.0])
+    A, _ = assembly.assemble(m.coords, m.l2g, p, 3.0, bc="none")
+    B, _ = assembly.assemble(moved, m.l2g, p, 3.0, bc="none")
+    assert (A.indptr == B.indptr).all() and (A.indices == B.indices).all()
+    assert np.max(np.abs(A.data - B.data)) <= 1e-13 * np.max(np.abs(A.data))
+
+
+def _refined(coarse, r, p):
+    """The mesh that splits every element of ``coarse`` into r^3: its
+    vertices are the images of the uniform r-times finer grid under the
+    coarse mesh's piecewise trilinear map, so each fine element is exactly
+    the image of a sub-cube (a trilinear map restricted to a sub-box is
+    trilinear) and the discrete spaces are nested."""
+    n0 = coarse.n
+    V = coarse.vertices.reshape(n0 + 1, n0 + 1, n0 + 1, 3)
+    fine = synth.hex_mesh(n0 * r, p)
+    y = fine.coords                                 # uniform lattice positions
+    e = np.minimum(np.floor(y * n0).astype(int), n0 - 1)
+    t = y * n0 - e
+    x = np.zeros_like(y)
+    for cx in (0, 1):
+        for cy in (0, 1):
+            for cz in (0, 1):
+                w = ((t[:, 0] if cx else 1 - t[:, 0]) * (t[:, 1] if cy else 1 - t[:, 1])
+                     * (t[:, 2] if cz else 1 - t[:, 2]))
+                x += w[:, None] * V[e[:, 0] + cx, e[:, 1] + cy, e[:, 2] + cz]
+    fine.coords = x
+    return fine
+
+
+def _nodal_error_on(m, p, lam):
+    A, cons = assembly.assemble(m.coords, m.l2g, p, lam)
+    xq = assembly.quadrature_points(m.coords, m.l2g, p)
+    f = (lam + 3 * math.pi ** 2) * np.prod(np.sin(math.pi * xq), axis=2)
+    b = assembly.load_vector(m.coords, m.l2g, p, f, cons)
+    u = spla.spsolve(A.tocsc(), b)
+    x = _gll_node_positions(m, p)
+    ue = np.prod(np.sin(math.pi * x), axis=1)
+    return np.max(np.abs(u - ue))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_manufactured_solution_rate_perturbed(p):
+    """Error at the nodes of the discrete solution on a perturbed mesh and
+    on its uniform refinement (every element split in eight): the rate of
+    an order-p method, p + 1."""
+    coarse = synth.hex_mesh(2, p, perturb=0.15, seed=31)
+    e1 = _nodal_error_on(coarse, p, 1.0)
+    e2 = _nodal_error_on(_refined(coarse, 2, p), p, 1.0)
     rate = math.log2(e1 / e2)
     assert rate > p + 0.6, (e1, e2, rate)
