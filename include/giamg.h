@@ -124,6 +124,12 @@ typedef struct giamg_opts {
                               level of Table 1, 27 rows / 343 nonzeros.  Default 0: coarse
                               levels hold the free nodes only */
     int32_t  pad2;
+    double   theta;        /* strength threshold of the smoothed-aggregation graph (Section
+                              2.5): j is a strong neighbour of i when |a_ij| >= theta
+                              sqrt(|a_ii a_jj|), an edge found in either direction kept in
+                              both; MIS-2 roots and aggregates are taken on that graph, the
+                              SPAI-0 smoothing of the tentative prolongation uses all of A.
+                              In [0, 1]; default 0: every stored off-diagonal entry */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -254,6 +260,23 @@ typedef struct giamg_level_desc {
     int64_t lean_A;        /* 1: A is multiplied in the lean form (see lean_max_nnz) */
 } giamg_level_desc;
 
+/*
+ * giamg_hierarchy_info -- sizes of the hierarchy's operators: the levels of
+ * the V-cycle of Algorithm 1 (p-levels from the element map of Section 2.2,
+ * then the smoothed-aggregation levels of Section 2.5), fine level first.
+ *
+ * n_levels host out: number of levels.
+ * rows     host out, int64 [cap]: rows of A on level l, for l < min(cap, levels).
+ * nnz      host out, int64 [cap]: stored nonzeros of A on level l.
+ * cap      entries the caller's arrays hold (>= 0; 0 with NULL arrays queries
+ *          the level count only).
+ * Returns GIAMG_OK, or GIAMG_EINVAL for a null handle, a null n_levels, a
+ * negative cap, or a null array with cap > 0.  Levels beyond cap are not
+ * written; the call reads host-side metadata only (no synchronisation).
+ */
+int giamg_hierarchy_info(giamg_handle h, int32_t* n_levels, int64_t* rows, int64_t* nnz,
+                         int32_t cap);
+
 int giamg_num_levels(giamg_handle h);
 int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out);
 
@@ -349,9 +372,10 @@ int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t
 
 /* Smoothed-aggregation transfer of Section 2.5 for a CSR operator (host
  * arrays, ascending columns; row_ptr[0] = 0 and non-decreasing, columns in
- * [0, n), else GIAMG_EINVAL): writes agg int32 [n], returns P. */
+ * [0, n), else GIAMG_EINVAL) with aggregation seed and strength threshold
+ * theta as in giamg_opts: writes agg int32 [n], returns P. */
 int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const double* val,
-                         int64_t n, uint64_t seed, int32_t* agg, int64_t* n_agg,
+                         int64_t n, uint64_t seed, double theta, int32_t* agg, int64_t* n_agg,
                          giamg_hcsr* P_out);
 
 /*

@@ -53,6 +53,7 @@ class Options:
     bc: str = "dirichlet"           # or "pin"
     pin: int = 0
     seed: int = 0                   # aggregation priority seed
+    theta: float = 0.0              # strength threshold of the aggregation graph
     power_iters: int = 20
     cheb_lo: float = 0.1
     cheb_hi: float = 1.1
@@ -100,7 +101,7 @@ def build(coords, l2g, p, lam, opts: Options = None) -> Hierarchy:
         free = np.ones(Ac.shape[0], dtype=bool)
     while (level.order == 1 and level.A.shape[0] > opts.coarse_max
            and len(H.levels) < opts.max_levels):
-        agg, roots = sa.aggregate(level.A, opts.seed)
+        agg, roots = sa.aggregate(level.A, opts.seed, opts.theta)
         n_agg = roots.size
         if n_agg >= level.A.shape[0] or n_agg == 0:
             break

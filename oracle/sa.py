@@ -6,7 +6,12 @@ constant over the aggregates, and it is smoothed with a sparse approximate
 inverse (SPAI) smoother (Broeker and Grote, 2002).  The paper defers the
 details to its Saena library; the readings taken here:
 
-* graph: the off-diagonal structural pattern of A (no strength threshold);
+* graph: the strong off-diagonal couplings of A.  j is a strong neighbour
+  of i when |a_ij| >= theta * sqrt(|a_ii a_jj|) (the strength measure of
+  Vanek, Mandel and Brezina, 1996); an edge that passes in either direction
+  is kept in both, so the graph is symmetric even when the Galerkin
+  product's rounding leaves a_ij and a_ji a few ulp apart.  theta = 0 (the
+  default) keeps every stored off-diagonal entry, explicit zeros included;
 * roots: the greedy maximal independent set of the distance-2 graph (MIS-2)
   taken in decreasing priority order, priority(i) = (h(i), i), where h(i) is
   the (i+1)-th output of SplitMix64 seeded with ``seed`` (Steele, Lea and
@@ -40,19 +45,24 @@ def priorities(n: int, seed: int):
     return [(splitmix64(seed, i), i) for i in range(n)]
 
 
-def neighbours(A: sp.csr_matrix):
-    """Adjacency lists of the off-diagonal pattern."""
-    out = []
-    for i in range(A.shape[0]):
-        cols = A.indices[A.indptr[i]:A.indptr[i + 1]]
-        out.append([int(c) for c in cols if c != i])
-    return out
+def neighbours(A: sp.csr_matrix, theta: float = 0.0):
+    """Sorted adjacency lists of the strength graph (see the module notes)."""
+    n = A.shape[0]
+    diag = np.abs(A.diagonal())
+    adj = [set() for _ in range(n)]
+    for i in range(n):
+        for s in range(A.indptr[i], A.indptr[i + 1]):
+            j = int(A.indices[s])
+            if j != i and abs(A.data[s]) >= theta * np.sqrt(diag[i] * diag[j]):
+                adj[i].add(j)
+                adj[j].add(i)
+    return [sorted(a) for a in adj]
 
 
-def mis2(A: sp.csr_matrix, seed: int):
+def mis2(A: sp.csr_matrix, seed: int, theta: float = 0.0):
     """Greedy MIS of the distance-2 graph in decreasing priority order."""
     n = A.shape[0]
-    nb = neighbours(A)
+    nb = neighbours(A, theta)
     prio = priorities(n, seed)
     order = sorted(range(n), key=lambda i: prio[i], reverse=True)
     blocked = [False] * n
@@ -69,12 +79,13 @@ def mis2(A: sp.csr_matrix, seed: int):
     return sorted(roots)
 
 
-def aggregate(A: sp.csr_matrix, seed: int):
-    """Aggregate id per node and the sorted root list."""
+def aggregate(A: sp.csr_matrix, seed: int, theta: float = 0.0):
+    """Aggregate id per node and the sorted root list (a node with no strong
+    neighbour is a root of its own aggregate)."""
     n = A.shape[0]
-    nb = neighbours(A)
+    nb = neighbours(A, theta)
     prio = priorities(n, seed)
-    roots = mis2(A, seed)
+    roots = mis2(A, seed, theta)
     agg = [-1] * n
     root_of = [-1] * n
     for a, r in enumerate(roots):

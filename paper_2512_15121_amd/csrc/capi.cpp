@@ -113,6 +113,7 @@ void check_setup_args(const double* coords, int64_t n_nodes, const int32_t* l2g,
     GIAMG_REQUIRE(o.row_groups == 0 || o.row_groups == 1, "row_groups must be 0 or 1");
     GIAMG_REQUIRE(o.lean_max_nnz >= 0, "lean_max_nnz must be >= 0");
     GIAMG_REQUIRE(o.keep_boundary == 0 || o.keep_boundary == 1, "keep_boundary must be 0 or 1");
+    GIAMG_REQUIRE(o.theta >= 0.0 && o.theta <= 1.0, "theta must be in [0, 1]");
     {
         int prev = p;
         for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
@@ -200,6 +201,7 @@ void giamg_default_opts(giamg_opts* o) {
     o->lean_max_nnz = 2000000;
     o->keep_boundary = 0;
     o->pad2 = 0;
+    o->theta = 0.0;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -258,6 +260,23 @@ int giamg_solve_batch(giamg_handle h, const double* B, double* X, int32_t k, dou
         GIAMG_REQUIRE(k >= 1, "k must be >= 1");
         GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
         return giamg::solve_batch(h->h, B, X, k, tol, infos);
+    });
+}
+
+int giamg_hierarchy_info(giamg_handle h, int32_t* n_levels, int64_t* rows, int64_t* nnz,
+                         int32_t cap) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(h != nullptr && n_levels != nullptr, "null handle or n_levels");
+        GIAMG_REQUIRE(cap >= 0, "cap must be >= 0");
+        GIAMG_REQUIRE(cap == 0 || (rows != nullptr && nnz != nullptr),
+                      "rows and nnz must be non-null when cap > 0");
+        const auto& lv = h->h.levels;
+        *n_levels = (int32_t)lv.size();
+        for (int32_t l = 0; l < cap && l < (int32_t)lv.size(); ++l) {
+            rows[l] = lv[l].n;
+            nnz[l] = lv[l].A.nnz;
+        }
+        return GIAMG_OK;
     });
 }
 
@@ -473,9 +492,11 @@ int giamg_host_p_transfer(const int32_t* l2g, int64_t n_elem, int32_t p, int32_t
 }
 
 int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
-                         uint64_t seed, int32_t* agg, int64_t* n_agg, giamg_hcsr* P_out) {
+                         uint64_t seed, double theta, int32_t* agg, int64_t* n_agg,
+                         giamg_hcsr* P_out) {
     return guarded([&]() -> int {
         GIAMG_REQUIRE(row_ptr && col && val && agg && n_agg && P_out && n > 0, "null argument");
+        GIAMG_REQUIRE(theta >= 0.0 && theta <= 1.0, "theta must be in [0, 1]");
         GIAMG_REQUIRE(n < (int64_t(1) << 31) - 1, "n exceeds the int32 index range");
         GIAMG_REQUIRE(row_ptr[0] == 0, "row_ptr[0] must be 0");
         for (int64_t i = 0; i < n; ++i)
@@ -487,7 +508,7 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
         A.val.assign(val, val + A.rp.back());
         for (auto c : A.ci) GIAMG_REQUIRE(c >= 0 && c < n, "column out of range");
         std::vector<int32_t> a;
-        giamg::HostCSR P = giamg::sa_transfer(A, seed, a, *n_agg);
+        giamg::HostCSR P = giamg::sa_transfer(A, seed, theta, a, *n_agg);
         std::memcpy(agg, a.data(), a.size() * sizeof(int32_t));
         *P_out = new giamg_hcsr_s{std::move(P)};
         return GIAMG_OK;

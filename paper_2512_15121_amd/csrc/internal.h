@@ -260,7 +260,7 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
                    int64_t n_fine, const std::vector<uint8_t>& free_mask,
                    std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis);
 // smoothed aggregation on a host copy of A: fills agg and returns P.
-HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg,
+HostCSR sa_transfer(const HostCSR& A, uint64_t seed, double theta, std::vector<int32_t>& agg,
                     int64_t& n_agg);
 HostCSR transpose(const HostCSR& M);
 // dense SPD inverse through Cholesky; returns false if not positive definite.

@@ -681,8 +681,48 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
 // smoothed aggregation (Section 2.5): MIS-2 roots by priority, aggregates,
 // tentative P, SPAI-0 smoothing
 // ---------------------------------------------------------------------------
-HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg, int64_t& n_agg) {
+HostCSR sa_transfer(const HostCSR& A, uint64_t seed, double theta, std::vector<int32_t>& agg,
+                    int64_t& n_agg) {
     const int64_t n = A.nrows;
+    // strength graph: j is a strong neighbour of i when |a_ij| >= theta
+    // sqrt(|a_ii a_jj|); an edge found in either direction is kept in both
+    // (the Galerkin rounding may leave a_ij and a_ji a few ulp apart), so
+    // the graph is symmetric.  theta = 0 keeps every stored off-diagonal
+    // entry, explicit zeros included.
+    std::vector<double> adiag(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t s = A.rp[i]; s < A.rp[i + 1]; ++s)
+            if (A.ci[s] == i) adiag[i] = std::fabs(A.val[s]);
+    auto strong = [&](int64_t i, int64_t s) {
+        const int64_t j = A.ci[s];
+        return j != i && std::fabs(A.val[s]) >= theta * std::sqrt(adiag[i] * adiag[j]);
+    };
+    std::vector<int64_t> gp(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t s = A.rp[i]; s < A.rp[i + 1]; ++s)
+            if (strong(i, s)) { ++gp[i + 1]; ++gp[A.ci[s] + 1]; }
+    for (int64_t i = 0; i < n; ++i) gp[i + 1] += gp[i];
+    std::vector<int64_t> gfill(gp.begin(), gp.end() - 1);
+    std::vector<int32_t> gc(gp[n]);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t s = A.rp[i]; s < A.rp[i + 1]; ++s)
+            if (strong(i, s)) {
+                gc[gfill[i]++] = A.ci[s];
+                gc[gfill[A.ci[s]]++] = (int32_t)i;
+            }
+    // sort each list and drop the duplicates left by edges found both ways
+    std::vector<int64_t> G(n + 1, 0);
+    {
+        int64_t w = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            std::sort(gc.begin() + gp[i], gc.begin() + gp[i + 1]);
+            const int64_t start = w;
+            for (int64_t s = gp[i]; s < gp[i + 1]; ++s)
+                if (w == start || gc[w - 1] != gc[s]) gc[w++] = gc[s];
+            G[i + 1] = w;
+        }
+        gc.resize(w);
+    }
     std::vector<uint64_t> h(n);
     for (int64_t i = 0; i < n; ++i) h[i] = splitmix64(seed, (uint64_t)i);
     auto higher = [&](int64_t a, int64_t b) {   // priority(a) > priority(b)
@@ -691,17 +731,16 @@ HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg, 
     std::vector<int64_t> order(n);
     for (int64_t i = 0; i < n; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), higher);
-    // greedy MIS of the distance-2 graph of the off-diagonal pattern
+    // greedy MIS of the distance-2 strength graph
     std::vector<uint8_t> blocked(n, 0), is_root(n, 0);
     for (int64_t v : order) {
         if (blocked[v]) continue;
         is_root[v] = 1;
         blocked[v] = 1;
-        for (int64_t s = A.rp[v]; s < A.rp[v + 1]; ++s) {
-            int64_t u = A.ci[s];
-            if (u == v) continue;
+        for (int64_t s = G[v]; s < G[v + 1]; ++s) {
+            int64_t u = gc[s];
             blocked[u] = 1;
-            for (int64_t t = A.rp[u]; t < A.rp[u + 1]; ++t) blocked[A.ci[t]] = 1;
+            for (int64_t t = G[u]; t < G[u + 1]; ++t) blocked[gc[t]] = 1;
         }
     }
     agg.assign(n, -1);
@@ -711,9 +750,8 @@ HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg, 
         if (is_root[v]) { agg[v] = (int32_t)n_agg++; root_of[v] = v; }
     for (int64_t v = 0; v < n; ++v) {
         if (!is_root[v]) continue;
-        for (int64_t s = A.rp[v]; s < A.rp[v + 1]; ++s) {
-            int64_t u = A.ci[s];
-            if (u == v) continue;
+        for (int64_t s = G[v]; s < G[v + 1]; ++s) {
+            int64_t u = gc[s];
             agg[u] = agg[v];
             root_of[u] = v;
         }
@@ -723,9 +761,9 @@ HostCSR sa_transfer(const HostCSR& A, uint64_t seed, std::vector<int32_t>& agg, 
     for (int64_t v = 0; v < n; ++v) {
         if (first[v] >= 0) continue;
         int64_t best = -1;
-        for (int64_t s = A.rp[v]; s < A.rp[v + 1]; ++s) {
-            int64_t u = A.ci[s];
-            if (u == v || first[u] < 0) continue;
+        for (int64_t s = G[v]; s < G[v + 1]; ++s) {
+            int64_t u = gc[s];
+            if (first[u] < 0) continue;
             int64_t r = first_root[u];
             if (best < 0 || higher(r, best)) best = r;
         }

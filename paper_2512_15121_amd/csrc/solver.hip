@@ -361,7 +361,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         HostCSR Ah;
         download_csr(F.A, Ah, H.stream);
         int64_t nagg = 0;
-        HostCSR P = sa_transfer(Ah, o.agg_seed, F.agg, nagg);
+        HostCSR P = sa_transfer(Ah, o.agg_seed, o.theta, F.agg, nagg);
         H.setup_ms[2] += ms_since(t0);
         if (nagg >= F.n || nagg == 0) {
             F.agg.clear();

@@ -45,7 +45,7 @@ class _Opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32),
                 ("row_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("lean_max_nnz", ctypes.c_int64), ("keep_boundary", ctypes.c_int32),
-                ("pad2", ctypes.c_int32)]
+                ("pad2", ctypes.c_int32), ("theta", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -101,6 +101,7 @@ class Options:
     row_groups: bool = False        # grouped product form where rows share column lists
     lean_max_nnz: int = 2000000     # row-direct kernel for operators up to this many nonzeros
     keep_boundary: bool = False     # coarse p-levels keep the constrained nodes
+    theta: float = 0.0              # strength threshold of the aggregation graph
 
     def _c(self) -> _Opts:
         d = asdict(self)
@@ -146,6 +147,7 @@ _SIGNATURES = {
     "giamg_free": (None, [P]),
     "giamg_solve": (I32, [P, P, P, F64, ctypes.POINTER(_Info)]),
     "giamg_solve_batch": (I32, [P, P, P, I32, F64, ctypes.POINTER(_Info)]),
+    "giamg_hierarchy_info": (I32, [P, P, P, P, I32]),
     "giamg_num_levels": (I32, [P]),
     "giamg_level_describe": (I32, [P, I32, ctypes.POINTER(_LevelDesc)]),
     "giamg_level_csr": (I32, [P, I32, I32, P, P, P]),
@@ -163,7 +165,7 @@ _SIGNATURES = {
     "giamg_host_boundary": (I32, [P, I64, I32, I64, I32, P]),
     "giamg_host_assemble": (I32, [P, I64, P, I64, I32, F64, I32, I64, I32, ctypes.POINTER(P)]),
     "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, I32, P, P, ctypes.POINTER(P)]),
-    "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, P, P, ctypes.POINTER(P)]),
+    "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, F64, P, P, ctypes.POINTER(P)]),
     "giamg_time_kernel": (I32, [P, I32, I32, I32, P, P]),
     "giamg_session_create": (I32, [P, I32, F64, ctypes.POINTER(P)]),
     "giamg_session_admit": (I32, [P, I32, P, P]),
@@ -248,11 +250,27 @@ def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
 
-def _dev(t):
+def _devs(*specs):
+    """Device pointers of the tensors in ``specs`` -- (tensor, torch dtype,
+    shape, name) each -- after checking what the library will read or write
+    through them: the C ABI takes bare pointers, so a wrong dtype or size
+    would make a kernel run past the buffer.  Every tensor's dtype, shape
+    and layout are checked before any device check, so the error names the
+    mismatch."""
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
-        raise ValueError("expected a contiguous device tensor")
-    return ctypes.c_void_p(t.data_ptr())
+    for t, dtype, shape, name in specs:
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor")
+    for t, _, _, name in specs:
+        if not t.is_cuda:
+            raise ValueError(f"{name}: expected a device tensor, got one on {t.device}")
+    return [ctypes.c_void_p(t.data_ptr()) for t, _, _, _ in specs]
 
 
 class Solver:
@@ -293,27 +311,47 @@ class Solver:
 
     # -- solves --------------------------------------------------------------
     def solve(self, b, x=None, tol=1e-10):
+        """b, x: float64 device tensors of n_nodes entries (x: initial guess,
+        overwritten with the solution; zeros when omitted)."""
         import torch
         if x is None:
             x = torch.zeros_like(b)
+        n = (self.n_nodes,)
+        bp, xp = _devs((b, torch.float64, n, "b"), (x, torch.float64, n, "x"))
         info = _Info()
-        rc = self.lib.giamg_solve(self._h, _dev(b), _dev(x), float(tol), ctypes.byref(info))
+        rc = self.lib.giamg_solve(self._h, bp, xp, float(tol), ctypes.byref(info))
         _check(rc)
         return x, SolveInfo(info.iters, info.status, info.relres, info.true_relres, info.solve_ms, info.bytes)
 
     def solve_batch(self, B, X=None, tol=1e-10):
+        """B, X: float64 device tensors [n_nodes, k], right-hand side j in
+        column j (X: initial guesses, overwritten)."""
         import torch
         if X is None:
             X = torch.zeros_like(B)
-        k = B.shape[1]
+        if not isinstance(B, torch.Tensor) or B.dim() != 2 or B.shape[1] < 1:
+            raise ValueError("B: expected a 2-D tensor [n_nodes, k] with k >= 1")
+        k = int(B.shape[1])
+        shape = (self.n_nodes, k)
+        Bp, Xp = _devs((B, torch.float64, shape, "B"), (X, torch.float64, shape, "X"))
         infos = (_Info * k)()
-        rc = self.lib.giamg_solve_batch(self._h, _dev(B), _dev(X), k, float(tol), infos)
+        rc = self.lib.giamg_solve_batch(self._h, Bp, Xp, k, float(tol), infos)
         _check(rc)
         return X, [SolveInfo(i.iters, i.status, i.relres, i.true_relres, i.solve_ms, i.bytes) for i in infos]
 
     # -- introspection -------------------------------------------------------
     def num_levels(self) -> int:
         return _check(self.lib.giamg_num_levels(self._h))
+
+    def hierarchy_info(self):
+        """(rows, nnz) of A on every level, fine level first."""
+        nl = ctypes.c_int32()
+        _check(self.lib.giamg_hierarchy_info(self._h, ctypes.byref(nl), None, None, 0))
+        rows = np.zeros(nl.value, dtype=np.int64)
+        nnz = np.zeros(nl.value, dtype=np.int64)
+        _check(self.lib.giamg_hierarchy_info(self._h, ctypes.byref(nl), _ptr(rows), _ptr(nnz),
+                                             nl.value))
+        return rows, nnz
 
     def level(self, l):
         d = _LevelDesc()
@@ -357,9 +395,35 @@ class Solver:
         return out.astype(bool)
 
     def apply(self, op, level, a, b=None, out=None, fp32=False):
+        """One V-cycle step on device vectors of the level they live on
+        (float64, or float32 with fp32=True): restrict reads level `level`
+        and writes level + 1, prolong_add reads level + 1 and updates level
+        `level`; b only for the residual."""
+        import torch
         code = OP[op] | (OP_FP32 if fp32 else 0)
-        bp = _dev(b) if b is not None else ctypes.c_void_p()
-        _check(self.lib.giamg_apply(self._h, code, level, _dev(a), bp, _dev(out)))
+        nl = self.num_levels()
+        if not 0 <= level < nl:
+            raise ValueError(f"level {level} out of range (hierarchy of {nl} levels)")
+        if op in ("restrict", "prolong_add") and level + 1 >= nl:
+            raise ValueError(f"{op} needs a coarser level below level {level}")
+        rows = self.level(level)["rows"]
+        rows_c = self.level(level + 1)["rows"] if op in ("restrict", "prolong_add") else rows
+        n_a = rows_c if op == "prolong_add" else rows
+        n_out = rows_c if op == "restrict" else rows
+        dt = torch.float32 if fp32 else torch.float64
+        if out is None:
+            raise ValueError("out is required")
+        if op == "residual" and b is None:
+            raise ValueError("the residual needs b (the iterate x)")
+        if op != "residual" and b is not None:
+            raise ValueError(f"{op} takes no b")
+        specs = [(a, dt, (n_a,), "a"), (out, dt, (n_out,), "out")]
+        if op == "residual":
+            specs.append((b, dt, (rows,), "b"))
+        ptrs = _devs(*specs)
+        ap, op_ = ptrs[0], ptrs[1]
+        bp = ptrs[2] if op == "residual" else ctypes.c_void_p()
+        _check(self.lib.giamg_apply(self._h, code, level, ap, bp, op_))
         return out
 
     def quadrature_points(self):
@@ -433,7 +497,7 @@ def host_p_transfer(l2g, p, q, n_fine, free_mask, basis="nodal"):
     return nxt, nc.value, _take_hcsr(h)
 
 
-def host_aggregate(rp, ci, val, seed=0):
+def host_aggregate(rp, ci, val, seed=0, theta=0.0):
     rp = np.ascontiguousarray(rp, dtype=np.int64)
     ci = np.ascontiguousarray(ci, dtype=np.int32)
     val = np.ascontiguousarray(val, dtype=np.float64)
@@ -441,8 +505,8 @@ def host_aggregate(rp, ci, val, seed=0):
     agg = np.zeros(n, dtype=np.int32)
     na = ctypes.c_int64()
     h = ctypes.c_void_p()
-    _check(library().giamg_host_aggregate(_ptr(rp), _ptr(ci), _ptr(val), n, seed, _ptr(agg),
-                                          ctypes.byref(na), ctypes.byref(h)))
+    _check(library().giamg_host_aggregate(_ptr(rp), _ptr(ci), _ptr(val), n, seed, float(theta),
+                                          _ptr(agg), ctypes.byref(na), ctypes.byref(h)))
     return agg, na.value, _take_hcsr(h)
 
 
@@ -463,8 +527,18 @@ class Session:
         self._keep = {}
 
     def admit(self, slots, bs):
+        """Start right-hand sides bs[i] (float64 device tensors of n_nodes
+        entries) in slots[i]."""
+        import torch
+        if len(slots) != len(bs):
+            raise ValueError("slots and bs must have the same length")
+        for s_ in slots:
+            if not 0 <= int(s_) < self.slots:
+                raise ValueError(f"slot {s_} out of range [0, {self.slots})")
+        n = (self.solver.n_nodes,)
+        devs = _devs(*[(b, torch.float64, n, f"bs[{i}]") for i, b in enumerate(bs)])
+        ptrs = (ctypes.c_void_p * len(bs))(*[d.value for d in devs])
         arr = (ctypes.c_int32 * len(slots))(*slots)
-        ptrs = (ctypes.c_void_p * len(bs))(*[b.data_ptr() for b in bs])
         for s_, b in zip(slots, bs):
             self._keep[s_] = b          # the kernels read b asynchronously
         _check(self.lib.giamg_session_admit(self._s, len(slots), arr, ptrs))
@@ -479,7 +553,11 @@ class Session:
         return running.astype(bool), [_info(i) for i in infos]
 
     def retire(self, slot, out):
-        _check(self.lib.giamg_session_retire(self._s, slot, _dev(out)))
+        import torch
+        if not 0 <= int(slot) < self.slots:
+            raise ValueError(f"slot {slot} out of range [0, {self.slots})")
+        op_, = _devs((out, torch.float64, (self.solver.n_nodes,), "out"))
+        _check(self.lib.giamg_session_retire(self._s, slot, op_))
         self._keep.pop(slot, None)
         return out
 
@@ -519,8 +597,11 @@ class Server:
         return pid.value
 
     def submit(self, problem, b):
+        if not 0 <= int(problem) < len(self._sizes):
+            raise ValueError(f"unknown problem {problem}")
         b = np.ascontiguousarray(b, dtype=np.float64)
-        assert b.size == self._sizes[problem]
+        if b.ndim != 1 or b.size != self._sizes[problem]:
+            raise ValueError(f"b: expected {self._sizes[problem]} entries, got shape {b.shape}")
         x = np.zeros_like(b)
         rid = ctypes.c_int64()
         _check(self.lib.giamg_server_submit(self._s, problem, _ptr(b), _ptr(x), ctypes.byref(rid)))

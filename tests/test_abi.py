@@ -175,7 +175,7 @@ def test_host_stages_reject_malformed_input():
     val = np.ones(4)
     for rp, word in (([1, 2, 4], b"row_ptr[0]"), ([0, 3, 2], b"non-decreasing")):
         rp = np.array(rp, dtype=np.int64)
-        rc = lib.giamg_host_aggregate(giamg._ptr(rp), giamg._ptr(col), giamg._ptr(val), 2, 0,
+        rc = lib.giamg_host_aggregate(giamg._ptr(rp), giamg._ptr(col), giamg._ptr(val), 2, 0, 0.0,
                                       giamg._ptr(agg), ctypes.byref(n_agg), ctypes.byref(out))
         assert rc == giamg.EINVAL and word in lib.giamg_last_error()
         assert not out.value
@@ -189,3 +189,34 @@ def test_host_stages_reject_malformed_input():
                                        ctypes.byref(out))
         assert rc == giamg.EINVAL, (n_elem, p, n_fine)
         assert not out.value
+
+
+def test_theta_and_hierarchy_info_validation_without_device_work():
+    """theta defaults to 0 and is checked in setup and the host aggregation
+    stage; giamg_hierarchy_info rejects a null handle."""
+    from paper_2512_15121_amd import giamg
+    import numpy as np
+    lib = giamg.library()
+    o = giamg._Opts()
+    lib.giamg_default_opts(ctypes.byref(o))
+    assert o.theta == 0.0 and giamg.Options().theta == 0.0
+    o.theta = 1.5
+    coords = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], dtype=np.float64)
+    l2g = np.arange(8, dtype=np.int32)[None, :]
+    h = ctypes.c_void_p()
+    rc = lib.giamg_setup(giamg._ptr(coords), 8, giamg._ptr(l2g), 1, 1, 1.0, ctypes.byref(o), None,
+                         ctypes.byref(h))
+    assert rc == giamg.EINVAL and b"theta" in lib.giamg_last_error()
+    assert not h.value
+    rp = np.array([0, 2, 4], dtype=np.int64)
+    col = np.array([0, 1, 0, 1], dtype=np.int32)
+    val = np.array([2.0, -1.0, -1.0, 2.0])
+    agg = np.zeros(2, dtype=np.int32)
+    n_agg = ctypes.c_int64()
+    out = ctypes.c_void_p()
+    rc = lib.giamg_host_aggregate(giamg._ptr(rp), giamg._ptr(col), giamg._ptr(val), 2, 0, -0.1,
+                                  giamg._ptr(agg), ctypes.byref(n_agg), ctypes.byref(out))
+    assert rc == giamg.EINVAL and b"theta" in lib.giamg_last_error() and not out.value
+    nl = ctypes.c_int32(-7)
+    rc = lib.giamg_hierarchy_info(None, ctypes.byref(nl), None, None, 0)
+    assert rc == giamg.EINVAL and nl.value == -7

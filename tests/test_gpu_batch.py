@@ -69,6 +69,35 @@ def test_batch_column_alone_is_bitwise_identical(env, precision):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("smoother,degree", [("chebyshev", 1), ("chebyshev", 3), ("chebyshev", 4),
+                                             ("jacobi", 3)])
+def test_batch_smoother_degrees_against_oracle(env, precision, smoother, degree):
+    """The block smoothers at every recurrence length (degree 1: one damped
+    step; 3 and 4: middle steps of the three-term recurrence; Jacobi sweeps),
+    per column against the oracle's single solve."""
+    torch, dev, m, _ = env
+    from paper_2512_15121_amd import Solver, Options
+    H = hierarchy.build(m.coords, m.l2g, 3, 0.0,
+                        hierarchy.Options(bc="pin", coarse_max=100, smoother=smoother,
+                                          degree=degree))
+    k = 5
+    B = synth.pinned_normal_batch(m.n_nodes, k, 40 + degree)
+    s = Solver(m.coords, m.l2g, 3, 0.0, Options(bc="pin", coarse_max=100, precision=precision,
+                                                smoother=smoother, degree=degree))
+    X, infos = s.solve_batch(torch.from_numpy(B).to(dev), tol=1e-10)
+    Xh = X.cpu().numpy()
+    for j in range(k):
+        ref = krylov.giamg_pcg(H, B[:, j].copy(), tol=1e-10)
+        assert infos[j].status == 0 and infos[j].true_relres < 1e-9
+        err = np.linalg.norm(Xh[:, j] - ref.x) / np.linalg.norm(ref.x)
+        if precision == "fp64":
+            assert abs(infos[j].iters - ref.iters) <= 1 and err <= 1e-9, (j, err)
+        else:
+            assert abs(infos[j].iters - ref.iters) <= 2 and err <= 1e-8, (j, err)
+    s.close()
+
+
 def test_batch_iteration_cap(env):
     torch, dev, m, H = env
     from paper_2512_15121_amd import Solver, Options, giamg

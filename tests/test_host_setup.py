@@ -88,6 +88,34 @@ def test_aggregation_against_oracle(n, seed):
     assert np.max(np.abs(val - P_o.data)) <= 1e-15
 
 
+@pytest.mark.parametrize("n,seed,theta", [(8, 3, 0.05), (9, 77, 0.1)])
+def test_aggregation_with_strength_threshold_against_oracle(n, seed, theta):
+    """Strength threshold theta > 0 (the graph drops weak couplings): the
+    library's aggregates and P equal the oracle's.  Both decide strength on
+    the same host values; the test first checks that no coupling lies within
+    1e-9 of the threshold, so the integer result does not hang on rounding."""
+    m = synth.hex_mesh(n, 1, perturb=0.2, seed=5)
+    A, cons = assembly.assemble(m.coords, m.l2g, 1, 0.3)
+    free = np.nonzero(~cons)[0]
+    Af = A[free][:, free].tocsr()
+    Af.sort_indices()
+    d = np.abs(Af.diagonal())
+    C = Af.tocoo()
+    off = C.row != C.col
+    ratio = np.abs(C.data[off]) / np.sqrt(d[C.row[off]] * d[C.col[off]])
+    assert np.min(np.abs(ratio - theta)) > 1e-9
+    assert (ratio < theta).any() and (ratio >= theta).any()     # the threshold bites
+    agg_o, roots = sa.aggregate(Af, seed, theta)
+    agg0, roots0 = sa.aggregate(Af, seed, 0.0)
+    assert not np.array_equal(agg_o, agg0)
+    P_o, _, _ = sa.smoothed_prolongation(Af, agg_o, roots.size)
+    agg, na, (rp, ci, val, shape) = giamg.host_aggregate(Af.indptr, Af.indices, Af.data, seed,
+                                                         theta)
+    assert na == roots.size and np.array_equal(agg, agg_o)
+    assert np.array_equal(rp, P_o.indptr) and np.array_equal(ci, P_o.indices)
+    assert np.max(np.abs(val - P_o.data)) <= 1e-15
+
+
 # ---- modal basis (appendix ordering, injection transfers) ----------------
 @pytest.mark.parametrize("n,p", [(3, 2), (2, 5)])
 def test_modal_boundary_bitexact(n, p):

@@ -129,3 +129,54 @@ def test_hierarchy_sizes_p2_12cube():
     assert H.levels[-1].A.shape[0] <= 500
     for lv, nxt in zip(H.levels[:-1], H.levels[1:]):
         assert lv.P.shape == (lv.A.shape[0], nxt.A.shape[0])
+
+
+def _anisotropic_2d(nx, ny, eps):
+    """5-point operator on an nx x ny grid, node iy * nx + ix: coupling -1
+    along x, -eps along y, diagonal 2 + 2 eps (Dirichlet closure)."""
+    n = nx * ny
+    rows, cols, vals = [], [], []
+    for iy in range(ny):
+        for ix in range(nx):
+            i = iy * nx + ix
+            rows.append(i); cols.append(i); vals.append(2.0 + 2.0 * eps)
+            for dx, dy, w in ((1, 0, -1.0), (-1, 0, -1.0), (0, 1, -eps), (0, -1, -eps)):
+                jx, jy = ix + dx, iy + dy
+                if 0 <= jx < nx and 0 <= jy < ny:
+                    rows.append(i); cols.append(jy * nx + jx); vals.append(w)
+    return assembly.csr_from_sorted_or_not(np.array(rows), np.array(cols), np.array(vals), n, n)
+
+
+def test_strength_threshold_semicoarsens_anisotropy():
+    """With a strength threshold the aggregates follow the strong direction
+    (the textbook behaviour of smoothed aggregation on an anisotropic
+    operator): every aggregate lies in one grid row and is a run of
+    consecutive nodes; with theta = 0 the weak couplings count and
+    aggregates cross rows."""
+    nx, ny = 17, 9
+    A = _anisotropic_2d(nx, ny, 0.01)
+    agg, roots = sa.aggregate(A, 5, theta=0.25)
+    iy = np.arange(nx * ny) // nx
+    ix = np.arange(nx * ny) % nx
+    for a in range(roots.size):
+        mem = np.nonzero(agg == a)[0]
+        assert np.unique(iy[mem]).size == 1
+        xs = np.sort(ix[mem])
+        assert (np.diff(xs) == 1).all() and 1 <= xs.size <= 5
+    agg0, roots0 = sa.aggregate(A, 5, theta=0.0)
+    assert any(np.unique(iy[agg0 == a]).size > 1 for a in range(roots0.size))
+    assert roots.size > roots0.size
+
+
+def test_strength_graph_is_symmetric_union():
+    """An edge that passes the threshold in one direction only is kept in
+    both; a node with no strong neighbour is a root of its own aggregate."""
+    A = sp.csr_matrix(np.array([[4.0, -1.0, 0.0, -0.1],
+                                [-0.9, 4.0, -1.0, 0.0],
+                                [0.0, -1.0, 4.0, 0.0],
+                                [-0.1, 0.0, 0.0, 4.0]]))
+    # threshold theta * 4 = 0.96: (0,1) passes as -1.0, its mirror -0.9 fails
+    nb = sa.neighbours(A, theta=0.24)
+    assert nb == [[1], [0, 2], [1], []]
+    agg, roots = sa.aggregate(A, 0, theta=0.24)
+    assert 3 in set(roots.tolist()) and (agg == agg[3]).sum() == 1
