@@ -75,7 +75,11 @@ def test_batch_column_alone_is_bitwise_identical(env, precision):
 def test_batch_smoother_degrees_against_oracle(env, precision, smoother, degree):
     """The block smoothers at every recurrence length (degree 1: one damped
     step; 3 and 4: middle steps of the three-term recurrence; Jacobi sweeps),
-    per column against the oracle's single solve."""
+    per column against the oracle's single solve.  The mixed path is flexible
+    CG around an FP32 cycle: its bar is the error against the FP64 oracle
+    and the true residual; its iteration count may drift a few from the FP64
+    count (a quarter, at least two) as the FP32 preconditioner changes the
+    Krylov space."""
     torch, dev, m, _ = env
     from paper_2512_15121_amd import Solver, Options
     H = hierarchy.build(m.coords, m.l2g, 3, 0.0,
@@ -94,7 +98,8 @@ def test_batch_smoother_degrees_against_oracle(env, precision, smoother, degree)
         if precision == "fp64":
             assert abs(infos[j].iters - ref.iters) <= 1 and err <= 1e-9, (j, err)
         else:
-            assert abs(infos[j].iters - ref.iters) <= 2 and err <= 1e-8, (j, err)
+            assert abs(infos[j].iters - ref.iters) <= max(2, ref.iters // 4), (j, infos[j].iters)
+            assert err <= 1e-8, (j, err)
     s.close()
 
 
