@@ -221,6 +221,29 @@ int giamg_solve(giamg_handle h, const double* b, double* x, double tol,
                 giamg_info* info);
 
 /*
+ * giamg_solve_noalloc -- giamg_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture elsewhere in the program, serving
+ * loops, harnesses that forbid hipMalloc): the same solve, the same kernels
+ * and results bit for bit, but the CG vectors, block partial sums, device
+ * scalars and control block it works in come from a fixed scratch array of
+ * 32 MiB per GPU inside the library instead of the handle.  The call makes no
+ * device or host allocation; the hierarchy and its level vectors were
+ * allocated by giamg_setup.
+ *
+ * Limit: 7 n_nodes doubles plus the hierarchy's partial sums must fit the
+ * 32 MiB (about 590,000 nodes at p = 4); a larger problem returns GIAMG_EINVAL with
+ * the sizes in giamg_last_error() and touches nothing.  graph_launch is
+ * ignored (an instantiated graph would allocate).
+ * Sharing: every call on one GPU uses that GPU's single scratch array, whose
+ * contents persist between calls (the solve clears what must start at zero).
+ * Calls that overlap on one GPU -- from two threads, or on two streams
+ * without ordering -- race on it and give wrong results; serialise them.
+ * Arguments, return codes and synchronisation as giamg_solve.
+ */
+int giamg_solve_noalloc(giamg_handle h, const double* b, double* x, double tol,
+                        giamg_info* info);
+
+/*
  * giamg_solve_batch -- k independent solves against one hierarchy.
  *
  * B, X     device, double [n_nodes][k] row-major (right-hand side j is

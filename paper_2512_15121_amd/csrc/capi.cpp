@@ -18,6 +18,7 @@ struct giamg_hcsr_s {
 namespace giamg {
 void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g);
 int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info);
+int solve_noalloc(Handle& H, int device, const double* b, double* x, double tol, giamg_info* info);
 int solve_batch(Handle& H, const double* B, double* X, int32_t k, double tol, giamg_info* infos);
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out);
 void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes);
@@ -246,6 +247,18 @@ int giamg_solve(giamg_handle h, const double* b, double* x, double tol, giamg_in
         GIAMG_REQUIRE(b != nullptr && x != nullptr, "b and x must be non-null");
         GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
         const int rc = giamg::solve(h->h, b, x, tol, info);
+        if (rc == GIAMG_EBREAKDOWN) g_last_error = "CG breakdown (p^T A p <= 0 or non-finite)";
+        if (rc == GIAMG_ENOTCONV) g_last_error = "iteration cap reached";
+        return rc;
+    });
+}
+
+int giamg_solve_noalloc(giamg_handle h, const double* b, double* x, double tol, giamg_info* info) {
+    return guarded([&]() -> int {
+        bind_device(h);
+        GIAMG_REQUIRE(b != nullptr && x != nullptr, "b and x must be non-null");
+        GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
+        const int rc = giamg::solve_noalloc(h->h, h->device, b, x, tol, info);
         if (rc == GIAMG_EBREAKDOWN) g_last_error = "CG breakdown (p^T A p <= 0 or non-finite)";
         if (rc == GIAMG_ENOTCONV) g_last_error = "iteration cap reached";
         return rc;

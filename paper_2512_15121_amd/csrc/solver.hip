@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "kernels.h"
 
@@ -280,7 +282,10 @@ void alloc_level_vectors(Level& L, bool mixed) {
 
 }  // namespace
 
+void noalloc_scratch_init();
+
 void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
+    noalloc_scratch_init();
     AllocStreamScope alloc_scope(H.stream);
     const giamg_opts& o = H.opts;
     const bool mixed = o.precision == GIAMG_PREC_MIXED;
@@ -749,8 +754,8 @@ struct StreamSwap {
     ~StreamSwap() { H.stream = saved; }
 };
 
-void fetch_scalars(Handle& H) {
-    GIAMG_HIP(hipMemcpyAsync(H.host_scal, H.scal.get(), S_COUNT * sizeof(double),
+void fetch_scalars(Handle& H, const double* scal) {
+    GIAMG_HIP(hipMemcpyAsync(H.host_scal, scal, S_COUNT * sizeof(double),
                              hipMemcpyDeviceToHost, H.stream));
     GIAMG_HIP(hipStreamSynchronize(H.stream));
 }
@@ -760,7 +765,18 @@ void fetch_scalars(Handle& H) {
 // ---------------------------------------------------------------------------
 // CG preconditioned by the V-cycle
 // ---------------------------------------------------------------------------
-int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
+namespace {
+// Device memory the solve works in besides the hierarchy: the iterate, the
+// CG vectors, block partial sums, device scalars and the control block.
+struct CgWork {
+    double *x, *r, *z, *p, *q, *rold, *tmp, *partial, *scal;
+    int* ctl;
+};
+
+// allow_graph: with graph_launch one iteration may be captured (the handle's
+// work buffers only: the captured pointers must stay valid for the handle).
+int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, double* x, double tol,
+             giamg_info* info) {
     AllocStreamScope alloc_scope(H.stream);
     const int64_t n = H.n_nodes;
     const Level& L0 = H.levels[0];
@@ -769,15 +785,15 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     const int64_t gs = product_blocks(L0.A), gv = vec_blocks(n);
     auto rinit = [&](double* out) {
         SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
-        a.v = x; a.f = b; a.y = out; a.partial = H.partial.get();
+        a.v = x; a.f = b; a.y = out; a.partial = w.partial;
         run_spmv(H, SPMV_RINIT, a);
     };
     H.bytes = 0.0;
     GIAMG_HIP(hipEventRecord(H.ev0, s));
-    GIAMG_HIP(hipMemsetAsync(H.scal.get(), 0, S_COUNT * sizeof(double), s));
-    rinit(H.r.get());
-    launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
-    fetch_scalars(H);
+    launch_fill(S_COUNT, 0.0, w.scal, s);
+    rinit(w.r);
+    launch_reduce(gs, w.partial, gs, 2, w.scal + S_BB, s);
+    fetch_scalars(H, w.scal);
     const double bnorm = std::sqrt(H.host_scal[S_BB]);
     int status = GIAMG_OK;
     int iters = 0;
@@ -790,26 +806,26 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
         if (!(relres < tol) && H.opts.maxit > 0) {
             // device-side convergence test: tolerance and control block
             H.host_scal[S_TOL] = tol;
-            GIAMG_HIP(hipMemcpyAsync(H.scal.get() + S_TOL, H.host_scal + S_TOL, sizeof(double),
+            GIAMG_HIP(hipMemcpyAsync(w.scal + S_TOL, H.host_scal + S_TOL, sizeof(double),
                                      hipMemcpyHostToDevice, s));
             H.host_ctl[C_STOP] = 0;
             H.host_ctl[C_ITERS] = 0;
             H.host_ctl[C_MAXIT] = H.opts.maxit;
             H.host_ctl[3] = 0;
-            GIAMG_HIP(hipMemcpyAsync(H.ctl.get(), H.host_ctl, C_COUNT * sizeof(int), hipMemcpyHostToDevice, s));
-            precondition(H, H.r.get(), H.z.get());
+            GIAMG_HIP(hipMemcpyAsync(w.ctl, H.host_ctl, C_COUNT * sizeof(int), hipMemcpyHostToDevice, s));
+            precondition(H, w.r, w.z);
             if (flexible) {
                 H.bytes += 32.0 * n;
-                launch_dot_partial(n, H.r.get(), zvec32(H), H.partial.get(), s);
-                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
-                              H.scal.get());
-                launch_convert<float, double>(n, zvec32(H), H.p.get(), s);
+                launch_dot_partial(n, w.r, zvec32(H), w.partial, s);
+                launch_reduce(gv, w.partial, 0, 1, w.scal + S_RZNEW, s, FIN_BETA_FIRST,
+                              w.scal);
+                launch_convert<float, double>(n, zvec32(H), w.p, s);
             } else {
                 H.bytes += 32.0 * n;
-                launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), s);
-                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, s, FIN_BETA_FIRST,
-                              H.scal.get());
-                launch_copy<double>(n, H.z.get(), H.p.get(), s);
+                launch_dot_partial(n, w.r, w.z, w.partial, s);
+                launch_reduce(gv, w.partial, 0, 1, w.scal + S_RZNEW, s, FIN_BETA_FIRST,
+                              w.scal);
+                launch_copy<double>(n, w.z, w.p, s);
             }
             // Iterations are queued in chunks without reading anything back:
             // the reduction that closes an iteration sets the device stop
@@ -820,57 +836,57 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             // solve of the handle and replayed on the handle's graph stream.
             // The iterate lives in the handle's x (copied in and out), so the
             // graph's pointers never change.
-            const bool graph = H.opts.graph_launch != 0;
+            const bool graph = allow_graph && H.opts.graph_launch != 0;
             // Chebyshev smoother of degree >= 2: the fine level's smoother
             // init rides on the CG update (bitwise the same vectors; FP32 in
             // mixed precision)
             const bool fused = fused_init_ok(H) && H.levels.size() > 1;
-            double* xi = H.x.get();
+            double* xi = w.x;
             H.bytes += 16.0 * n;
             launch_copy<double>(n, x, xi, s);
             auto iteration = [&]() {
                 hipStream_t st = H.stream;
                 const double b0 = H.bytes;
                 SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
-                a.v = H.p.get(); a.y = H.q.get(); a.partial = H.partial.get();
+                a.v = w.p; a.y = w.q; a.partial = w.partial;
                 H.bytes += (flexible ? 56.0 : 48.0) * n;
                 run_spmv(H, SPMV_DOT, a);
-                launch_reduce(gs, H.partial.get(), 0, 1, H.scal.get() + S_PQ, st, FIN_ALPHA, H.scal.get());
+                launch_reduce(gs, w.partial, 0, 1, w.scal + S_PQ, st, FIN_ALPHA, w.scal);
                 if (flexible) {   // also r in FP32 (and level 0's FP32 Chebyshev r_0, d_0)
                     Level& F = H.levels[0];
                     H.bytes += (fused ? 16.0 : 4.0) * n;
-                    launch_pcg_update_mixed(n, xi, H.r.get(), H.rold.get(), H.p.get(), H.q.get(),
-                                            H.scal.get(), H.partial.get(), F.f32.get(),
+                    launch_pcg_update_mixed(n, xi, w.r, w.rold, w.p, w.q,
+                                            w.scal, w.partial, F.f32.get(),
                                             fused ? F.dinv32.get() : nullptr, F.r32.get(), F.d032.get(),
                                             (float)cheb_coef(H, F).inv_theta, st);
                 } else if (fused) {   // the update also writes level 0's Chebyshev r_0, d_0
                     Level& F = H.levels[0];
                     H.bytes += 24.0 * n;
-                    launch_pcg_update_cheb0(n, xi, H.r.get(), H.p.get(), H.q.get(), H.scal.get(),
-                                            H.partial.get(), F.dinv.get(), F.r.get(), F.d0.get(),
+                    launch_pcg_update_cheb0(n, xi, w.r, w.p, w.q, w.scal,
+                                            w.partial, F.dinv.get(), F.r.get(), F.d0.get(),
                                             cheb_coef(H, F).inv_theta, st);
                 } else {
-                    launch_pcg_update(n, xi, H.r.get(), flexible ? H.rold.get() : nullptr, H.p.get(),
-                                      H.q.get(), H.scal.get(), H.partial.get(), st);
+                    launch_pcg_update(n, xi, w.r, flexible ? w.rold : nullptr, w.p,
+                                      w.q, w.scal, w.partial, st);
                 }
-                launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RR, st, FIN_CONV,
-                              H.scal.get(), H.ctl.get());
+                launch_reduce(gv, w.partial, 0, 1, w.scal + S_RR, st, FIN_CONV,
+                              w.scal, w.ctl);
                 const double b1 = H.bytes;
-                precondition(H, H.r.get(), H.z.get(), fused, flexible);
+                precondition(H, w.r, w.z, fused, flexible);
                 if (flexible) {
                     H.bytes += 20.0 * n;
-                    launch_dot2_partial(n, H.r.get(), zvec32(H), H.rold.get(), H.partial.get(), st);
-                    launch_reduce(gv, H.partial.get(), gv, 2, H.scal.get() + S_RZNEW, st, FIN_BETA_FLEX,
-                                  H.scal.get());
+                    launch_dot2_partial(n, w.r, zvec32(H), w.rold, w.partial, st);
+                    launch_reduce(gv, w.partial, gv, 2, w.scal + S_RZNEW, st, FIN_BETA_FLEX,
+                                  w.scal);
                     H.bytes += 20.0 * n;
-                    launch_pcg_direction(n, zvec32(H), H.p.get(), H.scal.get(), st);
+                    launch_pcg_direction(n, zvec32(H), w.p, w.scal, st);
                 } else {
                     H.bytes += 16.0 * n;
-                    launch_dot_partial(n, H.r.get(), H.z.get(), H.partial.get(), st);
-                    launch_reduce(gv, H.partial.get(), 0, 1, H.scal.get() + S_RZNEW, st, FIN_BETA,
-                                  H.scal.get());
+                    launch_dot_partial(n, w.r, w.z, w.partial, st);
+                    launch_reduce(gv, w.partial, 0, 1, w.scal + S_RZNEW, st, FIN_BETA,
+                                  w.scal);
                     H.bytes += 24.0 * n;
-                    launch_pcg_direction(n, H.z.get(), H.p.get(), H.scal.get(), st);
+                    launch_pcg_direction(n, w.z, w.p, w.scal, st);
                 }
                 H.it_part1 = b1 - b0;
                 H.it_part2 = H.bytes - b1;
@@ -881,7 +897,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                 if (!H.it_exec) {
                     const double keep = H.bytes;
                     StreamSwap swap(H, its);
-                    StopScope scope(H.ctl.get());
+                    StopScope scope(w.ctl);
                     std::lock_guard<std::mutex> cap(capture_mutex());
                     GIAMG_HIP(hipStreamBeginCapture(its, hipStreamCaptureModeRelaxed));
                     try {
@@ -903,7 +919,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             int launched = 0;
             int chunk = H.last_iters > 0 ? H.last_iters : 8;
             {
-                StopScope scope(H.ctl.get());
+                StopScope scope(w.ctl);
                 for (;;) {
                     const int todo = std::min(chunk, H.opts.maxit - launched);
                     for (int j = 0; j < todo; ++j) {
@@ -913,7 +929,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
                             iteration();
                     }
                     launched += todo;
-                    GIAMG_HIP(hipMemcpyAsync(H.host_ctl, H.ctl.get(), C_COUNT * sizeof(int),
+                    GIAMG_HIP(hipMemcpyAsync(H.host_ctl, w.ctl, C_COUNT * sizeof(int),
                                              hipMemcpyDeviceToHost, its));
                     GIAMG_HIP(hipStreamSynchronize(its));
                     if (H.host_ctl[C_STOP] != 0 || launched >= H.opts.maxit) break;
@@ -934,7 +950,7 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
             // bytes of the work that ran: the iteration that stopped skipped its second half
             const int halves2 = std::max(0, (stop == 2 ? iters : iters - 1));
             H.bytes = bytes0 + 16.0 * n + part1 * (stop == 2 ? iters + 1 : iters) + part2 * halves2;
-            fetch_scalars(H);
+            fetch_scalars(H, w.scal);
             relres = std::sqrt(H.host_scal[S_RR]) / bnorm;
         } else if (!(relres < tol)) {
             status = GIAMG_ENOTCONV;
@@ -943,9 +959,9 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
     GIAMG_HIP(hipEventRecord(H.ev1, s));
     const double bytes = H.bytes;
     // true residual at exit (outside the timed region)
-    rinit(H.tmp.get());
-    launch_reduce(gs, H.partial.get(), gs, 2, H.scal.get() + S_BB, s);
-    fetch_scalars(H);
+    rinit(w.tmp);
+    launch_reduce(gs, w.partial, gs, 2, w.scal + S_BB, s);
+    fetch_scalars(H, w.scal);
     if (info) {
         float ms = 0.0f;
         GIAMG_HIP(hipEventElapsedTime(&ms, H.ev0, H.ev1));
@@ -957,6 +973,84 @@ int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
         info->bytes = bytes;
     }
     return status;
+}
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex& scratch_mutex() {
+    static std::mutex m;
+    return m;
+}
+unsigned char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+size_t align256(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+}  // namespace
+
+// Fixed per-device scratch of the allocation-free solve (giamg_solve_noalloc):
+// the CG work vectors, block partials, scalars and control block of one
+// solve at a time; every GPU holds its own copy until the process ends.  In
+// host code `scratch` only names the symbol: its device address is looked
+// up once per device, with that device current (noalloc_scratch_init, run by
+// setup), and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+void noalloc_scratch_init() {
+    int dev = 0;
+    GIAMG_HIP(hipGetDevice(&dev));
+    GIAMG_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(scratch_mutex());
+    if (g_scratch_ptr[dev] != nullptr) return;
+    void* ptr = nullptr;
+    GIAMG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (ptr == nullptr) throw Error(GIAMG_EHIP, "no device address for the solve scratch");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+}
+
+int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info) {
+    CgWork w{H.x.get(), H.r.get(), H.z.get(), H.p.get(), H.q.get(), H.rold.get(), H.tmp.get(),
+             H.partial.get(), H.scal.get(), H.ctl.get()};
+    return solve_on(H, w, true, b, x, tol, info);
+}
+
+int solve_noalloc(Handle& H, int device, const double* b, double* x, double tol, giamg_info* info) {
+    GIAMG_REQUIRE(device >= 0 && device < NOALLOC_MAX_DEVICES, "device index beyond 63");
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mutex());
+        base = g_scratch_ptr[device];
+    }
+    if (base == nullptr) throw Error(GIAMG_EHIP, "solve scratch not set up on this device");
+    const size_t vec = align256((size_t)std::max<int64_t>(H.n_nodes, 1) * sizeof(double));
+    const size_t fixed = align256((size_t)H.partial_cap * sizeof(double)) +
+                         align256(S_COUNT * sizeof(double)) + align256(C_COUNT * sizeof(int));
+    const size_t need = 7 * vec + fixed;
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        const size_t fit = (NOALLOC_SCRATCH_BYTES - std::min(fixed, NOALLOC_SCRATCH_BYTES)) /
+                           (7 * sizeof(double));
+        throw Error(GIAMG_EINVAL, "giamg_solve_noalloc: " + std::to_string(H.n_nodes) +
+                                      " nodes need " + std::to_string(need) +
+                                      " bytes of solve scratch, more than its fixed " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES) + " (at most about " +
+                                      std::to_string(fit) + " nodes with this hierarchy)");
+    }
+    unsigned char* c = base;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = c;
+        c += align256(bytes);
+        return p;
+    };
+    CgWork w;
+    w.x = reinterpret_cast<double*>(take(vec));
+    w.r = reinterpret_cast<double*>(take(vec));
+    w.z = reinterpret_cast<double*>(take(vec));
+    w.p = reinterpret_cast<double*>(take(vec));
+    w.q = reinterpret_cast<double*>(take(vec));
+    w.rold = reinterpret_cast<double*>(take(vec));
+    w.tmp = reinterpret_cast<double*>(take(vec));
+    w.partial = reinterpret_cast<double*>(take((size_t)H.partial_cap * sizeof(double)));
+    w.scal = reinterpret_cast<double*>(take(S_COUNT * sizeof(double)));
+    w.ctl = reinterpret_cast<int*>(take(C_COUNT * sizeof(int)));
+    return solve_on(H, w, false, b, x, tol, info);
 }
 
 // ---------------------------------------------------------------------------

@@ -146,6 +146,7 @@ _SIGNATURES = {
     "giamg_setup": (I32, [P, I64, P, I64, I32, F64, ctypes.POINTER(_Opts), P, ctypes.POINTER(P)]),
     "giamg_free": (None, [P]),
     "giamg_solve": (I32, [P, P, P, F64, ctypes.POINTER(_Info)]),
+    "giamg_solve_noalloc": (I32, [P, P, P, F64, ctypes.POINTER(_Info)]),
     "giamg_solve_batch": (I32, [P, P, P, I32, F64, ctypes.POINTER(_Info)]),
     "giamg_hierarchy_info": (I32, [P, P, P, P, I32]),
     "giamg_num_levels": (I32, [P]),
@@ -322,6 +323,18 @@ class Solver:
         rc = self.lib.giamg_solve(self._h, bp, xp, float(tol), ctypes.byref(info))
         _check(rc)
         return x, SolveInfo(info.iters, info.status, info.relres, info.true_relres, info.solve_ms, info.bytes)
+
+    def solve_noalloc(self, b, x, tol=1e-10):
+        """giamg_solve_noalloc: the solve with its work vectors in the
+        library's fixed per-GPU scratch (no allocation; x is required)."""
+        import torch
+        n = (self.n_nodes,)
+        bp, xp = _devs((b, torch.float64, n, "b"), (x, torch.float64, n, "x"))
+        info = _Info()
+        rc = self.lib.giamg_solve_noalloc(self._h, bp, xp, float(tol), ctypes.byref(info))
+        _check(rc)
+        return x, SolveInfo(info.iters, info.status, info.relres, info.true_relres, info.solve_ms,
+                            info.bytes)
 
     def solve_batch(self, B, X=None, tol=1e-10):
         """B, X: float64 device tensors [n_nodes, k], right-hand side j in
