@@ -59,6 +59,67 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// Row sums of groups of L lanes (L = 16, 4 or 1, each group inside one
+// 16-lane DPP row): the same butterfly as group_sum<L> -- step k adds the
+// value of the lane that differs in bit k, own value first -- done with DPP
+// row rotations instead of LDS permutes.  After the step for bit 8 (4, 2)
+// every value repeats with period 8 (4, 2) inside the group, so rotating by
+// 4 (2, 1) reads exactly the xor partner's value: the sums are the
+// butterfly's bit for bit.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, false));
+}
+template <int L, typename T>
+__device__ __forceinline__ T row_group_sum(T v) {
+    static_assert(L == 16 || L == 4 || L == 1, "row groups of 16, 4 or 1 lanes");
+    if constexpr (L == 16) {
+        v += dpp_move<0x128>(v);   // row_ror:8  (xor 8)
+        v += dpp_move<0x124>(v);   // row_ror:4  (xor 4 on period-8 values)
+        v += dpp_move<0x122>(v);   // row_ror:2
+        v += dpp_move<0x121>(v);   // row_ror:1
+    } else if constexpr (L == 4) {
+        v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]  (xor 2)
+        v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]  (xor 1)
+    }
+    return v;
+}
+
+// Lane gl's share of a row held in LDS, prod[s .. e): the entries gl,
+// gl + L, ... added in that order into one accumulator, the LDS reads of up
+// to eight of them issued before the adds so their latencies overlap (the
+// additions and their order are those of the plain loop).
+template <int L, typename T>
+__device__ __forceinline__ T lane_row_sum(const T* prod, int s, int e, int gl) {
+    T acc = 0;
+    int j = s + gl;
+    for (; j + 7 * L < e; j += 8 * L) {
+        T p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = prod[j + u * L];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += p[u];
+    }
+    if (j + 3 * L < e) {
+        T p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = prod[j + u * L];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += p[u];
+        j += 4 * L;
+    }
+    for (; j < e; j += L) acc += prod[j];
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
@@ -305,7 +366,8 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 //     overlap the value stream; the nonzeros then carry 16-bit LDS slots in
 //     place of column ids.  Without staging each nonzero gathers straight
 //     from memory once its column id has arrived.
-//  2. groups of L lanes sum the rows from LDS in a fixed order;
+//  2. groups of L lanes sum the rows from LDS in a fixed order (reads issued
+//     ahead of the in-order adds, DPP butterflies);
 //  3. thread t finishes row r0 + t (coalesced row-local stores).
 // Both forms multiply the same operands and sum in the same order, so they
 // give bitwise identical results.  STAGE picks the form at compile time:
@@ -390,10 +452,8 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     // 2. row sums, L lanes per row
     const int g = tid / L, gl = tid % L;
     for (int rr = g; rr < nrows; rr += NT / L) {
-        const int s = rowoff[rr], e = rowoff[rr + 1];
-        T acc = 0;
-        for (int j = s + gl; j < e; j += L) acc += prod[j];
-        acc = group_sum<L>(acc);
+        T acc = lane_row_sum<L>(prod, rowoff[rr], rowoff[rr + 1], gl);
+        acc = row_group_sum<L>(acc);
         if (gl == 0) rowsum[rr] = acc;
     }
     __syncthreads();
@@ -478,9 +538,8 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
         const int q = rr / G, i = rr - q * G;
         const uint32_t gq = a.ggrp[B.q0 + q];
         const int s = i * E + (int)(gq >> 16), e = s + (int)(gq & 0xffffu);
-        T acc = 0;
-        for (int j = s + gl; j < e; j += L) acc += prod[j];
-        acc = group_sum<L>(acc);
+        T acc = lane_row_sum<L>(prod, s, e, gl);
+        acc = row_group_sum<L>(acc);
         if (gl == 0) rowsum[rr] = acc;
     }
 }
@@ -570,7 +629,7 @@ __global__ void __launch_bounds__(LEAN_THREADS) spmv_lean_kernel(SpmvArgs<T> a) 
             acc += p;
         }
     }
-    acc = group_sum<L>(acc);
+    acc = row_group_sum<L>(acc);
     double dot = 0.0, dot2 = 0.0;
     if (live && gl == 0) epilogue_store<T, MODE>(a, row, acc, in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
