@@ -61,6 +61,9 @@ extern "C" {
 #define GIAMG_BATCH_LANES 1   /* 8 to 64 lanes per row, each lane loads its own (column, value) */
 #define GIAMG_BATCH_WAVE  2   /* one row per wavefront, (column, value) pairs shared by readlane */
 #define GIAMG_BATCH_GROUP 3   /* one group of rows with identical column lists per wavefront */
+#define GIAMG_PRECOND_VCYCLE     0  /* one GIAMG V-cycle per CG iteration (the method) */
+#define GIAMG_PRECOND_JACOBI     1  /* the inverse diagonal: the diagonally preconditioned CG
+                                       the paper compares against (Section 3.2) */
 #define GIAMG_BASIS_NODAL        0  /* tensor Lagrange on Gauss-Lobatto-Legendre points */
 #define GIAMG_BASIS_MODAL        1  /* hierarchical modal basis of the paper's appendix:
                                        1-D modes (1-a)/2, (1+a)/2, then bubbles
@@ -130,6 +133,12 @@ typedef struct giamg_opts {
                               both; MIS-2 roots and aggregates are taken on that graph, the
                               SPAI-0 smoothing of the tentative prolongation uses all of A.
                               In [0, 1]; default 0: every stored off-diagonal entry */
+    int32_t  preconditioner; /* GIAMG_PRECOND_*; default the V-cycle.  JACOBI builds the fine
+                              level only (no coarse levels) and needs precision FP64;
+                              giamg_solve and giamg_solve_noalloc only (batched solves,
+                              sessions and the V-cycle steps of giamg_apply return
+                              GIAMG_ENOTSUP) */
+    int32_t  pad3;
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -255,6 +264,60 @@ int giamg_solve_noalloc(giamg_handle h, const double* b, double* x, double tol,
  */
 int giamg_solve_batch(giamg_handle h, const double* B, double* X, int32_t k,
                       double tol, giamg_info* infos);
+
+/* ---- profiling ------------------------------------------------------------
+ * Phase breakdown of the solve in the categories of the paper's detailed
+ * analysis (Section 3.2: first-level smoothing, smoothing, residual,
+ * restriction and prolongation, V-cycle, CG matrix-vector product, CG dot
+ * products, whole PCG iterations), measured with HIP events on the handle's
+ * stream around each phase of every solve while profiling is on.  Phases
+ * nest (a V-cycle contains its smoothing, residuals and transfers), so the
+ * totals overlap.  GIAMG_PHASE_FINE_STEP times every launch of the fine-level
+ * Chebyshev step (the dominant kernel) by events its dispatch records
+ * itself.  Work queued past convergence (kernels that return at once on the
+ * device stop flag) is not counted. */
+#define GIAMG_PHASE_FIRST_SMOOTH 0  /* pre- and post-smoothing on the finest level */
+#define GIAMG_PHASE_SMOOTH       1  /* smoothing on every level, the finest included */
+#define GIAMG_PHASE_RESIDUAL     2  /* V-cycle residuals f - A x on every level */
+#define GIAMG_PHASE_TRANSFER     3  /* restriction and prolongation ("PR transfer") */
+#define GIAMG_PHASE_COARSE       4  /* direct solve on the coarsest level */
+#define GIAMG_PHASE_VCYCLE       5  /* whole V-cycles (the preconditioner applications) */
+#define GIAMG_PHASE_CG_MATVEC    6  /* CG product q = A p (with its dot-product partials) */
+#define GIAMG_PHASE_CG_DOT       7  /* CG reductions and dot products */
+#define GIAMG_PHASE_CG_UPDATE    8  /* CG vector updates: iterate, residual, direction */
+#define GIAMG_PHASE_PCG          9  /* whole PCG iterations */
+#define GIAMG_PHASE_FINE_STEP   10  /* single launches of the fine-level Chebyshev step */
+#define GIAMG_PHASE_COUNT       11
+
+typedef struct giamg_profile {
+    double  ms[GIAMG_PHASE_COUNT];     /* summed GPU milliseconds per phase */
+    int64_t count[GIAMG_PHASE_COUNT];  /* intervals summed per phase */
+    int64_t solves;                    /* solves profiled */
+    int64_t iterations;                /* their CG iterations */
+} giamg_profile;
+
+/* on = 1: profile every phase of the following giamg_solve calls of the
+ * handle; on = 2: time only the launches of the fine-level Chebyshev step
+ * (GIAMG_PHASE_FINE_STEP: no markers between the other kernels, so the
+ * solve runs as unprofiled); on = 0: stop.  Profiled solves launch every
+ * kernel from the host (as with graph_launch = 0) and create HIP events as
+ * needed; giamg_solve_noalloc is never profiled.  Returns GIAMG_OK or
+ * GIAMG_EINVAL. */
+int giamg_profile_enable(giamg_handle h, int32_t on);
+/* Copy the accumulated breakdown into *out (host); reset = 1 clears it. */
+int giamg_profile_read(giamg_handle h, giamg_profile* out, int32_t reset);
+
+/*
+ * giamg_read_bandwidth -- attainable HBM read bandwidth of the current
+ * device: a streaming kernel reads a fresh buffer of `bytes` bytes (16-byte
+ * non-temporal loads, one partial sum written per block) `reps` times; *gbs
+ * receives the median over the launches of bytes / duration (HIP events
+ * recorded by the dispatches).  The buffer comes from the registered
+ * allocator and is released before returning.  bytes >= 1 MiB, reps in
+ * [1, 1000]; GIAMG_EINVAL otherwise, GIAMG_ENOMEM if the buffer cannot be
+ * allocated.  Synchronises the device's null stream.
+ */
+int giamg_read_bandwidth(int64_t bytes, int32_t reps, double* gbs);
 
 /* ---- hierarchy introspection (host outputs; synchronise the stream) ---- */
 #define GIAMG_LEVEL_P        0   /* p-coarsened level (or the fine level) */

@@ -75,3 +75,11 @@ def giamg_pcg(H, b, tol=1e-10, maxit=500, x0=None, flexible=False):
     from .cycle import vcycle
     return pcg(H.levels[0].A, b, lambda r: vcycle(H, r), tol, maxit, x0,
                flexible)
+
+
+def jacobi_pcg(A, b, tol=1e-10, maxit=10000):
+    """CG preconditioned by the inverse diagonal of A: the diagonally
+    preconditioned CG (DCG) that the paper measures GIAMG against
+    (Section 3.2, overall comparison), with the same stopping rule."""
+    d = A.diagonal().astype(np.float64)
+    return pcg(A, b, lambda r: r / d, tol, maxit)

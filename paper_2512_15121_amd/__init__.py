@@ -5,4 +5,5 @@ Kirby, Moxey and Sundar (arXiv 2512.15121).
 The solver lives in ``libgiamg.so`` (C ABI declared in include/giamg.h, HIP
 kernels for gfx950); ``giamg`` is its ctypes binding.
 """
-from .giamg import Solver, Options, SolveInfo, GiamgError, Session, Server, library  # noqa: F401
+from .giamg import (Solver, Options, SolveInfo, GiamgError, Session, Server, library,  # noqa: F401
+                    read_bandwidth)

@@ -19,6 +19,9 @@ namespace giamg {
 void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g);
 int solve(Handle& H, const double* b, double* x, double tol, giamg_info* info);
 int solve_noalloc(Handle& H, int device, const double* b, double* x, double tol, giamg_info* info);
+void profile_enable(Handle& H, int on);
+void profile_read(Handle& H, giamg_profile* out, bool reset);
+void read_bandwidth(int64_t bytes, int reps, double* gbs);
 int solve_batch(Handle& H, const double* B, double* X, int32_t k, double tol, giamg_info* infos);
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out);
 void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes);
@@ -115,6 +118,10 @@ void check_setup_args(const double* coords, int64_t n_nodes, const int32_t* l2g,
     GIAMG_REQUIRE(o.lean_max_nnz >= 0, "lean_max_nnz must be >= 0");
     GIAMG_REQUIRE(o.keep_boundary == 0 || o.keep_boundary == 1, "keep_boundary must be 0 or 1");
     GIAMG_REQUIRE(o.theta >= 0.0 && o.theta <= 1.0, "theta must be in [0, 1]");
+    GIAMG_REQUIRE(o.preconditioner == GIAMG_PRECOND_VCYCLE || o.preconditioner == GIAMG_PRECOND_JACOBI,
+                  "unknown preconditioner");
+    GIAMG_REQUIRE(o.preconditioner == GIAMG_PRECOND_VCYCLE || o.precision == GIAMG_PREC_FP64,
+                  "the Jacobi preconditioner runs in FP64 only (precision must be FP64)");
     {
         int prev = p;
         for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
@@ -203,6 +210,8 @@ void giamg_default_opts(giamg_opts* o) {
     o->keep_boundary = 0;
     o->pad2 = 0;
     o->theta = 0.0;
+    o->preconditioner = GIAMG_PRECOND_VCYCLE;
+    o->pad3 = 0;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -272,6 +281,8 @@ int giamg_solve_batch(giamg_handle h, const double* B, double* X, int32_t k, dou
         GIAMG_REQUIRE(B != nullptr && X != nullptr, "B and X must be non-null");
         GIAMG_REQUIRE(k >= 1, "k must be >= 1");
         GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
+        if (h->h.opts.preconditioner != GIAMG_PRECOND_VCYCLE)
+            throw giamg::Error(GIAMG_ENOTSUP, "batched solves need the V-cycle preconditioner");
         return giamg::solve_batch(h->h, B, X, k, tol, infos);
     });
 }
@@ -548,6 +559,8 @@ int giamg_session_create(giamg_handle h, int32_t slots, double tol, giamg_sessio
         bind_device(h);
         GIAMG_REQUIRE(out != nullptr, "out is null");
         GIAMG_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
+        if (h->h.opts.preconditioner != GIAMG_PRECOND_VCYCLE)
+            throw giamg::Error(GIAMG_ENOTSUP, "sessions need the V-cycle preconditioner");
         giamg::Session* S = giamg::session_create(h->h, slots, tol);
         try {
             *out = new giamg_session_s{S, h};
@@ -601,6 +614,33 @@ void giamg_session_free(giamg_session s) {
     (void)hipSetDevice(s->owner->device);
     giamg::session_destroy(s->s);
     delete s;
+}
+
+int giamg_profile_enable(giamg_handle h, int32_t on) {
+    return guarded([&]() -> int {
+        bind_device(h);
+        GIAMG_REQUIRE(on >= 0 && on <= 2, "on must be 0, 1 or 2");
+        giamg::profile_enable(h->h, on);
+        return GIAMG_OK;
+    });
+}
+
+int giamg_profile_read(giamg_handle h, giamg_profile* out, int32_t reset) {
+    return guarded([&]() -> int {
+        bind_device(h);
+        GIAMG_REQUIRE(out != nullptr, "out is null");
+        GIAMG_REQUIRE(reset == 0 || reset == 1, "reset must be 0 or 1");
+        giamg::profile_read(h->h, out, reset != 0);
+        return GIAMG_OK;
+    });
+}
+
+int giamg_read_bandwidth(int64_t bytes, int32_t reps, double* gbs) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(gbs != nullptr, "gbs is null");
+        giamg::read_bandwidth(bytes, reps, gbs);
+        return GIAMG_OK;
+    });
 }
 
 const char* giamg_last_error(void) { return g_last_error.c_str(); }

@@ -232,6 +232,20 @@ struct Handle {
     std::unique_ptr<BatchState, BatchDeleter> batch;
     double bytes = 0.0;               // algorithmic bytes of launched kernels
     double setup_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    // phase profiling (giamg_profile_enable): event intervals per category,
+    // tagged with the CG iteration and half they belong to, so work queued
+    // past convergence can be dropped when the solve's count is known
+    struct ProfRec {
+        int cat, iter, half;           // half 0: start-up or whole iteration, 1: product and
+        hipEvent_t a, b;               // update, 2: V-cycle, dots and direction
+    };
+    struct Profile {
+        int on = 0;                    // 1: every phase, 2: the fine Chebyshev step only
+        int iter = 0, half = 0;        // where the host is queueing
+        std::vector<hipEvent_t> pool;  // events free for reuse
+        std::vector<ProfRec> pending;
+        giamg_profile acc{};
+    } prof;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     ~Handle();
 };

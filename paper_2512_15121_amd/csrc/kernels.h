@@ -106,6 +106,9 @@ struct SpmvArgs {
 
 template <typename T>
 void launch_spmv(int mode, const SpmvArgs<T>& a, hipStream_t s);
+// Median read bandwidth (GB/s) of a streaming kernel over `reps` reads of a
+// fresh buffer of `bytes` bytes on the current device's null stream.
+void read_bandwidth(int64_t bytes, int reps, double* gbs);
 // Greedy row blocking of a CSR operator: consecutive rows while their
 // nonzeros fit cap; the reduction width follows the mean row length.
 void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, int64_t max_rows, std::vector<int64_t>& blocks,
@@ -147,6 +150,8 @@ void launch_convert(int64_t n, const Tin* a, Tout* b, hipStream_t s);
 template <typename T>
 void launch_coarse_apply(int64_t n, const double* inv, const T* f, T* x, hipStream_t s);
 void launch_fill(int64_t n, double v, double* x, hipStream_t s);
+// y = d .* x (elementwise; the diagonal preconditioner)
+void launch_mul(int64_t n, const double* d, const double* x, double* y, hipStream_t s);
 
 // reductions: block partials then a single-block finalize
 int64_t vec_blocks(int64_t n);

@@ -917,6 +917,76 @@ void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
     }
     GIAMG_HIP(hipGetLastError());
 }
+
+// ---------------------------------------------------------------------------
+// Attainable read bandwidth: a streaming read shaped like the products'
+// value stream -- each block of 512 threads reads one contiguous 64 KB chunk
+// with all eight 16-byte non-temporal loads per thread issued at once, blocks
+// remapped so every XCD streams a contiguous range -- and one partial sum
+// per block written so the loads are live.
+// ---------------------------------------------------------------------------
+typedef double double2_v __attribute__((ext_vector_type(2)));
+constexpr int RS_THREADS = 512, RS_LOADS = 8;
+
+__global__ void __launch_bounds__(RS_THREADS) read_stream_kernel(const double2_v* __restrict__ p, int64_t n2,
+                                                                 double* __restrict__ out) {
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = lb * (int64_t)(RS_THREADS * RS_LOADS);
+    double acc = 0.0;
+    double2_v v[RS_LOADS];
+#pragma unroll
+    for (int k = 0; k < RS_LOADS; ++k) {
+        const int64_t i = min(base + k * RS_THREADS + threadIdx.x, n2 - 1);
+        v[k] = ldnt(p + i);
+    }
+#pragma unroll
+    for (int k = 0; k < RS_LOADS; ++k) acc += v[k].x + v[k].y;
+    __shared__ double red[RS_THREADS / WAVE];
+    acc = wave_sum(acc);
+    if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RS_THREADS / WAVE; ++w) t += red[w];
+        out[lb] = t;
+    }
+}
+
+void read_bandwidth(int64_t bytes, int reps, double* gbs) {
+    GIAMG_REQUIRE(bytes >= (int64_t(1) << 20), "bytes must be at least 1 MiB");
+    GIAMG_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+    const int64_t n2 = bytes / 16;
+    const unsigned grid = (unsigned)((n2 + RS_THREADS * RS_LOADS - 1) / (RS_THREADS * RS_LOADS));
+    DevBuf<double2_v> buf(n2);
+    DevBuf<double> out(grid);
+    hipStream_t s = nullptr;
+    GIAMG_HIP(hipMemsetAsync(buf.get(), 0, n2 * 16, s));
+    std::vector<hipEvent_t> ev(2 * (size_t)reps + 2, nullptr);
+    std::vector<double> rate;
+    try {
+        for (auto& e : ev) GIAMG_HIP(hipEventCreate(&e));
+        // one untimed launch, then the timed ones
+        for (int i = 0; i <= reps; ++i) {
+            hipExtLaunchKernelGGL(read_stream_kernel, dim3(grid), dim3(RS_THREADS), 0, s, ev[2 * i],
+                                  ev[2 * i + 1], 0, buf.get(), n2, out.get());
+            GIAMG_HIP(hipGetLastError());
+        }
+        GIAMG_HIP(hipEventSynchronize(ev[2 * reps + 1]));
+        for (int i = 1; i <= reps; ++i) {
+            float t = 0.0f;
+            GIAMG_HIP(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            rate.push_back((double)n2 * 16.0 / (t * 1e-3) / 1e9);
+        }
+    } catch (...) {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    std::sort(rate.begin(), rate.end());
+    *gbs = rate[rate.size() / 2];
+}
+
 template void launch_spmv<double>(int, const SpmvArgs<double>&, hipStream_t);
 template void launch_spmv<float>(int, const SpmvArgs<float>&, hipStream_t);
 
@@ -1029,6 +1099,19 @@ __global__ void fill_kernel(int64_t n, double v, double* __restrict__ x) {
 void launch_fill(int64_t n, double v, double* x, hipStream_t s) {
     if (n <= 0) return;
     fill_kernel<<<vgrid(n), VEC_THREADS, 0, s>>>(n, v, x);
+    GIAMG_HIP(hipGetLastError());
+}
+
+__global__ void mul_kernel(int64_t n, const double* __restrict__ d, const double* __restrict__ x,
+                           double* __restrict__ y, const int* stop) {
+    if (stopped(stop)) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = d[i] * x[i];
+}
+void launch_mul(int64_t n, const double* d, const double* x, double* y, hipStream_t s) {
+    if (n <= 0) return;
+    mul_kernel<<<vgrid(n), VEC_THREADS, 0, s>>>(n, d, x, y, g_stop);
     GIAMG_HIP(hipGetLastError());
 }
 

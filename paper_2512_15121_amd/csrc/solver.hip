@@ -29,6 +29,11 @@ double ms_since(clock_t_::time_point t0) {
 }  // namespace
 
 Handle::~Handle() {
+    for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+    for (const ProfRec& r : prof.pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
     if (host_scal) (void)hipHostFree(host_scal);
     if (host_ctl) (void)hipHostFree(host_ctl);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -324,7 +329,8 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     for (int64_t i = 0; i < n; ++i) free_mask[i] = o.keep_boundary ? 1 : !H.constrained[i];
     int order = H.porder;
     const bool explicit_schedule = o.schedule[0] != 0;
-    for (int step = 0; order > 1 && (int)H.levels.size() < o.max_levels; ++step) {
+    const bool jacobi = o.preconditioner == GIAMG_PRECOND_JACOBI;   // fine level only
+    for (int step = 0; !jacobi && order > 1 && (int)H.levels.size() < o.max_levels; ++step) {
         int q;
         if (explicit_schedule) {   // the listed orders only
             if (step >= 8 || o.schedule[step] == 0) break;
@@ -359,7 +365,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         order = q;
     }
     // h-levels (smoothed aggregation) below order 1
-    while (H.levels.back().order == 1 && H.levels.back().n > o.coarse_max &&
+    while (!jacobi && H.levels.back().order == 1 && H.levels.back().n > o.coarse_max &&
            (int)H.levels.size() < o.max_levels) {
         Level& F = H.levels.back();
         t0 = clock_t_::now();
@@ -387,7 +393,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     }
     // coarsest: dense inverse through Cholesky
     t0 = clock_t_::now();
-    {
+    if (!jacobi) {
         Level& Lc = H.levels.back();
         H.nc = Lc.n;
         GIAMG_REQUIRE(H.nc <= 16384, "coarsest level too large for the dense solve");
@@ -430,7 +436,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         Level& L = H.levels[l];
         alloc_level_vectors(L, mixed);
         if (mixed) make_fp32_operator(L.A, H.stream);
-        if (l + 1 == H.levels.size()) break;
+        if (l + 1 == H.levels.size() && !jacobi) break;
         if (mixed) make_fp32_operator(L.AP, H.stream);
         L.dinv.alloc(L.n);
         DevBuf<int> bad(1);
@@ -446,6 +452,7 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
             L.dinv32.alloc(L.n);
             launch_convert<double, float>(L.n, L.dinv.get(), L.dinv32.get(), H.stream);
         }
+        if (jacobi) break;   // the diagonal is the whole preconditioner
         L.lam_hat = power_estimate(H, L);
     }
     H.setup_ms[5] = ms_since(t0) + grouping_ms;
@@ -553,6 +560,75 @@ double spmv_bytes(int mode, const SpmvArgs<T>& a) {
            rows * vb * a.n;
 }
 
+// ---- phase profiling -------------------------------------------------------
+hipEvent_t prof_event(Handle& H) {
+    if (!H.prof.pool.empty()) {
+        hipEvent_t e = H.prof.pool.back();
+        H.prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    GIAMG_HIP(hipEventCreate(&e));
+    return e;
+}
+
+// Events around one phase on the handle's stream while profiling is on.
+class Phase {
+public:
+    Phase(Handle& h, int cat) : H(h), cat_(cat) {
+        if (H.prof.on != 1 || cat < 0) return;
+        a_ = prof_event(H);
+        GIAMG_HIP(hipEventRecord(a_, H.stream));
+    }
+    ~Phase() {
+        if (a_ == nullptr) return;
+        hipEvent_t b = nullptr;
+        if (!H.prof.pool.empty()) {
+            b = H.prof.pool.back();
+            H.prof.pool.pop_back();
+        } else if (hipEventCreate(&b) != hipSuccess) {
+            b = nullptr;
+        }
+        try {
+            if (b != nullptr && hipEventRecord(b, H.stream) == hipSuccess) {
+                H.prof.pending.push_back({cat_, H.prof.iter, H.prof.half, a_, b});
+                return;
+            }
+        } catch (...) {
+        }
+        (void)hipEventDestroy(a_);
+        if (b != nullptr) (void)hipEventDestroy(b);
+    }
+    Phase(const Phase&) = delete;
+    Phase& operator=(const Phase&) = delete;
+
+private:
+    Handle& H;
+    int cat_;
+    hipEvent_t a_ = nullptr;
+};
+
+// Sum the intervals of a finished solve: iters CG iterations, whose first
+// halves (product, update, stopping test) ran for iterations 1..first and
+// second halves (V-cycle, dots, direction) for 1..second.
+void prof_harvest(Handle& H, int iters, int first, int second) {
+    for (const Handle::ProfRec& r : H.prof.pending) {
+        const bool ran = r.iter == 0 || (r.half == 2 ? r.iter <= second : r.iter <= first);
+        if (ran) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                H.prof.acc.ms[r.cat] += t;
+                H.prof.acc.count[r.cat] += 1;
+            }
+        }
+        H.prof.pool.push_back(r.a);
+        H.prof.pool.push_back(r.b);
+    }
+    H.prof.pending.clear();
+    H.prof.acc.solves += 1;
+    H.prof.acc.iterations += iters;
+}
+
 template <typename T>
 void run_spmv(Handle& H, int mode, const SpmvArgs<T>& a) {
     H.bytes += spmv_bytes(mode, a);
@@ -628,6 +704,12 @@ void smooth_chebyshev(Handle& H, Level& L, const T* f, T* x, bool zero_start,
         a.v = d[(j - 1) & 1]; a.y = d[j & 1]; a.r = r; a.x = x;
         a.c1 = (T)c.c1[j - 1]; a.c2 = (T)c.c2[j - 1];
         a.flags = (j == k - 1 ? CHEB_LAST : 0) | ((zero_start && j == 1) ? CHEB_ASSIGN : 0);
+        if (H.prof.on != 0 && &L == &H.levels[0]) {   // the dominant kernel, timed by its dispatch
+            a.ev_start = prof_event(H);
+            a.ev_stop = prof_event(H);
+            H.prof.pending.push_back({GIAMG_PHASE_FINE_STEP, H.prof.iter, H.prof.half, a.ev_start,
+                                      a.ev_stop});
+        }
         run_spmv(H, SPMV_CHEB_STEP, a);
     }
 }
@@ -709,20 +791,36 @@ template <typename T>
 void vcycle(Handle& H, size_t l, const T* f, T* x, bool init_done = false) {
     Level& L = H.levels[l];
     if (l + 1 == H.levels.size()) {
+        Phase ph(H, GIAMG_PHASE_COARSE);
         H.bytes += 8.0 * H.nc * H.nc + 2.0 * sizeof(T) * H.nc;
         launch_coarse_apply<T>(H.nc, H.coarse_inv.get(), f, x, H.stream);
         return;
     }
     Level& C = H.levels[l + 1];
-    smooth<T>(H, L, f, x, true, nullptr, nullptr, init_done);
-    residual<T>(H, L, f, x, LV<T>::t(L));
+    {
+        Phase ph(H, GIAMG_PHASE_SMOOTH);
+        Phase ph0(H, l == 0 ? GIAMG_PHASE_FIRST_SMOOTH : -1);
+        smooth<T>(H, L, f, x, true, nullptr, nullptr, init_done);
+    }
+    {
+        Phase ph(H, GIAMG_PHASE_RESIDUAL);
+        residual<T>(H, L, f, x, LV<T>::t(L));
+    }
     const bool fuse = fused_init_ok(H) && l + 2 < H.levels.size();
-    if (fuse)
-        restrict_cheb0<T>(H, L, C, LV<T>::t(L));
-    else
-        restrict_to<T>(H, L, LV<T>::t(L), LV<T>::f(C));
+    {
+        Phase ph(H, GIAMG_PHASE_TRANSFER);
+        if (fuse)
+            restrict_cheb0<T>(H, L, C, LV<T>::t(L));
+        else
+            restrict_to<T>(H, L, LV<T>::t(L), LV<T>::f(C));
+    }
     vcycle<T>(H, l + 1, LV<T>::f(C), LV<T>::x(C), fuse);
-    prolong_add<T>(H, L, LV<T>::x(C), x);
+    {
+        Phase ph(H, GIAMG_PHASE_TRANSFER);
+        prolong_add<T>(H, L, LV<T>::x(C), x);
+    }
+    Phase ph(H, GIAMG_PHASE_SMOOTH);
+    Phase ph0(H, l == 0 ? GIAMG_PHASE_FIRST_SMOOTH : -1);
     smooth<T>(H, L, f, x, false, LV<T>::t(L), LV<T>::x(C));
 }
 
@@ -732,6 +830,13 @@ void vcycle(Handle& H, size_t l, const T* f, T* x, bool init_done = false) {
 // level 0's x32 (zvec32), read by the dots and the direction update widened
 // exactly; z is not written.
 void precondition(Handle& H, const double* r, double* z, bool init_done = false, bool r32_ready = false) {
+    if (H.opts.preconditioner == GIAMG_PRECOND_JACOBI) {   // z = D^-1 r
+        Level& L = H.levels[0];
+        H.bytes += 24.0 * L.n;
+        launch_mul(L.n, L.dinv.get(), r, z, H.stream);
+        return;
+    }
+    Phase ph(H, GIAMG_PHASE_VCYCLE);
     if (H.opts.precision == GIAMG_PREC_MIXED) {
         Level& L = H.levels[0];
         if (!r32_ready) {
@@ -789,6 +894,8 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
         run_spmv(H, SPMV_RINIT, a);
     };
     H.bytes = 0.0;
+    H.prof.iter = 0;
+    H.prof.half = 0;
     GIAMG_HIP(hipEventRecord(H.ev0, s));
     launch_fill(S_COUNT, 0.0, w.scal, s);
     rinit(w.r);
@@ -797,6 +904,7 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
     const double bnorm = std::sqrt(H.host_scal[S_BB]);
     int status = GIAMG_OK;
     int iters = 0;
+    int prof_first = 0, prof_second = 0;   // CG halves that ran (profiling)
     double relres = 0.0;
     if (bnorm == 0.0) {
         H.bytes += 8.0 * n;
@@ -836,7 +944,7 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
             // solve of the handle and replayed on the handle's graph stream.
             // The iterate lives in the handle's x (copied in and out), so the
             // graph's pointers never change.
-            const bool graph = allow_graph && H.opts.graph_launch != 0;
+            const bool graph = allow_graph && H.opts.graph_launch != 0 && H.prof.on == 0;
             // Chebyshev smoother of degree >= 2: the fine level's smoother
             // init rides on the CG update (bitwise the same vectors; FP32 in
             // mixed precision)
@@ -847,47 +955,71 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
             auto iteration = [&]() {
                 hipStream_t st = H.stream;
                 const double b0 = H.bytes;
-                SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
-                a.v = w.p; a.y = w.q; a.partial = w.partial;
-                H.bytes += (flexible ? 56.0 : 48.0) * n;
-                run_spmv(H, SPMV_DOT, a);
-                launch_reduce(gs, w.partial, 0, 1, w.scal + S_PQ, st, FIN_ALPHA, w.scal);
-                if (flexible) {   // also r in FP32 (and level 0's FP32 Chebyshev r_0, d_0)
-                    Level& F = H.levels[0];
-                    H.bytes += (fused ? 16.0 : 4.0) * n;
-                    launch_pcg_update_mixed(n, xi, w.r, w.rold, w.p, w.q,
-                                            w.scal, w.partial, F.f32.get(),
-                                            fused ? F.dinv32.get() : nullptr, F.r32.get(), F.d032.get(),
-                                            (float)cheb_coef(H, F).inv_theta, st);
-                } else if (fused) {   // the update also writes level 0's Chebyshev r_0, d_0
-                    Level& F = H.levels[0];
-                    H.bytes += 24.0 * n;
-                    launch_pcg_update_cheb0(n, xi, w.r, w.p, w.q, w.scal,
-                                            w.partial, F.dinv.get(), F.r.get(), F.d0.get(),
-                                            cheb_coef(H, F).inv_theta, st);
-                } else {
-                    launch_pcg_update(n, xi, w.r, flexible ? w.rold : nullptr, w.p,
-                                      w.q, w.scal, w.partial, st);
+                Phase pcg(H, GIAMG_PHASE_PCG);
+                H.prof.half = 1;
+                {
+                    Phase ph(H, GIAMG_PHASE_CG_MATVEC);
+                    SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
+                    a.v = w.p; a.y = w.q; a.partial = w.partial;
+                    H.bytes += (flexible ? 56.0 : 48.0) * n;
+                    run_spmv(H, SPMV_DOT, a);
                 }
-                launch_reduce(gv, w.partial, 0, 1, w.scal + S_RR, st, FIN_CONV,
-                              w.scal, w.ctl);
+                {
+                    Phase ph(H, GIAMG_PHASE_CG_DOT);
+                    launch_reduce(gs, w.partial, 0, 1, w.scal + S_PQ, st, FIN_ALPHA, w.scal);
+                }
+                {
+                    Phase ph(H, GIAMG_PHASE_CG_UPDATE);
+                    if (flexible) {   // also r in FP32 (and level 0's FP32 Chebyshev r_0, d_0)
+                        Level& F = H.levels[0];
+                        H.bytes += (fused ? 16.0 : 4.0) * n;
+                        launch_pcg_update_mixed(n, xi, w.r, w.rold, w.p, w.q,
+                                                w.scal, w.partial, F.f32.get(),
+                                                fused ? F.dinv32.get() : nullptr, F.r32.get(),
+                                                F.d032.get(), (float)cheb_coef(H, F).inv_theta, st);
+                    } else if (fused) {   // the update also writes level 0's Chebyshev r_0, d_0
+                        Level& F = H.levels[0];
+                        H.bytes += 24.0 * n;
+                        launch_pcg_update_cheb0(n, xi, w.r, w.p, w.q, w.scal,
+                                                w.partial, F.dinv.get(), F.r.get(), F.d0.get(),
+                                                cheb_coef(H, F).inv_theta, st);
+                    } else {
+                        launch_pcg_update(n, xi, w.r, flexible ? w.rold : nullptr, w.p,
+                                          w.q, w.scal, w.partial, st);
+                    }
+                }
+                {
+                    Phase ph(H, GIAMG_PHASE_CG_DOT);
+                    launch_reduce(gv, w.partial, 0, 1, w.scal + S_RR, st, FIN_CONV,
+                                  w.scal, w.ctl);
+                }
                 const double b1 = H.bytes;
+                H.prof.half = 2;
                 precondition(H, w.r, w.z, fused, flexible);
                 if (flexible) {
-                    H.bytes += 20.0 * n;
-                    launch_dot2_partial(n, w.r, zvec32(H), w.rold, w.partial, st);
-                    launch_reduce(gv, w.partial, gv, 2, w.scal + S_RZNEW, st, FIN_BETA_FLEX,
-                                  w.scal);
+                    {
+                        Phase ph(H, GIAMG_PHASE_CG_DOT);
+                        H.bytes += 20.0 * n;
+                        launch_dot2_partial(n, w.r, zvec32(H), w.rold, w.partial, st);
+                        launch_reduce(gv, w.partial, gv, 2, w.scal + S_RZNEW, st, FIN_BETA_FLEX,
+                                      w.scal);
+                    }
+                    Phase ph(H, GIAMG_PHASE_CG_UPDATE);
                     H.bytes += 20.0 * n;
                     launch_pcg_direction(n, zvec32(H), w.p, w.scal, st);
                 } else {
-                    H.bytes += 16.0 * n;
-                    launch_dot_partial(n, w.r, w.z, w.partial, st);
-                    launch_reduce(gv, w.partial, 0, 1, w.scal + S_RZNEW, st, FIN_BETA,
-                                  w.scal);
+                    {
+                        Phase ph(H, GIAMG_PHASE_CG_DOT);
+                        H.bytes += 16.0 * n;
+                        launch_dot_partial(n, w.r, w.z, w.partial, st);
+                        launch_reduce(gv, w.partial, 0, 1, w.scal + S_RZNEW, st, FIN_BETA,
+                                      w.scal);
+                    }
+                    Phase ph(H, GIAMG_PHASE_CG_UPDATE);
                     H.bytes += 24.0 * n;
                     launch_pcg_direction(n, w.z, w.p, w.scal, st);
                 }
+                H.prof.half = 0;
                 H.it_part1 = b1 - b0;
                 H.it_part2 = H.bytes - b1;
             };
@@ -923,6 +1055,7 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
                 for (;;) {
                     const int todo = std::min(chunk, H.opts.maxit - launched);
                     for (int j = 0; j < todo; ++j) {
+                        H.prof.iter = launched + j + 1;
                         if (graph)
                             GIAMG_HIP(hipGraphLaunch(H.it_exec, its));
                         else
@@ -947,6 +1080,8 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
             const int stop = H.host_ctl[C_STOP];
             status = stop == 1 ? GIAMG_OK : stop == 2 ? GIAMG_EBREAKDOWN : GIAMG_ENOTCONV;
             H.last_iters = iters;
+            prof_first = stop == 2 ? iters + 1 : iters;
+            prof_second = stop == 1 ? iters - 1 : iters;
             // bytes of the work that ran: the iteration that stopped skipped its second half
             const int halves2 = std::max(0, (stop == 2 ? iters : iters - 1));
             H.bytes = bytes0 + 16.0 * n + part1 * (stop == 2 ? iters + 1 : iters) + part2 * halves2;
@@ -958,6 +1093,10 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
     }
     GIAMG_HIP(hipEventRecord(H.ev1, s));
     const double bytes = H.bytes;
+    if (H.prof.on != 0 || !H.prof.pending.empty()) {
+        GIAMG_HIP(hipEventSynchronize(H.ev1));
+        prof_harvest(H, iters, prof_first, prof_second);
+    }
     // true residual at exit (outside the timed region)
     rinit(w.tmp);
     launch_reduce(gs, w.partial, gs, 2, w.scal + S_BB, s);
@@ -1050,7 +1189,16 @@ int solve_noalloc(Handle& H, int device, const double* b, double* x, double tol,
     w.partial = reinterpret_cast<double*>(take((size_t)H.partial_cap * sizeof(double)));
     w.scal = reinterpret_cast<double*>(take(S_COUNT * sizeof(double)));
     w.ctl = reinterpret_cast<int*>(take(C_COUNT * sizeof(int)));
-    return solve_on(H, w, false, b, x, tol, info);
+    const int prof = H.prof.on;   // profiling creates events: off for this call
+    H.prof.on = 0;
+    try {
+        const int rc = solve_on(H, w, false, b, x, tol, info);
+        H.prof.on = prof;
+        return rc;
+    } catch (...) {
+        H.prof.on = prof;
+        throw;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,6 +1272,13 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
 }
 }  // namespace
 
+void profile_enable(Handle& H, int on) { H.prof.on = on; }
+
+void profile_read(Handle& H, giamg_profile* out, bool reset) {
+    *out = H.prof.acc;
+    if (reset) H.prof.acc = giamg_profile{};
+}
+
 void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double* bytes) {
     AllocStreamScope alloc_scope(H.stream);
     GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
@@ -1180,6 +1335,9 @@ void apply_t(Handle& H, int op, size_t l, const T* a, const T* b, T* out) {
 
 void apply(Handle& H, int op, int level, const void* a, const void* b, void* out) {
     AllocStreamScope alloc_scope(H.stream);
+    const int base = op & ~GIAMG_OP_FP32;
+    if (H.opts.preconditioner != GIAMG_PRECOND_VCYCLE && base != GIAMG_OP_SPMV && base != GIAMG_OP_RESIDUAL)
+        throw Error(GIAMG_ENOTSUP, "a Jacobi-preconditioned handle has no V-cycle steps");
     GIAMG_REQUIRE(level >= 0 && level < (int)H.levels.size(), "level out of range");
     GIAMG_REQUIRE(a != nullptr, "a is null");
     GIAMG_REQUIRE(b != nullptr || (op & ~GIAMG_OP_FP32) != GIAMG_OP_RESIDUAL,

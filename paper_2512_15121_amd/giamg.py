@@ -21,6 +21,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 LEVEL_KIND = {0: "p", 1: "h"}
 MAT = {"A": 0, "P": 1, "R": 2, "AP": 3}
 BASIS = {"nodal": 0, "modal": 1}
+PRECONDITIONER = {"vcycle": 0, "jacobi": 1}
 BATCH_KERNEL = {"auto": 0, "lanes": 1, "wave": 2, "group": 3}
 OP = {"spmv": 0, "residual": 1, "restrict": 2, "prolong_add": 3, "presmooth": 4,
       "postsmooth": 5, "coarse": 6, "vcycle": 7}
@@ -45,7 +46,8 @@ class _Opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32 * 8), ("batch_kernel", ctypes.c_int32),
                 ("row_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("lean_max_nnz", ctypes.c_int64), ("keep_boundary", ctypes.c_int32),
-                ("pad2", ctypes.c_int32), ("theta", ctypes.c_double)]
+                ("pad2", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("preconditioner", ctypes.c_int32), ("pad3", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -65,6 +67,15 @@ class _ServerStats(ctypes.Structure):
                 ("cache_hits", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
                 ("resident_bytes", ctypes.c_int64), ("groups_resident", ctypes.c_int32),
                 ("pad", ctypes.c_int32)]
+
+
+PHASES = ["first_smooth", "smooth", "residual", "transfer", "coarse", "vcycle", "cg_matvec",
+          "cg_dot", "cg_update", "pcg", "fine_step"]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * len(PHASES)), ("count", ctypes.c_int64 * len(PHASES)),
+                ("solves", ctypes.c_int64), ("iterations", ctypes.c_int64)]
 
 
 class _LevelDesc(ctypes.Structure):
@@ -102,6 +113,7 @@ class Options:
     lean_max_nnz: int = 2000000     # row-direct kernel for operators up to this many nonzeros
     keep_boundary: bool = False     # coarse p-levels keep the constrained nodes
     theta: float = 0.0              # strength threshold of the aggregation graph
+    preconditioner: str = "vcycle"  # or "jacobi": the diagonally preconditioned CG baseline
 
     def _c(self) -> _Opts:
         d = asdict(self)
@@ -117,6 +129,8 @@ class Options:
         d["pad"] = 0
         d["pad2"] = 0
         d["keep_boundary"] = int(d["keep_boundary"])
+        d["preconditioner"] = PRECONDITIONER[d["preconditioner"]]
+        d["pad3"] = 0
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]
@@ -160,6 +174,9 @@ _SIGNATURES = {
     "giamg_load_vector": (I32, [P, P, P]),
     "giamg_setup_times": (I32, [P, P]),
     "giamg_last_error": (ctypes.c_char_p, []),
+    "giamg_profile_enable": (I32, [P, I32]),
+    "giamg_profile_read": (I32, [P, ctypes.POINTER(_Profile), I32]),
+    "giamg_read_bandwidth": (I32, [I64, I32, P]),
     "giamg_hcsr_size": (I32, [P, P, P, P]),
     "giamg_hcsr_copy": (I32, [P, P, P, P]),
     "giamg_hcsr_free": (None, [P]),
@@ -458,11 +475,34 @@ class Solver:
         _check(self.lib.giamg_time_kernel(self._h, code, level, reps, _ptr(ms), _ptr(by)))
         return float(ms[0]), float(by[0])
 
+    def profile(self, on=True, fine_step_only=False):
+        """Profile the following solves: every phase (the breakdown), or
+        only the launches of the fine Chebyshev step (fine_step_only)."""
+        level = 0 if not on else (2 if fine_step_only else 1)
+        _check(self.lib.giamg_profile_enable(self._h, level))
+
+    def profile_read(self, reset=True):
+        """{phase: (ms summed, intervals)} plus solves and iterations."""
+        pr = _Profile()
+        _check(self.lib.giamg_profile_read(self._h, ctypes.byref(pr), 1 if reset else 0))
+        out = {name: (pr.ms[i], pr.count[i]) for i, name in enumerate(PHASES)}
+        out["solves"] = pr.solves
+        out["iterations"] = pr.iterations
+        return out
+
     def setup_times(self):
         ms = np.zeros(7)
         _check(self.lib.giamg_setup_times(self._h, _ptr(ms)))
         keys = ["assembly", "p_transfer", "aggregation", "galerkin", "coarsest", "smoother", "total"]
         return dict(zip(keys, ms.tolist()))
+
+
+def read_bandwidth(nbytes=1 << 30, reps=10):
+    """Median GB/s of the library's streaming read kernel over reps reads of
+    a buffer of nbytes on the current device."""
+    g = np.zeros(1)
+    _check(library().giamg_read_bandwidth(int(nbytes), int(reps), _ptr(g)))
+    return float(g[0])
 
 
 # ---- host-side setup steps (no GPU) ---------------------------------------

@@ -65,7 +65,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2512_15121_amd import giamg
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    mirrors = {"giamg_opts": giamg._Opts, "giamg_info": giamg._Info,
+    mirrors = {"giamg_opts": giamg._Opts, "giamg_info": giamg._Info, "giamg_profile": giamg._Profile,
                "giamg_level_desc": giamg._LevelDesc, "giamg_server_opts": giamg._ServerOpts,
                "giamg_server_statistics": giamg._ServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "giamg.h"', "int main(void) {"]
@@ -94,9 +94,12 @@ def test_option_constants_match_header():
     text = open(os.path.join(ROOT, "include", "giamg.h")).read()
     defs = {m.group(1): int(m.group(2))
             for m in re.finditer(r"#define\s+(GIAMG_\w+)\s+\(?(-?\d+)\)?", text)}
+    for i, name in enumerate(giamg.PHASES):
+        assert defs["GIAMG_PHASE_" + name.upper()] == i, name
+    assert defs["GIAMG_PHASE_COUNT"] == len(giamg.PHASES)
     tables = {"GIAMG_BATCH_": giamg.BATCH_KERNEL, "GIAMG_BASIS_": giamg.BASIS,
               "GIAMG_BC_": giamg.BC, "GIAMG_PREC_": giamg.PRECISION,
-              "GIAMG_SMOOTHER_": giamg.SMOOTHER}
+              "GIAMG_SMOOTHER_": giamg.SMOOTHER, "GIAMG_PRECOND_": giamg.PRECONDITIONER}
     for prefix, table in tables.items():
         for name, value in table.items():
             assert defs[prefix + name.upper()] == value, prefix + name
@@ -220,3 +223,8 @@ def test_theta_and_hierarchy_info_validation_without_device_work():
     nl = ctypes.c_int32(-7)
     rc = lib.giamg_hierarchy_info(None, ctypes.byref(nl), None, None, 0)
     assert rc == giamg.EINVAL and nl.value == -7
+    assert lib.giamg_profile_enable(None, 1) == giamg.EINVAL
+    g = np.zeros(1)
+    assert lib.giamg_read_bandwidth(1024, 3, giamg._ptr(g)) == giamg.EINVAL
+    assert b"1 MiB" in lib.giamg_last_error()
+    assert lib.giamg_read_bandwidth(1 << 20, 0, giamg._ptr(g)) == giamg.EINVAL

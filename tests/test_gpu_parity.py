@@ -709,3 +709,83 @@ def test_hierarchy_info_through_the_c_abi(torch_dev):
     H0 = hierarchy.build(m.coords, m.l2g, 4, 10.0, hierarchy.Options(coarse_max=100))
     assert H.levels[-1].A.shape[0] > H0.levels[-1].A.shape[0]
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profile_counts_and_unchanged_results(torch_dev, precision):
+    """Phase profiling (the paper's breakdown categories): a solve of k CG
+    iterations with Chebyshev degree 2 runs k V-cycles (the start-up one and
+    k - 1 in the loop: the converged iteration skips its second half), two
+    fine-level Chebyshev steps per V-cycle, k CG products; work queued past
+    convergence is not counted.  Profiling changes no result bit, and the
+    phases fit inside the solve's own time."""
+    torch, dev = torch_dev
+    name = "p4_6cube_cheb_sa"
+    m, H = _case(name)
+    b = _to(torch, dev, synth.normal_rhs(m.n_nodes, 12))
+    s = _solver(name, precision=precision)
+    x0, i0 = s.solve(b, tol=1e-10)
+    s.profile(True)
+    total_ms = 0.0
+    for _ in range(2):
+        x1, i1 = s.solve(b, tol=1e-10)
+        total_ms += i1.solve_ms
+        assert torch.equal(x1, x0) and i1.iters == i0.iters
+    p = s.profile_read(reset=True)
+    s.profile(False)
+    k = i0.iters
+    assert p["solves"] == 2 and p["iterations"] == 2 * k
+    assert p["vcycle"][1] == 2 * k and p["pcg"][1] == 2 * k and p["cg_matvec"][1] == 2 * k
+    assert p["fine_step"][1] == 2 * 2 * k
+    assert p["first_smooth"][1] == 2 * 2 * k
+    nl = s.num_levels()
+    assert p["coarse"][1] == 2 * k
+    assert p["smooth"][1] == 2 * 2 * k * (nl - 1)
+    for ph in ("first_smooth", "smooth", "residual", "transfer", "coarse", "vcycle", "cg_matvec",
+               "cg_dot", "cg_update", "pcg", "fine_step"):
+        assert p[ph][0] > 0, ph
+    assert p["pcg"][0] <= total_ms and p["vcycle"][0] <= total_ms
+    assert p["first_smooth"][0] <= p["smooth"][0] + 1e-6
+    assert p["fine_step"][0] <= p["first_smooth"][0] + 1e-6
+    # reading again after the reset: empty
+    q = s.profile_read(reset=False)
+    assert q["solves"] == 0 and q["vcycle"] == (0.0, 0)
+    s.close()
+
+
+def test_jacobi_pcg_baseline_parity(torch_dev):
+    """The diagonally preconditioned CG baseline of the paper's comparison
+    (Section 3.2): one level, against the oracle's Jacobi-PCG.  A run of a
+    fixed number of iterations matches to 1e-9 (iterate) and 1e-6
+    (recursive residual); to the tolerance the iteration counts agree within
+    one percent (hundreds of iterations let rounding move the stopping point
+    by one or two).  The V-cycle-only entry points refuse such a handle."""
+    torch, dev = torch_dev
+    from paper_2512_15121_amd import giamg
+    name = "p4_6cube_cheb_sa"
+    m, H = _case(name)
+    A = H.levels[0].A
+    b = synth.normal_rhs(m.n_nodes, 12)
+    bt = _to(torch, dev, b)
+    s = _solver(name, preconditioner="jacobi")
+    assert s.num_levels() == 1
+    x, info = s.solve(bt, tol=1e-10)
+    ref = krylov.jacobi_pcg(A, b, tol=1e-10)
+    assert info.status == 0 and ref.converged and ref.iters > 50
+    assert abs(info.iters - ref.iters) <= max(1, ref.iters // 100), (info.iters, ref.iters)
+    assert info.true_relres < 2e-10
+    k = 40
+    s2 = _solver(name, preconditioner="jacobi", maxit=k)
+    x2, i2 = s2.solve(bt, tol=0.0)
+    ref2 = krylov.jacobi_pcg(A, b, tol=0.0, maxit=k)
+    assert i2.iters == k == ref2.iters
+    assert np.linalg.norm(x2.cpu().numpy() - ref2.x) <= 1e-9 * np.linalg.norm(ref2.x)
+    assert abs(i2.relres - ref2.history[-1]) <= 1e-6 * ref2.history[-1]
+    with pytest.raises(giamg.GiamgError) as e:
+        s.solve_batch(torch.zeros(m.n_nodes, 2, dtype=torch.float64, device=dev))
+    assert e.value.code == giamg.ENOTSUP
+    s.close()
+    s2.close()
+    with pytest.raises(giamg.GiamgError) as e:
+        _solver(name, preconditioner="jacobi", precision="mixed")
+    assert e.value.code == giamg.EINVAL

@@ -137,3 +137,47 @@ def test_manufactured_4cube_converges_order_robust():
         assert res.converged and res.true_relres < 1e-9
         iters.append(res.iters)
     assert max(iters) <= 2 * min(iters) + 5
+
+
+def test_jacobi_pcg_exact_on_a_diagonal_matrix():
+    """With A diagonal the preconditioner is A^-1: one iteration solves."""
+    import scipy.sparse as sp
+    d = np.linspace(0.5, 40.0, 30)
+    b = np.sin(np.arange(30.0))
+    res = krylov.jacobi_pcg(sp.diags(d).tocsr(), b, tol=1e-14)
+    assert res.iters == 1 and np.allclose(res.x, b / d, rtol=1e-15, atol=0)
+
+
+def test_jacobi_pcg_is_cg_on_the_scaled_system():
+    """Jacobi-PCG on A x = b produces x_k = D^-1/2 y_k, y_k the iterates of
+    plain CG on (D^-1/2 A D^-1/2) y = D^-1/2 b (the classical equivalence),
+    written here as a textbook CG loop on the scaled matrix."""
+    import scipy.sparse as sp
+    import synth
+    from oracle import assembly
+    m = synth.hex_mesh(3, 3, perturb=0.15, seed=8)
+    A, _ = assembly.assemble(m.coords, m.l2g, 3, 2.0)
+    b = synth.normal_rhs(m.n_nodes, 3)
+    s = 1.0 / np.sqrt(A.diagonal())
+    S = sp.diags(s)
+    Ah = (S @ A @ S).tocsr()
+    bh = s * b
+    for k in (1, 5, 17):
+        y = np.zeros_like(bh)
+        r = bh.copy()
+        pdir = r.copy()
+        rr = r @ r
+        for _ in range(k):
+            q = Ah @ pdir
+            alpha = rr / (pdir @ q)
+            y += alpha * pdir
+            r -= alpha * q
+            rr_new = r @ r
+            pdir = r + (rr_new / rr) * pdir
+            rr = rr_new
+        res = krylov.jacobi_pcg(A, b, tol=0.0, maxit=k)
+        assert res.iters == k
+        assert np.linalg.norm(res.x - s * y) <= 1e-11 * np.linalg.norm(s * y)
+    full = krylov.jacobi_pcg(A, b, tol=1e-12)
+    ref = np.linalg.solve(A.toarray(), b)
+    assert np.linalg.norm(full.x - ref) <= 1e-9 * np.linalg.norm(ref)
