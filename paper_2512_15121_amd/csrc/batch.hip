@@ -1324,9 +1324,15 @@ struct Session {
     double tol = 0.0;
     DevBuf<double> Bm, X;
     DevBuf<int> slots;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;         // after the last enqueued step (and its state copy)
+    hipEvent_t slots_copied = nullptr; // after the last copy out of host_slots
+    ColState* host_states = nullptr;   // pinned: column states as of the last step
+    int* host_slots = nullptr;         // pinned: slot list of the last admission
     ~Session() {
         if (done) (void)hipEventDestroy(done);
+        if (slots_copied) (void)hipEventDestroy(slots_copied);
+        if (host_states) (void)hipHostFree(host_states);
+        if (host_slots) (void)hipHostFree(host_slots);
     }
 };
 
@@ -1369,6 +1375,11 @@ Session* session_create(Handle& H, int k, double tol) {
     }
     GIAMG_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
     GIAMG_HIP(hipEventCreateWithFlags(&S->done, hipEventDisableTiming));
+    GIAMG_HIP(hipEventCreateWithFlags(&S->slots_copied, hipEventDisableTiming));
+    GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->host_states), k * sizeof(ColState)));
+    GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->host_slots), k * sizeof(int)));
+    std::memset(S->host_states, 0, k * sizeof(ColState));
+    GIAMG_HIP(hipEventRecord(S->slots_copied, s));
     GIAMG_HIP(hipStreamSynchronize(s));
     return S.release();
 }
@@ -1393,17 +1404,49 @@ void session_admit(Session* S, const int* slot, const double* const* b, int coun
         GIAMG_REQUIRE(sl[i] >= 0 && sl[i] < S->k, "slot out of range");
         bscatter_kernel<<<bgrid(H.n_nodes), 256, 0, s>>>(H.n_nodes, S->k, sl[i], b[i], S->Bm.get(), S->X.get());
     }
-    GIAMG_HIP(hipMemcpyAsync(S->slots.get(), sl.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
+    // the slot list goes through pinned memory, so the copy is asynchronous;
+    // the previous admission's copy out of it has finished first
+    GIAMG_HIP(hipEventSynchronize(S->slots_copied));
+    std::memcpy(S->host_slots, sl.data(), count * sizeof(int));
+    GIAMG_HIP(hipMemcpyAsync(S->slots.get(), S->host_slots, count * sizeof(int), hipMemcpyHostToDevice, s));
+    GIAMG_HIP(hipEventRecord(S->slots_copied, s));
     bmark_init_kernel<<<1, 256, 0, s>>>(S->k, B.st.get(), S->slots.get(), count);
     BatchCtx c{H, B, S->k, B.run.get(), false};
     start_columns(c, S->Bm.get(), S->X.get(), S->tol);
     GIAMG_HIP(hipEventRecord(S->done, s));
 }
 
-// Enqueue `iters` CG iterations for every running slot (asynchronous).
+// Enqueue `iters` CG iterations for every running slot, then a copy of the
+// column states to pinned host memory (asynchronous; session_ready tells
+// when both are done and session_states reads the copy).
 void session_step(Session* S, int iters) {
     for (int i = 0; i < iters; ++i) GIAMG_HIP(hipGraphLaunch(S->B->exec, S->B->stream));
+    GIAMG_HIP(hipMemcpyAsync(S->host_states, S->B->st.get(), S->k * sizeof(ColState), hipMemcpyDeviceToHost,
+                             S->B->stream));
     GIAMG_HIP(hipEventRecord(S->done, S->B->stream));
+}
+
+namespace {
+void decode_states(const Session* S, const ColState* hs, int* state, giamg_info* infos) {
+    for (int j = 0; j < S->k; ++j) {
+        const ColState& c = hs[j];
+        state[j] = (c.active || c.init) ? 1 : 0;
+        if (infos) {
+            infos[j].iters = c.iters;
+            infos[j].status = c.status;
+            infos[j].relres = c.bb > 0 ? std::sqrt(c.rr) / std::sqrt(c.bb) : 0.0;
+            infos[j].true_relres = -1.0;
+            infos[j].solve_ms = 0.0;
+            infos[j].bytes = 0.0;
+        }
+    }
+}
+}  // namespace
+
+// Slot states as of the last completed step (no synchronisation; call after
+// session_ready returned true).
+void session_states(Session* S, int* state, giamg_info* infos) {
+    decode_states(S, S->host_states, state, infos);
 }
 
 bool session_ready(Session* S) {
@@ -1421,18 +1464,7 @@ void session_poll(Session* S, int* state, giamg_info* infos) {
     std::vector<ColState> hs(S->k);
     GIAMG_HIP(hipMemcpyAsync(hs.data(), B.st.get(), S->k * sizeof(ColState), hipMemcpyDeviceToHost, B.stream));
     GIAMG_HIP(hipStreamSynchronize(B.stream));
-    for (int j = 0; j < S->k; ++j) {
-        const ColState& c = hs[j];
-        state[j] = (c.active || c.init) ? 1 : 0;
-        if (infos) {
-            infos[j].iters = c.iters;
-            infos[j].status = c.status;
-            infos[j].relres = c.bb > 0 ? std::sqrt(c.rr) / std::sqrt(c.bb) : 0.0;
-            infos[j].true_relres = -1.0;
-            infos[j].solve_ms = 0.0;
-            infos[j].bytes = 0.0;
-        }
-    }
+    decode_states(S, hs.data(), state, infos);
 }
 
 // Copy the slot's solution to x (device, n entries) and free the slot.

@@ -31,7 +31,7 @@ void session_destroy(Session* S);
 void session_admit(Session* S, const int* slot, const double* const* b, int count);
 void session_step(Session* S, int iters);
 bool session_ready(Session* S);
-void session_poll(Session* S, int* state, giamg_info* infos);
+void session_states(Session* S, int* state, giamg_info* infos);
 void session_retire_async(Session* S, int slot, double* x);
 hipStream_t session_stream(Session* S);
 int64_t session_device_bytes(const Session* S);
@@ -66,20 +66,40 @@ struct Request {
     std::string msg;         // error message of a failed request
 };
 
+// A resident hierarchy with its session.  Slot s holds request slot_req[s]
+// (-1: free).  A right-hand side enters through stretch s of the pinned input
+// staging and of the device staging; a finished column drains (gathered into
+// the device staging, copied to stretch s of the pinned output staging)
+// behind the `drained` event, and its request completes once that event has
+// passed.  A slot is free for a new request as soon as its drain is queued:
+// the group's stream runs the drain before the next admission's copies.
 struct Group {
     int problem = -1;
     std::unique_ptr<Handle> H;
     Session* S = nullptr;
     hipStream_t stream = nullptr;
     std::vector<int64_t> slot_req;   // request id per slot, -1 free
-    bool inflight = false;
+    std::vector<char> running;       // the column iterates (as of the last completed step)
+    std::vector<std::pair<int, int64_t>> draining;   // (slot, request) on their way to the host
+    std::vector<giamg_info> info;    // per slot: the state of its column when it finished
+    hipEvent_t drained = nullptr;
+    bool inflight = false;           // a step is queued and not yet complete
     Clock::time_point last_used;
     int64_t bytes = 0;
     DevBuf<double> stage;            // [slots][n] right-hand sides / results
+    double* pin_in = nullptr;        // [slots][n] host staging of right-hand sides
+    double* pin_out = nullptr;       // [slots][n] host staging of solutions
+    bool idle() const {
+        return !inflight && draining.empty() &&
+               std::none_of(slot_req.begin(), slot_req.end(), [](int64_t v) { return v >= 0; });
+    }
     ~Group() {
-        if (S) session_destroy(S);
+        if (S) session_destroy(S);   // waits for the session's stream
         H.reset();
         if (stream) (void)hipStreamDestroy(stream);
+        if (drained) (void)hipEventDestroy(drained);
+        if (pin_in) (void)hipHostFree(pin_in);
+        if (pin_out) (void)hipHostFree(pin_out);
     }
 };
 }  // namespace
@@ -104,27 +124,10 @@ struct Server {
     int worker_dead = 0;     // error code once the setup worker has died
     std::string worker_msg;
     std::thread loop, setup;
-    // Pinned host staging of the loop thread: the right-hand sides admitted
-    // into, or the solutions harvested from, one group at a time ([slots][n]).
-    double* pinned = nullptr;
-    size_t pinned_n = 0;
-    hipEvent_t copied = nullptr;     // the staging copies of one admission batch are done
-    double* pinned_for(size_t n) {
-        if (n > pinned_n) {
-            if (pinned) GIAMG_HIP(hipHostFree(pinned));
-            pinned = nullptr;
-            pinned_n = 0;
-            GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), n * sizeof(double)));
-            pinned_n = n;
-        }
-        return pinned;
-    }
     ~Server() {
-        // the groups first: they wait for their streams before freeing
+        // the groups wait for their streams before freeing
         groups.clear();
         setup_done.clear();
-        if (pinned) (void)hipHostFree(pinned);
-        if (copied) (void)hipEventDestroy(copied);
     }
 
     // Device bytes of a problem's group: measured after its first setup,
@@ -167,7 +170,14 @@ struct Server {
                 build_hierarchy(H, P.coords.data(), P.l2g.data());
                 g->S = session_create(H, o.slots, o.tol);
                 g->stage.alloc((size_t)o.slots * P.n_nodes);
+                GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->pin_in),
+                                        (size_t)o.slots * P.n_nodes * sizeof(double)));
+                GIAMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->pin_out),
+                                        (size_t)o.slots * P.n_nodes * sizeof(double)));
+                GIAMG_HIP(hipEventCreateWithFlags(&g->drained, hipEventDisableTiming));
                 g->slot_req.assign(o.slots, -1);
+                g->running.assign(o.slots, 0);
+                g->info.assign(o.slots, giamg_info{});
                 g->bytes = handle_device_bytes(H) + session_device_bytes(g->S) +
                            (int64_t)g->stage.n * 8;
             } catch (const Error& e) {
@@ -230,9 +240,7 @@ struct Server {
             int victim = -1;
             for (size_t i = 0; i < groups.size(); ++i) {
                 Group* g = groups[i].get();
-                if (!g || g->inflight || queued.count((int)i)) continue;
-                if (std::any_of(g->slot_req.begin(), g->slot_req.end(), [](int64_t v) { return v >= 0; }))
-                    continue;
+                if (!g || !g->idle() || queued.count((int)i)) continue;
                 if (victim < 0 || g->last_used < groups[victim]->last_used) victim = (int)i;
             }
             if (victim < 0) return false;
@@ -247,55 +255,144 @@ struct Server {
         return true;
     }
 
+    // requires mu held: up to `room` pending requests for `problem`, in
+    // arrival order, taken off the pending list
+    std::vector<Request*> take_pending(int problem, int room) {
+        std::vector<Request*> out;
+        for (auto it = pending.begin(); it != pending.end() && (int)out.size() < room;) {
+            Request& r = requests[*it];
+            if (r.problem == problem) {
+                out.push_back(&r);
+                it = pending.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        return out;
+    }
+
+    // One pass over a group at a chunk boundary (no step in flight): drain
+    // the columns that finished, admit pending requests into free slots,
+    // queue the next chunk of iterations.  Every call here is asynchronous.
+    bool group_boundary(Group& g, bool requests_waiting, std::vector<int>& state,
+                        std::vector<giamg_info>& infos) {
+        bool progress = false;
+        const int64_t n = problems[g.problem].n_nodes;
+        hipStream_t st = session_stream(g.S);
+        if (g.inflight) {   // the step completed: read the column states it copied out
+            g.inflight = false;
+            state.assign(o.slots, 0);
+            infos.assign(o.slots, giamg_info{});
+            session_states(g.S, state.data(), infos.data());
+            for (int sl = 0; sl < o.slots; ++sl) {
+                if (g.running[sl] && !state[sl]) g.info[sl] = infos[sl];
+                g.running[sl] = g.running[sl] && state[sl];
+            }
+            progress = true;
+        }
+        // finished columns drain (one drain in flight per group)
+        if (g.draining.empty()) {
+            for (int sl = 0; sl < o.slots; ++sl) {
+                if (g.slot_req[sl] < 0 || g.running[sl]) continue;
+                double* dev = g.stage.get() + (size_t)sl * n;
+                session_retire_async(g.S, sl, dev);
+                GIAMG_HIP(hipMemcpyAsync(g.pin_out + (size_t)sl * n, dev, n * sizeof(double),
+                                         hipMemcpyDeviceToHost, st));
+                g.draining.emplace_back(sl, g.slot_req[sl]);
+                g.slot_req[sl] = -1;
+            }
+            if (!g.draining.empty()) {
+                GIAMG_HIP(hipEventRecord(g.drained, st));
+                progress = true;
+            }
+        }
+        // admissions into the free slots
+        const int room = (int)std::count(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1);
+        std::vector<Request*> adm;
+        if (room > 0 && requests_waiting) {
+            std::lock_guard<std::mutex> lk(mu);
+            adm = take_pending(g.problem, room);
+        }
+        if (!adm.empty()) {
+            std::vector<int> slots;
+            std::vector<const double*> ptrs;
+            for (Request* rp : adm) {
+                const int sl =
+                    (int)(std::find(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1) - g.slot_req.begin());
+                g.slot_req[sl] = rp->id;
+                g.running[sl] = 1;
+                double* dst = g.stage.get() + (size_t)sl * n;
+                double* src = g.pin_in + (size_t)sl * n;
+                std::memcpy(src, rp->b.data(), n * sizeof(double));
+                GIAMG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st));
+                slots.push_back(sl);
+                ptrs.push_back(dst);
+            }
+            session_admit(g.S, slots.data(), ptrs.data(), (int)slots.size());
+            progress = true;
+        }
+        // the next chunk for the running columns
+        if (std::any_of(g.running.begin(), g.running.end(), [](char v) { return v != 0; })) {
+            session_step(g.S, o.chunk);
+            g.inflight = true;
+            progress = true;
+        }
+        if (progress) g.last_used = Clock::now();
+        return progress;
+    }
+
     void loop_main() {
         GIAMG_HIP(hipSetDevice(device));
         std::vector<int> state;
         std::vector<giamg_info> infos;
         while (true) {
             bool progress = false;
-            std::unique_lock<std::mutex> lk(mu);
-            if (stop) break;
-            if (worker_dead) throw Error(worker_dead, worker_msg);
-            // finished setups become resident groups
-            while (!setup_done.empty()) {
-                std::unique_ptr<Group> g = std::move(setup_done.back());
-                setup_done.pop_back();
-                Problem& P = problems[g->problem];
-                reserved -= P.reserved;
-                P.reserved = 0;
-                P.known_bytes = g->bytes;
-                resident += g->bytes;
-                st.peak_bytes = std::max(st.peak_bytes, resident);
-                P.setting_up = false;
-                size_t slot = 0;
-                while (slot < groups.size() && groups[slot]) ++slot;
-                if (slot == groups.size()) groups.emplace_back();
-                P.group = (int)slot;
-                g->last_used = Clock::now();
-                groups[slot] = std::move(g);
-                st.setups += 1;
-                progress = true;
-            }
-            // admissions, in arrival order
-            std::map<int, std::vector<Request*>> admit;   // group -> requests
-            for (auto it = pending.begin(); it != pending.end();) {
-                Request& r = requests[*it];
-                Problem& P = problems[r.problem];
-                if (P.failed) {
-                    r.msg = P.fail_msg;
-                    finish(r, P.failed);
-                    it = pending.erase(it);
+            std::map<int, std::vector<Request*>> wanted;   // groups with requests waiting
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (stop) break;
+                if (worker_dead) throw Error(worker_dead, worker_msg);
+                // finished setups become resident groups
+                while (!setup_done.empty()) {
+                    std::unique_ptr<Group> g = std::move(setup_done.back());
+                    setup_done.pop_back();
+                    Problem& P = problems[g->problem];
+                    reserved -= P.reserved;
+                    P.reserved = 0;
+                    P.known_bytes = g->bytes;
+                    resident += g->bytes;
+                    st.peak_bytes = std::max(st.peak_bytes, resident);
+                    P.setting_up = false;
+                    size_t slot = 0;
+                    while (slot < groups.size() && groups[slot]) ++slot;
+                    if (slot == groups.size()) groups.emplace_back();
+                    P.group = (int)slot;
+                    g->last_used = Clock::now();
+                    groups[slot] = std::move(g);
+                    st.setups += 1;
                     progress = true;
-                    continue;
                 }
-                if (!r.counted) {
-                    r.counted = true;
-                    if (P.group >= 0) st.cache_hits += 1;
-                }
-                if (P.group < 0) {
-                    if (!P.setting_up) {
+                // requests of failed problems end; problems without a
+                // resident hierarchy are set up when the budget allows
+                for (auto it = pending.begin(); it != pending.end();) {
+                    Request& r = requests[*it];
+                    Problem& P = problems[r.problem];
+                    if (P.failed) {
+                        r.msg = P.fail_msg;
+                        finish(r, P.failed);
+                        it = pending.erase(it);
+                        progress = true;
+                        continue;
+                    }
+                    if (!r.counted) {
+                        r.counted = true;
+                        if (P.group >= 0) st.cache_hits += 1;
+                    }
+                    if (P.group >= 0) {
+                        wanted[P.group].push_back(&r);
+                    } else if (!P.setting_up) {
                         const int64_t est = need(P);
-                        if (make_room(est, admit)) {
+                        if (make_room(est, wanted)) {
                             P.setting_up = true;
                             P.reserved = est;
                             reserved += est;
@@ -305,97 +402,32 @@ struct Server {
                         }
                     }
                     ++it;
-                    continue;
                 }
-                Group& g = *groups[P.group];
-                const auto found = admit.find(P.group);
-                const int64_t queued = found == admit.end() ? 0 : (int64_t)found->second.size();
-                const int64_t free_slots =
-                    std::count(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1) - queued;
-                if (g.inflight || free_slots <= 0) {
-                    ++it;
-                    continue;
-                }
-                admit[P.group].push_back(&r);
-                it = pending.erase(it);
             }
-            lk.unlock();
-            // no synchronising HIP call of this thread may overlap a capture
-            std::unique_lock<std::mutex> cap(capture_mutex());
-            for (auto& kv : admit) {
-                if (kv.second.empty()) continue;
-                Group& g = *groups[kv.first];
-                std::vector<int> slots;
-                std::vector<const double*> ptrs;
-                const int64_t n = problems[g.problem].n_nodes;
-                // every right-hand side of the batch through its own stretch
-                // of the pinned staging, one wait for all the copies
-                double* host = pinned_for((size_t)o.slots * n);
-                for (Request* rp : kv.second) {
-                    int slot = (int)(std::find(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1) - g.slot_req.begin());
-                    g.slot_req[slot] = rp->id;
-                    double* dst = g.stage.get() + (size_t)slot * n;
-                    double* src = host + (size_t)slot * n;
-                    std::memcpy(src, rp->b.data(), n * sizeof(double));
-                    GIAMG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice,
-                                             session_stream(g.S)));
-                    slots.push_back(slot);
-                    ptrs.push_back(dst);
-                }
-                if (!copied) GIAMG_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
-                GIAMG_HIP(hipEventRecord(copied, session_stream(g.S)));
-                session_admit(g.S, slots.data(), ptrs.data(), (int)slots.size());
-                GIAMG_HIP(hipEventSynchronize(copied));   // the staging is free again
-                g.last_used = Clock::now();
-                progress = true;
-            }
-            // advance every group with running slots; harvest finished ones
-            for (auto& gp : groups) {
-                if (!gp) continue;
-                Group& g = *gp;
-                const bool busy = std::any_of(g.slot_req.begin(), g.slot_req.end(),
-                                              [](int64_t v) { return v >= 0; });
-                if (!busy) continue;
-                if (g.inflight && !session_ready(g.S)) continue;
-                if (g.inflight) {
-                    g.inflight = false;
-                    state.assign(o.slots, 0);
-                    infos.assign(o.slots, giamg_info{});
-                    session_poll(g.S, state.data(), infos.data());
-                    const int64_t n = problems[g.problem].n_nodes;
-                    // retire every finished slot and copy the solutions out
-                    // through the pinned staging, one wait for all of them
-                    std::vector<int> done;
-                    for (int s = 0; s < o.slots; ++s)
-                        if (g.slot_req[s] >= 0 && !state[s]) done.push_back(s);
-                    if (!done.empty()) {
-                        double* host = pinned_for((size_t)o.slots * n);
-                        for (int s : done) {
-                            double* dev = g.stage.get() + (size_t)s * n;
-                            session_retire_async(g.S, s, dev);
-                            GIAMG_HIP(hipMemcpyAsync(host + (size_t)s * n, dev, n * sizeof(double),
-                                                     hipMemcpyDeviceToHost, session_stream(g.S)));
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                if (!groups[gi]) continue;
+                Group& g = *groups[gi];
+                // drains that reached the host: their requests complete
+                if (!g.draining.empty()) {
+                    const hipError_t e = hipEventQuery(g.drained);
+                    if (e != hipSuccess && e != hipErrorNotReady) GIAMG_HIP(e);
+                    if (e == hipSuccess) {
+                        const int64_t n = problems[g.problem].n_nodes;
+                        std::lock_guard<std::mutex> lk(mu);
+                        for (const auto& d : g.draining) {
+                            Request& r = requests[d.second];
+                            std::memcpy(r.x, g.pin_out + (size_t)d.first * n, n * sizeof(double));
+                            r.info = g.info[d.first];
+                            finish(r, g.info[d.first].status);
                         }
-                        GIAMG_HIP(hipStreamSynchronize(session_stream(g.S)));
-                        std::lock_guard<std::mutex> lk2(mu);
-                        for (int s : done) {
-                            Request& r = requests[g.slot_req[s]];
-                            std::memcpy(r.x, host + (size_t)s * n, n * sizeof(double));
-                            r.info = infos[s];
-                            finish(r, infos[s].status);
-                            g.slot_req[s] = -1;
-                        }
+                        g.draining.clear();
+                        g.last_used = Clock::now();
                         progress = true;
                     }
-                    g.last_used = Clock::now();
                 }
-                if (std::any_of(g.slot_req.begin(), g.slot_req.end(), [](int64_t v) { return v >= 0; })) {
-                    session_step(g.S, o.chunk);
-                    g.inflight = true;
-                    progress = true;
-                }
+                if (g.inflight && !session_ready(g.S)) continue;
+                if (group_boundary(g, wanted.count((int)gi) > 0, state, infos)) progress = true;
             }
-            cap.unlock();
             if (!progress) {
                 std::unique_lock<std::mutex> lk3(mu);
                 if (stop) break;
