@@ -55,5 +55,55 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host code checked by AddressSanitizer and UndefinedBehaviorSanitizer: every
+# sanitizer flag applies to the host compilation only (device code is built
+# as usual); the result is a separate library for CPU-side tests, loaded with
+# the sanitizer runtime preloaded.
+SAN_OUT = os.path.join(HERE, "_build_san", "libgiamg_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-g"]
+
+
+def sanitizer_runtime() -> str:
+    """Path of the AddressSanitizer runtime of the ROCm clang (it carries
+    the UndefinedBehaviorSanitizer handlers too)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise RuntimeError("no AddressSanitizer runtime under /opt/rocm/lib/llvm")
+    return hits[-1]
+
+
+def _compile_san(src):
+    obj = os.path.join(os.path.dirname(SAN_OUT), os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *SAN_FLAGS, "-x", "hip", "-c", os.path.join(SRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, r
+
+
+def build_sanitized() -> str:
+    """Build libgiamg_san.so (host code under ASan and UBSan)."""
+    os.makedirs(os.path.dirname(SAN_OUT), exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(_compile_san, SOURCES))
+    objs = []
+    for src, obj, r in results:
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc failed on {src} (sanitized build)")
+        objs.append(obj)
+    tmp = SAN_OUT + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libasan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-o", tmp, *objs, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("sanitized link failed")
+    os.replace(tmp, SAN_OUT)
+    return SAN_OUT
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
