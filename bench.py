@@ -411,6 +411,8 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
                 except Exception as e:      # recorded, reported as a failed request
                     status[i] = getattr(e, "code", -1)
                     log(f"serving: request {i} failed: {e}")
+                if (i + 1) % 250 == 0:
+                    log(f"serving: {i + 1} of {len(reqs)} requests done")
         th = threading.Thread(target=waiter, daemon=True)
         th.start()
         t0 = time.perf_counter()
@@ -493,6 +495,10 @@ def main():
                     help="only run the parameter studies at p = 5 (Chebyshev degree x "
                          "p-schedule x basis, with breakdowns) and print them as one JSON line")
     ap.add_argument("--serving", default="small", choices=["small", "medium", "full", "off"])
+    ap.add_argument("--serving-slots", type=int, default=8,
+                    help="right-hand sides batched per hierarchy in the serving leg")
+    ap.add_argument("--serving-chunk", type=int, default=2,
+                    help="CG iterations between admission points in the serving leg")
     ap.add_argument("--serving-only", action="store_true",
                     help="only run the serving leg given by --serving and print it as one JSON line")
     ap.add_argument("--batched-only", action="store_true",
@@ -520,7 +526,8 @@ def main():
         return
     if args.serving_only:
         from paper_2512_15121_amd import Server
-        print(json.dumps({"serving": serving(torch, Server, Options, args.serving)}), flush=True)
+        print(json.dumps({"serving": serving(torch, Server, Options, args.serving, args.serving_slots,
+                                             args.serving_chunk)}), flush=True)
         return
     mesh, b, lam, w = problem(args.workload)
     if args.pmc_probe:
@@ -616,7 +623,8 @@ def main():
         extra["study_nodal_p5"] = study(torch, Solver, Options, reps=1, bases=("nodal",))
     if args.serving != "off":
         from paper_2512_15121_amd import Server
-        extra["serving"] = serving(torch, Server, Options, args.serving)
+        extra["serving"] = serving(torch, Server, Options, args.serving, args.serving_slots,
+                                   args.serving_chunk)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -643,16 +651,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def serving(torch, Server, Options, size):
+def serving(torch, Server, Options, size, slots=8, chunk=2):
     """The serving trace of the chosen size (small: 200 requests, n <= 8,
     p <= 4; medium: 2000 requests, n <= 16, p <= 6; full: 2000 requests,
-    n <= 24, p <= 6)."""
+    n <= 24, p <= 6, hierarchies of up to ~30 GB, 250 GB of HBM budget)."""
     try:
         if size == "full":
-            return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24), p_range=(2, 6))
+            return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24), p_range=(2, 6),
+                               budget=250e9, slots=slots, chunk=chunk)
         if size == "medium":
-            return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 16), p_range=(2, 6))
-        return serving_leg(torch, Server, Options)
+            return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 16), p_range=(2, 6),
+                               slots=slots, chunk=chunk)
+        return serving_leg(torch, Server, Options, slots=slots, chunk=chunk)
     except Exception as e:
         log(f"serving leg failed: {e}")
         return {"error": str(e)}

@@ -376,8 +376,16 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 // the kernel, so nothing ahead of the value stream waits on loads.  A row
 // longer than the capacity (forms 0 and 2 only) has a block of its own, summed
 // straight from memory by the whole block.
+// Occupancy target of the streaming product: 8 waves per SIMD (64 VGPRs),
+// except the FP32 form that carries both the staged and the direct gathers
+// (16 values per thread of each), which needs a few more registers and runs
+// at 7 rather than spill to scratch.
+template <typename T, int STAGE>
+constexpr int stream_waves() { return (sizeof(T) == 4 && STAGE == 2) ? 7 : 8; }
+
 template <typename T, int MODE, int L, int STAGE>
-__global__ void __launch_bounds__(spmv_threads<T>()) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(spmv_threads<T>())
+__attribute__((amdgpu_waves_per_eu(stream_waves<T, STAGE>(), 8)))
 spmv_stream_kernel(SpmvArgs<T> a) {
     if (stopped(a.stop)) return;
     constexpr int CAP = spmv_cap<T>();
