@@ -396,6 +396,7 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
         lat = [0.0] * len(reqs)
         status = [0] * len(reqs)
         rids = [None] * len(reqs)
+        t_sub = [0.0] * len(reqs)
         ready = [threading.Event() for _ in reqs]
 
         def waiter():
@@ -425,31 +426,42 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
                         time.sleep(delay)
                 rids[i] = srv.submit(pid, b)
                 t_last = time.perf_counter()
+                t_sub[i] = t_last - t0
                 ready[i].set()
         finally:
             for e in ready:                # release the waiter whatever happened
                 e.set()
             th.join()
-        return time.perf_counter() - t0, t_last - t0, np.array(lat), status
+        return time.perf_counter() - t0, t_last - t0, np.array(lat), status, np.array(t_sub)
 
     def open_loop(rate):
         reps = max(1, int(np.ceil(min_window_s * rate / len(trace))))
         reqs = trace * reps
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
-        t_all, t_arr, lat, st = run(reqs, arrivals)
+        t_all, t_arr, lat, st, t_sub = run(reqs, arrivals)
         q = max(1, len(reqs) // 4)
+        # steady window: the last three quarters of the arrival span, where
+        # completions (submission + latency) are counted against arrivals;
+        # served_rate over the whole run also counts the drain after the
+        # last arrival
+        a, b = 0.25 * t_arr, t_arr
+        done_t = t_sub + lat * 1e-3
+        w_arr = int(np.count_nonzero((t_sub >= a) & (t_sub <= b)))
+        w_done = int(np.count_nonzero((done_t >= a) & (done_t <= b)))
         return {"offered_rate": round(rate, 2), "requests": len(reqs),
                 "arrival_rate": round(len(reqs) / max(t_arr, 1e-9), 2),
                 "served_rate": round(len(reqs) / t_all, 2),
+                "window_arrival_rate": round(w_arr / max(b - a, 1e-9), 2),
+                "window_served_rate": round(w_done / max(b - a, 1e-9), 2),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "first_quarter_p50_ms": round(float(np.median(lat[:q])), 3),
                 "last_quarter_p50_ms": round(float(np.median(lat[-q:])), 3)}, st
 
     try:
-        t_warm, _, _, _ = run(trace, None)       # warm-up: every hierarchy set up once
+        t_warm = run(trace, None)[0]             # warm-up: every hierarchy set up once
         log(f"serving: warm-up pass {t_warm:.2f} s ({len(problems)} hierarchies)")
-        t_closed, _, lat_closed, st_closed = run(trace, None)
+        t_closed, _, lat_closed, st_closed, _ = run(trace, None)
         sat = len(trace) / t_closed
         log(f"serving: closed loop {sat:.1f} solves/s")
         o7, st7 = open_loop(0.7 * sat)
@@ -564,7 +576,7 @@ def main():
     alg_bytes = cheb_step_algorithmic_bytes(nnz0, n0, 8)
     iso_ms, fmt_bytes = solver.time_kernel("cheb_step", level=0, reps=50)
     achieved = alg_bytes / (step_ms * 1e-3) / 1e9
-    stream_gbs = read_bandwidth(1 << 30, 10)
+    stream_gbs = read_bandwidth(4 << 30, 10)
     traffic = traffic_entry(args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

@@ -309,8 +309,9 @@ int giamg_profile_read(giamg_handle h, giamg_profile* out, int32_t reset);
 
 /*
  * giamg_read_bandwidth -- attainable HBM read bandwidth of the current
- * device: a streaming kernel reads a fresh buffer of `bytes` bytes (16-byte
- * non-temporal loads, one partial sum written per block) `reps` times; *gbs
+ * device: a streaming kernel reads a fresh, zeroed buffer of `bytes` bytes
+ * (contiguous 64 KB per block, 16-byte non-temporal loads, nothing written
+ * for a zero buffer) once untimed and then `reps` times; *gbs
  * receives the median over the launches of bytes / duration (HIP events
  * recorded by the dispatches).  The buffer comes from the registered
  * allocator and is released before returning.  bytes >= 1 MiB, reps in
@@ -473,6 +474,8 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
  *   GIAMG_KERNEL_SPMV       plain y = A_l v
  *   GIAMG_KERNEL_RESTRICT   y = R_l v
  *   GIAMG_KERNEL_PROLONG    x += P_l v
+ *   GIAMG_KERNEL_CG_PRODUCT q = A_l p with per-block partial sums of p.q
+ *                           (the outer CG's product, FP64)
  * ms receives the mean duration of one launch, bytes its algorithmic HBM
  * bytes (values, column ids or 16-bit slots and run tables, row pointers,
  * the gathered vector once, row-local vectors).
@@ -481,6 +484,7 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
 #define GIAMG_KERNEL_SPMV      1
 #define GIAMG_KERNEL_RESTRICT  2
 #define GIAMG_KERNEL_PROLONG   3
+#define GIAMG_KERNEL_CG_PRODUCT 4
 int giamg_time_kernel(giamg_handle h, int32_t kernel, int32_t level, int32_t reps,
                       double* ms, double* bytes);
 

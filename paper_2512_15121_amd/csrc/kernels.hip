@@ -217,29 +217,45 @@ __device__ __forceinline__ void epilogue_store(const SpmvArgs<T>& a, int64_t row
 template <int MODE>
 constexpr bool has_partials() { return MODE == SPMV_DOT || MODE == SPMV_RINIT; }
 
-// Fixed-order block sums of two values per thread, returned in a and b to
-// every thread: each wave adds its lanes by a butterfly (every lane ends with
-// the same bits, addition being commutative), then every thread adds the
-// waves' sums in wave order.  One barrier; red holds 2 * NT / WAVE doubles
-// and may be reused after a further barrier.
-template <int NT>
-__device__ __forceinline__ void block_sum2(double* red, int tid, double& a, double& b) {
+// Butterfly sum over the lanes of a wave with partners 32, 16, 8, 4, 2, 1 in
+// that order (the order of group_sum<WAVE>): the two steps across 16-lane
+// rows by LDS permutes, the four inside each row by DPP rotations
+// (row_group_sum<16>).  Every lane ends with the same bits as
+// group_sum<WAVE> gives.
+__device__ __forceinline__ double wave_butterfly(double v) {
+    v += __shfl_xor(v, 32, WAVE);
+    v += __shfl_xor(v, 16, WAVE);
+    return row_group_sum<16>(v);
+}
+
+// Fixed-order block sums of NV (1 or 2) values per thread, valid in thread 0
+// only: each wave adds its lanes by the butterfly above, then thread 0 adds
+// the waves' sums in wave order.  One barrier; red holds 2 * NT / WAVE
+// doubles and may be reused after a further barrier.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum_to0(double* red, int tid, double& a, double& b) {
+    static_assert(NV == 1 || NV == 2, "one or two sums");
     constexpr int NW = NT / WAVE;
-    a = group_sum<WAVE>(a);
-    b = group_sum<WAVE>(b);
+    a = wave_butterfly(a);
+    if constexpr (NV == 2) b = wave_butterfly(b);
     if (tid % WAVE == 0) {
         red[tid / WAVE] = a;
-        red[NW + tid / WAVE] = b;
+        if constexpr (NV == 2) red[NW + tid / WAVE] = b;
     }
     __syncthreads();
-    a = red[0];
-    b = red[NW];
+    if (tid == 0) {
+        a = red[0];
+        if constexpr (NV == 2) b = red[NW];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) {
-        a += red[w];
-        b += red[NW + w];
+        for (int w = 1; w < NW; ++w) {
+            a += red[w];
+            if constexpr (NV == 2) b += red[NW + w];
+        }
     }
 }
+
+template <int MODE>
+constexpr int n_partials() { return MODE == SPMV_RINIT ? 2 : 1; }
 
 // Forms of step 1 of the streaming product (below).  Loads that depend on
 // earlier loads are unconditional, from clamped (always valid) indices, and
@@ -417,7 +433,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             }
             if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
             double s = (double)(acc0 + acc1), unused = 0.0;
-            block_sum2<NT>(red, tid, s, unused);
+            block_sum_to0<NT, 1>(red, tid, s, unused);
             const T y = (T)s;
             if (tid == 0) {
                 epilogue_store<T, MODE>(a, r0, y, in, dot, dot2);
@@ -468,7 +484,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     // 3. row epilogues
     if (own) epilogue_store<T, MODE>(a, r0 + tid, rowsum[tid], in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
-        block_sum2<NT>(red, tid, dot, dot2);
+        block_sum_to0<NT, n_partials<MODE>()>(red, tid, dot, dot2);
         if (tid == 0) {
             a.partial[lb] = dot;
             if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
@@ -586,7 +602,7 @@ spmv_group_kernel(SpmvArgs<T> a) {
     __syncthreads();
     if (tid < R) epilogue_store<T, MODE>(a, row, rowsum[tid], in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
-        block_sum2<GROUP_THREADS>(red, tid, dot, dot2);
+        block_sum_to0<GROUP_THREADS, n_partials<MODE>()>(red, tid, dot, dot2);
         if (tid == 0) {
             a.partial[lb] = dot;
             if (MODE == SPMV_RINIT) a.partial[a.nblk + lb] = dot2;
@@ -642,7 +658,7 @@ __global__ void __launch_bounds__(LEAN_THREADS) spmv_lean_kernel(SpmvArgs<T> a) 
     if (live && gl == 0) epilogue_store<T, MODE>(a, row, acc, in, dot, dot2);
     if constexpr (has_partials<MODE>()) {
         __shared__ double red[2 * LEAN_THREADS / WAVE];
-        block_sum2<LEAN_THREADS>(red, tid, dot, dot2);
+        block_sum_to0<LEAN_THREADS, n_partials<MODE>()>(red, tid, dot, dot2);
         if (tid == 0) {
             a.partial[blockIdx.x] = dot;
             if (MODE == SPMV_RINIT) a.partial[a.nblk + blockIdx.x] = dot2;
@@ -930,8 +946,8 @@ void launch_spmv(int mode, const SpmvArgs<T>& args, hipStream_t s) {
 // Attainable read bandwidth: a streaming read shaped like the products'
 // value stream -- each block of 512 threads reads one contiguous 64 KB chunk
 // with all eight 16-byte non-temporal loads per thread issued at once, blocks
-// remapped so every XCD streams a contiguous range -- and one partial sum
-// per block written so the loads are live.
+// remapped so every XCD streams a contiguous range -- over a zeroed buffer,
+// with a store that only a nonzero sum would make.
 // ---------------------------------------------------------------------------
 typedef double double2_v __attribute__((ext_vector_type(2)));
 constexpr int RS_THREADS = 512, RS_LOADS = 8;
@@ -940,24 +956,18 @@ __global__ void __launch_bounds__(RS_THREADS) read_stream_kernel(const double2_v
                                                                  double* __restrict__ out) {
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t base = lb * (int64_t)(RS_THREADS * RS_LOADS);
-    double acc = 0.0;
     double2_v v[RS_LOADS];
 #pragma unroll
     for (int k = 0; k < RS_LOADS; ++k) {
         const int64_t i = min(base + k * RS_THREADS + threadIdx.x, n2 - 1);
         v[k] = ldnt(p + i);
     }
+    double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < RS_LOADS; ++k) acc += v[k].x + v[k].y;
-    __shared__ double red[RS_THREADS / WAVE];
-    acc = wave_sum(acc);
-    if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < RS_THREADS / WAVE; ++w) t += red[w];
-        out[lb] = t;
-    }
+    // the buffer holds zeros: the store never happens, but the compiler
+    // cannot drop the loads, and no reduction lengthens the block
+    if (acc != 0.0) out[lb] = acc;
 }
 
 void read_bandwidth(int64_t bytes, int reps, double* gbs) {
@@ -1174,7 +1184,7 @@ int64_t vec_blocks(int64_t n) {
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     constexpr int NW = NT / WAVE;
-    v = group_sum<WAVE>(v);
+    v = wave_butterfly(v);
     if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = v;
     __syncthreads();
     double r = sh[0];

@@ -1212,9 +1212,15 @@ void time_kernel_t(Handle& H, int kernel, size_t l, int reps, double* ms, double
     GIAMG_REQUIRE(kernel == GIAMG_KERNEL_SPMV || !last, "no transfer or smoother on the coarsest level");
     SpmvArgs<T> a;
     int mode = SPMV_PLAIN;
-    if (kernel == GIAMG_KERNEL_CHEB_STEP || kernel == GIAMG_KERNEL_SPMV) {
+    DevBuf<double> partial;
+    if (kernel == GIAMG_KERNEL_CHEB_STEP || kernel == GIAMG_KERNEL_SPMV || kernel == GIAMG_KERNEL_CG_PRODUCT) {
         a = args_A<T>(L);
         a.v = LV<T>::d0(L); a.y = LV<T>::d1(L);
+        if (kernel == GIAMG_KERNEL_CG_PRODUCT) {
+            mode = SPMV_DOT;
+            partial.alloc((size_t)std::max<int64_t>(a.nblk, 1));
+            a.partial = partial.get();
+        }
         if (kernel == GIAMG_KERNEL_CHEB_STEP) {
             const ChebCoef c = cheb_coef(H, L);
             mode = SPMV_CHEB_STEP;
@@ -1285,6 +1291,7 @@ void time_kernel(Handle& H, int kernel, int level, int reps, double* ms, double*
     GIAMG_REQUIRE(reps >= 1 && reps <= 100000, "reps must be in [1, 100000]");
     if (kernel & GIAMG_OP_FP32) {
         GIAMG_REQUIRE(H.opts.precision == GIAMG_PREC_MIXED, "FP32 operators exist only in mixed mode");
+        GIAMG_REQUIRE((kernel & ~GIAMG_OP_FP32) != GIAMG_KERNEL_CG_PRODUCT, "the CG product is FP64 only");
         time_kernel_t<float>(H, kernel & ~GIAMG_OP_FP32, level, reps, ms, bytes);
     } else {
         time_kernel_t<double>(H, kernel, level, reps, ms, bytes);

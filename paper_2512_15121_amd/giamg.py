@@ -198,7 +198,7 @@ _SIGNATURES = {
     "giamg_server_stats": (I32, [P, P]),
     "giamg_server_free": (None, [P]),
 }
-KERNEL = {"cheb_step": 0, "spmv": 1, "restrict": 2, "prolong": 3}
+KERNEL = {"cheb_step": 0, "spmv": 1, "restrict": 2, "prolong": 3, "cg_product": 4}
 
 
 def library() -> ctypes.CDLL:

@@ -753,6 +753,34 @@ def test_profile_counts_and_unchanged_results(torch_dev, precision):
     s.close()
 
 
+def test_kernel_timing_and_read_bandwidth(torch_dev):
+    """The measurement entry points: every kernel kind of giamg_time_kernel
+    runs on the fine level and reports a positive duration and its bytes
+    (the CG product in FP64 only), the solve is unchanged by them, and the
+    read-stream reference reports a positive rate."""
+    torch, dev = torch_dev
+    from paper_2512_15121_amd import giamg
+    name = "p4_6cube_cheb_sa"
+    m, H = _case(name)
+    b = _to(torch, dev, synth.normal_rhs(m.n_nodes, 12))
+    s = _solver(name, precision="mixed")
+    x0, i0 = s.solve(b, tol=1e-10)
+    n0, nnz0 = s.level(0)["rows"], s.level(0)["nnz_A"]
+    for kind in ("cheb_step", "spmv", "restrict", "prolong", "cg_product"):
+        ms, by = s.time_kernel(kind, level=0, reps=3)
+        assert ms > 0 and by > 0, kind
+        if kind in ("cheb_step", "spmv", "cg_product"):
+            assert by >= 8 * nnz0 + 8 * n0, kind
+    ms, by = s.time_kernel("cheb_step", level=0, reps=3, fp32=True)
+    assert ms > 0 and 4 * nnz0 <= by
+    with pytest.raises(giamg.GiamgError):
+        s.time_kernel("cg_product", level=0, reps=3, fp32=True)
+    x1, i1 = s.solve(b, tol=1e-10)
+    assert torch.equal(x1, x0) and i1.iters == i0.iters
+    s.close()
+    assert giamg.read_bandwidth(1 << 24, 3) > 0
+
+
 def test_jacobi_pcg_baseline_parity(torch_dev):
     """The diagonally preconditioned CG baseline of the paper's comparison
     (Section 3.2): one level, against the oracle's Jacobi-PCG.  A run of a
