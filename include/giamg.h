@@ -64,6 +64,9 @@ extern "C" {
 #define GIAMG_PRECOND_VCYCLE     0  /* one GIAMG V-cycle per CG iteration (the method) */
 #define GIAMG_PRECOND_JACOBI     1  /* the inverse diagonal: the diagonally preconditioned CG
                                        the paper compares against (Section 3.2) */
+#define GIAMG_ASSEMBLY_AUTO      0  /* fine operator assembled on the device where it fits */
+#define GIAMG_ASSEMBLY_DEVICE    1  /* on the device, or GIAMG_ENOTSUP */
+#define GIAMG_ASSEMBLY_HOST      2  /* on the host, then copied to the device */
 #define GIAMG_BASIS_NODAL        0  /* tensor Lagrange on Gauss-Lobatto-Legendre points */
 #define GIAMG_BASIS_MODAL        1  /* hierarchical modal basis of the paper's appendix:
                                        1-D modes (1-a)/2, (1+a)/2, then bubbles
@@ -138,7 +141,15 @@ typedef struct giamg_opts {
                               giamg_solve and giamg_solve_noalloc only (batched solves,
                               sessions and the V-cycle steps of giamg_apply return
                               GIAMG_ENOTSUP) */
-    int32_t  pad3;
+    int32_t  assembly;     /* GIAMG_ASSEMBLY_*: where the fine operator A = K + lambda M is
+                              assembled (Section 3.1's element integrals).  AUTO (the
+                              default): on the device when every row's candidate columns
+                              and the element-row work fit the kernels' LDS lists (p <= 8
+                              on hexahedral meshes with at most 8 elements per node), on
+                              the host otherwise; DEVICE: on the device or GIAMG_ENOTSUP;
+                              HOST: on the host (C++ threads), then copied.  Same pattern
+                              and entry order; the element integrals are contracted in
+                              another order, so values agree to rounding */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -334,7 +345,7 @@ typedef struct giamg_level_desc {
     int32_t kind;        /* GIAMG_LEVEL_* */
     int32_t order;       /* polynomial order of the level (1 for h-levels) */
     int32_t coarsest;    /* 1 on the last level */
-    int32_t pad;
+    int32_t device_assembly;  /* fine level: 1 if A was assembled on the device; else 0 */
     int64_t rows;        /* rows of A on this level */
     int64_t nnz_A, nnz_P, nnz_R;   /* P/R are 0 on the coarsest level */
     double  lam_hat;     /* lambda_max(D^-1 A) estimate (0 on the coarsest level) */

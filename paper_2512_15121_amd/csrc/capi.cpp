@@ -122,6 +122,9 @@ void check_setup_args(const double* coords, int64_t n_nodes, const int32_t* l2g,
                   "unknown preconditioner");
     GIAMG_REQUIRE(o.preconditioner == GIAMG_PRECOND_VCYCLE || o.precision == GIAMG_PREC_FP64,
                   "the Jacobi preconditioner runs in FP64 only (precision must be FP64)");
+    GIAMG_REQUIRE(o.assembly == GIAMG_ASSEMBLY_AUTO || o.assembly == GIAMG_ASSEMBLY_DEVICE ||
+                      o.assembly == GIAMG_ASSEMBLY_HOST,
+                  "unknown assembly mode");
     {
         int prev = p;
         for (int i = 0; i < 8 && o.schedule[i] != 0; ++i) {
@@ -211,7 +214,7 @@ void giamg_default_opts(giamg_opts* o) {
     o->pad2 = 0;
     o->theta = 0.0;
     o->preconditioner = GIAMG_PRECOND_VCYCLE;
-    o->pad3 = 0;
+    o->assembly = GIAMG_ASSEMBLY_AUTO;
 }
 
 int giamg_setup(const double* coords, int64_t n_nodes, const int32_t* l2g, int64_t n_elem,
@@ -320,7 +323,7 @@ int giamg_level_describe(giamg_handle h, int32_t level, giamg_level_desc* out) {
         out->kind = L.kind;
         out->order = L.order;
         out->coarsest = level + 1 == (int)h->h.levels.size();
-        out->pad = 0;
+        out->device_assembly = L.device_assembled ? 1 : 0;
         out->rows = L.n;
         out->nnz_A = L.A.nnz;
         out->nnz_P = L.P.nnz;

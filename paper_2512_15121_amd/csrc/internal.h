@@ -183,6 +183,7 @@ struct BatchDeleter {
 struct Level {
     int kind = GIAMG_LEVEL_P;
     int order = 1;
+    bool device_assembled = false;  // fine level: A built by assemble_fine_device
     int64_t n = 0;
     DevCSR A, P, R;                // P, R empty on the coarsest level
     DevCSR AP;                     // A P (rows of this level, columns of the next), kept
@@ -264,6 +265,24 @@ void element_corners(const double* coords, const int32_t* l2g, int64_t n_elem, i
 HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
                       int p, int64_t n_nodes, double lambda,
                       const std::vector<uint8_t>& constrained, int basis);
+// 1-D tables of the element integrals: L[i][q], D[i][q] (the p + 1 modes or
+// GLL Lagrange functions and their derivatives at the p + 2 Gauss points
+// g[q], weights w[q]).
+void reference_tables(int p, int basis, std::vector<double>& L, std::vector<double>& D,
+                      std::vector<double>& g, std::vector<double>& w);
+// Node -> (element, local index) lists, elements ascending within a node:
+// entries nstart[i] .. nstart[i + 1] - 1 of nel / nloc.  Throws GIAMG_EINVAL
+// for a node of no element.
+void node_elements(const int32_t* l2g, int64_t n_elem, int nl, int64_t n_nodes, std::vector<int64_t>& nstart,
+                   std::vector<int32_t>& nel, std::vector<int32_t>& nloc);
+struct DevCSR;
+// The same operator as assemble_fine (same pattern and entries, each entry
+// summed over its elements in ascending order), built on the device into d
+// (rows, columns, values and the FP64 row blocks).  Throws GIAMG_ENOTSUP when
+// a row's elements hold more candidate columns than the kernels' LDS lists.
+void assemble_fine_device(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem, int p,
+                          int64_t n_nodes, double lambda, const std::vector<uint8_t>& constrained, int basis,
+                          DevCSR& d, hipStream_t s);
 void quadrature_points(const std::vector<double>& corners, int64_t n_elem, int p, double* xq);
 void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t n_elem,
                  int p, int64_t n_nodes, const std::vector<uint8_t>& constrained,

@@ -411,6 +411,36 @@ bool element_matrix(const RefTables& t, const double* X, double lambda, double* 
 
 }  // namespace
 
+void reference_tables(int p, int basis, std::vector<double>& L, std::vector<double>& D,
+                      std::vector<double>& g, std::vector<double>& w) {
+    RefTables t = make_tables(p, basis);
+    L = t.L;
+    D = t.D;
+    g = t.g;
+    w = t.wg;
+}
+
+void node_elements(const int32_t* l2g, int64_t n_elem, int nl, int64_t n_nodes, std::vector<int64_t>& nstart,
+                   std::vector<int32_t>& nel, std::vector<int32_t>& nloc) {
+    GIAMG_REQUIRE(n_elem < (int64_t(1) << 31), "too many elements");
+    nstart.assign(n_nodes + 1, 0);
+    for (int64_t i = 0; i < n_elem * nl; ++i) nstart[l2g[i] + 1]++;
+    for (int64_t i = 0; i < n_nodes; ++i) nstart[i + 1] += nstart[i];
+    nel.resize(nstart.back());
+    nloc.resize(nstart.back());
+    std::vector<int64_t> fill(nstart.begin(), nstart.end() - 1);
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int a = 0; a < nl; ++a) {
+            const int32_t g = l2g[e * nl + a];
+            nel[fill[g]] = (int32_t)e;
+            nloc[fill[g]] = a;
+            fill[g]++;
+        }
+    for (int64_t i = 0; i < n_nodes; ++i)
+        if (nstart[i] == nstart[i + 1])
+            throw Error(GIAMG_EINVAL, "node " + std::to_string(i) + " belongs to no element");
+}
+
 // ---------------------------------------------------------------------------
 // fine-level assembly: symbolic pattern, element matrices, gather by rows
 // ---------------------------------------------------------------------------
@@ -419,24 +449,9 @@ HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, in
                       const std::vector<uint8_t>& cons, int basis) {
     const int nl = (p + 1) * (p + 1) * (p + 1);
     // node -> (element, local) lists, elements ascending
-    std::vector<int64_t> nstart(n_nodes + 1, 0);
-    for (int64_t i = 0; i < n_elem * nl; ++i) nstart[l2g[i] + 1]++;
-    for (int64_t i = 0; i < n_nodes; ++i) nstart[i + 1] += nstart[i];
-    std::vector<int64_t> nel(nstart.back());
-    std::vector<int32_t> nloc(nstart.back());
-    {
-        std::vector<int64_t> fill(nstart.begin(), nstart.end() - 1);
-        for (int64_t e = 0; e < n_elem; ++e)
-            for (int a = 0; a < nl; ++a) {
-                int32_t g = l2g[e * nl + a];
-                nel[fill[g]] = e;
-                nloc[fill[g]] = a;
-                fill[g]++;
-            }
-    }
-    for (int64_t i = 0; i < n_nodes; ++i)
-        if (nstart[i] == nstart[i + 1])
-            throw Error(GIAMG_EINVAL, "node " + std::to_string(i) + " belongs to no element");
+    std::vector<int64_t> nstart;
+    std::vector<int32_t> nel, nloc;
+    node_elements(l2g, n_elem, nl, n_nodes, nstart, nel, nloc);
 
     HostCSR A;
     A.nrows = A.ncols = n_nodes;
@@ -450,7 +465,7 @@ HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, in
             if (cons[r]) { counts[r] = 1; continue; }
             int64_t c = 0;
             for (int64_t s = nstart[r]; s < nstart[r + 1]; ++s) {
-                const int32_t* g = l2g + nel[s] * nl;
+                const int32_t* g = l2g + (int64_t)nel[s] * nl;
                 for (int a = 0; a < nl; ++a)
                     if (!cons[g[a]] && mark[g[a]] != (int32_t)r) { mark[g[a]] = (int32_t)r; ++c; }
             }
@@ -482,7 +497,7 @@ HostCSR assemble_fine(const std::vector<double>& corners, const int32_t* l2g, in
             if (cons[r]) { A.ci[o] = (int32_t)r; A.val[o] = 1.0; continue; }
             int64_t c = 0;
             for (int64_t s = nstart[r]; s < nstart[r + 1]; ++s) {
-                const int32_t* g = l2g + nel[s] * nl;
+                const int32_t* g = l2g + (int64_t)nel[s] * nl;
                 for (int a = 0; a < nl; ++a)
                     if (!cons[g[a]] && pos[g[a]] != -2) { pos[g[a]] = -2; A.ci[o + c++] = g[a]; }
             }

@@ -309,9 +309,6 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
     GIAMG_REQUIRE(H.lambda > 0.0 || ncons > 0, "lambda = 0 needs at least one constrained node");
     element_corners(coords, l2g, ne, H.porder, H.corners, o.basis);
     H.l2g.assign(l2g, l2g + ne * (int64_t)(H.porder + 1) * (H.porder + 1) * (H.porder + 1));
-    HostCSR A0 = assemble_fine(H.corners, l2g, ne, H.porder, n, H.lambda, H.constrained, o.basis);
-    H.setup_ms[0] = ms_since(t0);
-
     H.levels.clear();
     H.levels.emplace_back();
     {
@@ -320,9 +317,23 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         L.order = H.porder;
         L.n = n;
         L.l2g = H.l2g;
-        upload_csr(A0, L.A, H.stream, false);
+        if (o.assembly != GIAMG_ASSEMBLY_HOST) {
+            try {
+                assemble_fine_device(H.corners, l2g, ne, H.porder, n, H.lambda, H.constrained, o.basis, L.A,
+                                     H.stream);
+                L.device_assembled = true;
+            } catch (const Error& e) {
+                // AUTO: meshes whose rows outgrow the kernels' LDS lists go to the host
+                if (e.code != GIAMG_ENOTSUP || o.assembly == GIAMG_ASSEMBLY_DEVICE) throw;
+                L.A = DevCSR();
+            }
+        }
+        if (!L.device_assembled) {
+            HostCSR A0 = assemble_fine(H.corners, l2g, ne, H.porder, n, H.lambda, H.constrained, o.basis);
+            upload_csr(A0, L.A, H.stream, false);
+        }
     }
-    A0 = HostCSR();
+    H.setup_ms[0] = ms_since(t0);
     // p-levels
     std::vector<uint8_t> free_mask(n);
     // keep_boundary: constrained fine nodes pass to the coarse levels too

@@ -22,6 +22,7 @@ LEVEL_KIND = {0: "p", 1: "h"}
 MAT = {"A": 0, "P": 1, "R": 2, "AP": 3}
 BASIS = {"nodal": 0, "modal": 1}
 PRECONDITIONER = {"vcycle": 0, "jacobi": 1}
+ASSEMBLY = {"auto": 0, "device": 1, "host": 2}
 BATCH_KERNEL = {"auto": 0, "lanes": 1, "wave": 2, "group": 3}
 OP = {"spmv": 0, "residual": 1, "restrict": 2, "prolong_add": 3, "presmooth": 4,
       "postsmooth": 5, "coarse": 6, "vcycle": 7}
@@ -47,7 +48,7 @@ class _Opts(ctypes.Structure):
                 ("row_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("lean_max_nnz", ctypes.c_int64), ("keep_boundary", ctypes.c_int32),
                 ("pad2", ctypes.c_int32), ("theta", ctypes.c_double),
-                ("preconditioner", ctypes.c_int32), ("pad3", ctypes.c_int32)]
+                ("preconditioner", ctypes.c_int32), ("assembly", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -80,7 +81,7 @@ class _Profile(ctypes.Structure):
 
 class _LevelDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("coarsest", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("coarsest", ctypes.c_int32), ("device_assembly", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("nnz_A", ctypes.c_int64),
                 ("nnz_P", ctypes.c_int64), ("nnz_R", ctypes.c_int64),
                 ("lam_hat", ctypes.c_double), ("nnz_AP", ctypes.c_int64),
@@ -114,6 +115,7 @@ class Options:
     keep_boundary: bool = False     # coarse p-levels keep the constrained nodes
     theta: float = 0.0              # strength threshold of the aggregation graph
     preconditioner: str = "vcycle"  # or "jacobi": the diagonally preconditioned CG baseline
+    assembly: str = "auto"          # fine operator built on the device where it fits, or "device", "host"
 
     def _c(self) -> _Opts:
         d = asdict(self)
@@ -130,7 +132,7 @@ class Options:
         d["pad2"] = 0
         d["keep_boundary"] = int(d["keep_boundary"])
         d["preconditioner"] = PRECONDITIONER[d["preconditioner"]]
-        d["pad3"] = 0
+        d["assembly"] = ASSEMBLY[d["assembly"]]
         d["smoother"] = SMOOTHER[d["smoother"]]
         d["bc"] = BC[d["bc"]]
         d["precision"] = PRECISION[d["precision"]]
@@ -390,7 +392,7 @@ class Solver:
                 "rows": d.rows, "nnz_A": d.nnz_A, "nnz_P": d.nnz_P, "nnz_R": d.nnz_R,
                 "nnz_AP": d.nnz_AP, "lam_hat": d.lam_hat, "staged_nnz_A": d.staged_nnz_A,
                 "runs_A": d.runs_A, "groups_A": d.groups_A, "group_entries_A": d.group_entries_A,
-                "lean_A": bool(d.lean_A)}
+                "lean_A": bool(d.lean_A), "device_assembly": bool(d.device_assembly)}
 
     def level_csr(self, l, which="A"):
         d = self.level(l)

@@ -100,7 +100,7 @@ def test_option_constants_match_header():
     tables = {"GIAMG_BATCH_": giamg.BATCH_KERNEL, "GIAMG_BASIS_": giamg.BASIS,
               "GIAMG_BC_": giamg.BC, "GIAMG_PREC_": giamg.PRECISION,
               "GIAMG_SMOOTHER_": giamg.SMOOTHER, "GIAMG_PRECOND_": giamg.PRECONDITIONER,
-              "GIAMG_KERNEL_": giamg.KERNEL}
+              "GIAMG_KERNEL_": giamg.KERNEL, "GIAMG_ASSEMBLY_": giamg.ASSEMBLY}
     for prefix, table in tables.items():
         for name, value in table.items():
             assert defs[prefix + name.upper()] == value, prefix + name
