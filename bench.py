@@ -412,8 +412,9 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
                 except Exception as e:      # recorded, reported as a failed request
                     status[i] = getattr(e, "code", -1)
                     log(f"serving: request {i} failed: {e}")
-                if (i + 1) % 250 == 0:
-                    log(f"serving: {i + 1} of {len(reqs)} requests done")
+                if (i + 1) % 100 == 0:
+                    log(f"serving: {i + 1} of {len(reqs)} requests done "
+                        f"({time.perf_counter() - t0:.1f} s)")
         th = threading.Thread(target=waiter, daemon=True)
         th.start()
         t0 = time.perf_counter()
@@ -506,7 +507,7 @@ def main():
     ap.add_argument("--study", action="store_true",
                     help="only run the parameter studies at p = 5 (Chebyshev degree x "
                          "p-schedule x basis, with breakdowns) and print them as one JSON line")
-    ap.add_argument("--serving", default="small", choices=["small", "medium", "full", "off"])
+    ap.add_argument("--serving", default="small", choices=["small", "medium", "large", "full", "off"])
     ap.add_argument("--serving-slots", type=int, default=8,
                     help="right-hand sides batched per hierarchy in the serving leg")
     ap.add_argument("--serving-chunk", type=int, default=2,
@@ -665,11 +666,17 @@ def main():
 
 def serving(torch, Server, Options, size, slots=8, chunk=2):
     """The serving trace of the chosen size (small: 200 requests, n <= 8,
-    p <= 4; medium: 2000 requests, n <= 16, p <= 6; full: 2000 requests,
-    n <= 24, p <= 6, hierarchies of up to ~30 GB, 250 GB of HBM budget)."""
+    p <= 4; medium: 2000 requests, n <= 16, p <= 6, ~78 GB of hierarchies;
+    large: 2000 requests, n <= 20, p <= 6, ~187 GB, the largest n range
+    whose hierarchies all fit one MI355X's HBM; full: n <= 24, ~381 GB of
+    hierarchies for a 250 GB budget, so the cache evicts and sets
+    hierarchies up again)."""
     try:
         if size == "full":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24), p_range=(2, 6),
+                               budget=250e9, slots=slots, chunk=chunk)
+        if size == "large":
+            return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 20), p_range=(2, 6),
                                budget=250e9, slots=slots, chunk=chunk)
         if size == "medium":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 16), p_range=(2, 6),

@@ -764,7 +764,12 @@ double spmm_bytes(const DevCSR& M, int k, double vb, double rowvecs) {
            rowvecs * vb * (double)M.nrows * k;
 }
 
-// Group the rows of M by identical column lists (host pass over the pattern).
+// Group the rows of M by identical column lists (host pass over the
+// pattern), groups in the order of their first rows.  (Groups in Z-order of
+// their elements, with each XCD taking a contiguous range of them, raised
+// the L2 hit rate of the block products from 0.55 to 0.88 and cut their L2
+// misses fourfold, but measured 2-3 % slower: the products are not bound by
+// the misses.)
 RowGroups build_row_groups(const DevCSR& M, hipStream_t s) {
     RowGroups G;
     const int64_t n = M.nrows;

@@ -5,6 +5,13 @@
 
 namespace giamg {
 
+// Hardware dispatches block b to XCD (b mod 8).  Logical block ids are
+// reassigned so that each XCD receives one contiguous range of G blocks.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+    int64_t x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Fused epilogues of the CSR product y_i = sum_j A_ij v_j, applied per row.
 enum SpmvMode : int {
     SPMV_PLAIN = 0,      // y = A v

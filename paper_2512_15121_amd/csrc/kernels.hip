@@ -37,13 +37,6 @@ StopScope::~StopScope() { g_stop = prev_; }
 
 __device__ __forceinline__ bool stopped(const int* stop) { return stop != nullptr && *stop != 0; }
 
-// Hardware dispatches block b to XCD (b mod 8).  Logical block ids are
-// reassigned so that each XCD receives one contiguous range.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
-    int64_t x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
