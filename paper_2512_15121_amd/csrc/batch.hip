@@ -31,6 +31,7 @@ constexpr int BW = 64;              // wavefront width
 constexpr int DOT_ROWS = 256;       // rows per column-dot block (fixed)
 constexpr int MAX_K = 1024;
 constexpr int CHUNK = 4;            // graph replays between host checks
+constexpr int GROUP_MAX = 8;        // rows per row group of the group kernel
 
 template <typename T>
 struct SpmmArgs {
@@ -164,9 +165,11 @@ __global__ void __launch_bounds__(WPB* BW) spmm_wave_kernel(SpmmArgs<T> a) {
 
 // The G rows of one group share their column list; the wave reads each
 // block-vector row v[c][tile] once and applies it to all G rows.  Row i of
-// the group sums over its nonzeros in CSR order, as in spmm_kernel.
+// the group sums over its nonzeros in CSR order, as in spmm_kernel.  FP64
+// form: each lane loads one value per row of a 64-entry chunk and the wave
+// hands them out by readlane.
 template <typename T, int MODE, int G>
-__device__ __forceinline__ void group_rows(const SpmmArgs<T>& a, int32_t row_lane, int64_t start_lane,
+__device__ __forceinline__ void group_rows_readlane(const SpmmArgs<T>& a, int32_t row_lane, int64_t start_lane,
                                            int lane, int64_t col, int64_t lc) {
     constexpr int U = G >= 4 ? 4 : 8;   // gathers in flight per wave
     const int64_t k = a.k;
@@ -215,6 +218,67 @@ __device__ __forceinline__ void group_rows(const SpmmArgs<T>& a, int32_t row_lan
     }
 }
 
+// FP32 form of the same: the rows' values come in chunks of 64 per row by
+// coalesced loads into the wave's LDS area wv ([GROUP_MAX][64]) and enter the
+// multiply-adds by uniform-address (broadcast) LDS reads, four values per
+// read, instead of one readlane per value (FP32 Chebyshev step 209 -> 185 us,
+// residual 186 -> 157 us at 20^3 p = 3, k = 64; in FP64 the values held in
+// flight take 104 VGPRs and the readlane form stays faster).
+template <typename T, int MODE, int G>
+__device__ __forceinline__ void group_rows_lds(const SpmmArgs<T>& a, int32_t row_lane, int64_t start_lane,
+                                           int lane, int64_t col, int64_t lc, T* wv) {
+    constexpr int U = G >= 4 ? 4 : 8;   // gathers in flight per wave
+    const int64_t k = a.k;
+    int64_t r[G], st[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        r[i] = __builtin_amdgcn_readlane(row_lane, i);
+        const int lo = __builtin_amdgcn_readlane((int)start_lane, i);
+        const int hi = __builtin_amdgcn_readlane((int)(start_lane >> 32), i);
+        st[i] = ((int64_t)hi << 32) | (uint32_t)lo;
+    }
+    const int64_t m = a.rp[r[0] + 1] - st[0];
+    T acc[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) acc[i] = 0;
+    for (int64_t b = 0; b < m; b += BW) {
+        const int mb = (int)min((int64_t)BW, m - b);
+        const int li = lane < mb ? lane : mb - 1;
+        const int32_t cw = a.ci[st[0] + b + li];
+#pragma unroll
+        for (int i = 0; i < G; ++i) wv[i * BW + lane] = a.val[st[i] + b + li];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int t = 0;
+        for (; t + U <= mb; t += U) {
+            T xs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t c = __builtin_amdgcn_readlane(cw, t + u);
+                xs[u] = a.v[c * k + lc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < G; ++i) acc[i] += wv[i * BW + t + u] * xs[u];
+        }
+        for (; t < mb; ++t) {
+            const int64_t c = __builtin_amdgcn_readlane(cw, t);
+            const T x = a.v[c * k + lc];
+#pragma unroll
+            for (int i = 0; i < G; ++i) acc[i] += wv[i * BW + t] * x;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (col < k) {
+#pragma unroll
+        for (int i = 0; i < G; ++i) spmm_epilogue<T, MODE>(a, r[i], col, acc[i]);
+    }
+}
+
 // One wavefront per group of rows with identical column lists (at most
 // GROUP_MAX rows; a.gptr / a.grows list them), 64 columns per wave.
 template <typename T, int MODE, int WPB>
@@ -229,15 +293,30 @@ __global__ void __launch_bounds__(WPB* BW) spmm_group_kernel(SpmmArgs<T> a) {
     const int64_t start_lane = a.rp[row_lane];
     const int64_t col = (int64_t)blockIdx.y * BW + lane;
     const int64_t lc = col < a.k ? col : a.k - 1;
-    switch (g) {
-        case 1: group_rows<T, MODE, 1>(a, row_lane, start_lane, lane, col, lc); break;
-        case 2: group_rows<T, MODE, 2>(a, row_lane, start_lane, lane, col, lc); break;
-        case 3: group_rows<T, MODE, 3>(a, row_lane, start_lane, lane, col, lc); break;
-        case 4: group_rows<T, MODE, 4>(a, row_lane, start_lane, lane, col, lc); break;
-        case 5: group_rows<T, MODE, 5>(a, row_lane, start_lane, lane, col, lc); break;
-        case 6: group_rows<T, MODE, 6>(a, row_lane, start_lane, lane, col, lc); break;
-        case 7: group_rows<T, MODE, 7>(a, row_lane, start_lane, lane, col, lc); break;
-        default: group_rows<T, MODE, 8>(a, row_lane, start_lane, lane, col, lc); break;
+    if constexpr (sizeof(T) == 4) {
+        __shared__ T wvals[WPB][GROUP_MAX * BW];
+        T* wv = wvals[threadIdx.x / BW];
+        switch (g) {
+            case 1: group_rows_lds<T, MODE, 1>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            case 2: group_rows_lds<T, MODE, 2>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            case 3: group_rows_lds<T, MODE, 3>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            case 4: group_rows_lds<T, MODE, 4>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            case 5: group_rows_lds<T, MODE, 5>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            case 6: group_rows_lds<T, MODE, 6>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            case 7: group_rows_lds<T, MODE, 7>(a, row_lane, start_lane, lane, col, lc, wv); break;
+            default: group_rows_lds<T, MODE, 8>(a, row_lane, start_lane, lane, col, lc, wv); break;
+        }
+    } else {
+        switch (g) {
+            case 1: group_rows_readlane<T, MODE, 1>(a, row_lane, start_lane, lane, col, lc); break;
+            case 2: group_rows_readlane<T, MODE, 2>(a, row_lane, start_lane, lane, col, lc); break;
+            case 3: group_rows_readlane<T, MODE, 3>(a, row_lane, start_lane, lane, col, lc); break;
+            case 4: group_rows_readlane<T, MODE, 4>(a, row_lane, start_lane, lane, col, lc); break;
+            case 5: group_rows_readlane<T, MODE, 5>(a, row_lane, start_lane, lane, col, lc); break;
+            case 6: group_rows_readlane<T, MODE, 6>(a, row_lane, start_lane, lane, col, lc); break;
+            case 7: group_rows_readlane<T, MODE, 7>(a, row_lane, start_lane, lane, col, lc); break;
+            default: group_rows_readlane<T, MODE, 8>(a, row_lane, start_lane, lane, col, lc); break;
+        }
     }
 }
 
@@ -250,7 +329,6 @@ struct Tile { int kt, wpb, kind; };
 const Tile kTiles[] = {{64, 8, TILE_GROUP}, {64, 4, TILE_GROUP}, {64, 8, TILE_WAVE}, {64, 4, TILE_WAVE},
                        {64, 4, TILE_LANES}, {64, 8, TILE_LANES}, {64, 2, TILE_LANES}, {32, 4, TILE_LANES},
                        {32, 8, TILE_LANES}, {16, 4, TILE_LANES}, {16, 8, TILE_LANES}, {8, 8, TILE_LANES}};
-constexpr int GROUP_MAX = 8;
 
 template <typename T, int MODE>
 void launch_spmm_tile(const SpmmArgs<T>& a, Tile t, hipStream_t s) {
