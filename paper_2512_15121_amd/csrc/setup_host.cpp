@@ -642,53 +642,71 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
                 fill[g]++;
             }
     }
-    // rows: union over the node's elements, first occurrence kept
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(n_fine);
-    parallel_for(n_fine, 4096, [&](int64_t b, int64_t e) {
-        std::vector<int32_t> seen;
-        for (int64_t r = b; r < e; ++r) {
-            if (!is_free((int32_t)r)) continue;
-            auto& row = rows[r];
-            for (int64_t t = nstart[r]; t < nstart[r + 1]; ++t) {
-                int64_t el = nel[t];
-                int loc = nloc[t];
-                int i = loc / ((p + 1) * (p + 1)), j = (loc / (p + 1)) % (p + 1), k = loc % (p + 1);
-                for (int a = 0; a <= q; ++a) {
-                    double va = I1[i * (q + 1) + a];
-                    if (va == 0.0) continue;
-                    for (int bb = 0; bb <= q; ++bb) {
-                        double vb = I1[j * (q + 1) + bb];
-                        if (vb == 0.0) continue;
-                        for (int c = 0; c <= q; ++c) {
-                            double vc = I1[k * (q + 1) + c];
-                            if (vc == 0.0) continue;
-                            int32_t gc = l2g_next[el * ncl + lidx(q, a, bb, c)];
-                            if (gc < 0) continue;
-                            bool dup = false;
-                            for (auto& pr : row)
-                                if (pr.first == gc) { dup = true; break; }
-                            if (!dup) row.emplace_back(gc, va * vb * vc);
-                        }
+    // Row r of P: the union over the node's elements (ascending) of the
+    // coarse nodes with a nonzero interpolation weight, the first
+    // occurrence of a coarse node kept, then sorted by column.  Two passes
+    // over the rows (sizes, then entries into the final arrays), each
+    // thread with one scratch row.
+    auto build_row = [&](int64_t r, std::vector<std::pair<int32_t, double>>& row) {
+        row.clear();
+        if (!is_free((int32_t)r)) return;
+        for (int64_t t = nstart[r]; t < nstart[r + 1]; ++t) {
+            const int64_t el = nel[t];
+            const int loc = nloc[t];
+            const int i = loc / ((p + 1) * (p + 1)), j = (loc / (p + 1)) % (p + 1), k = loc % (p + 1);
+            for (int a = 0; a <= q; ++a) {
+                const double va = I1[i * (q + 1) + a];
+                if (va == 0.0) continue;
+                for (int bb = 0; bb <= q; ++bb) {
+                    const double vb = I1[j * (q + 1) + bb];
+                    if (vb == 0.0) continue;
+                    for (int c = 0; c <= q; ++c) {
+                        const double vc = I1[k * (q + 1) + c];
+                        if (vc == 0.0) continue;
+                        const int32_t gc = l2g_next[el * ncl + lidx(q, a, bb, c)];
+                        if (gc < 0) continue;
+                        bool dup = false;
+                        for (const auto& pr : row)
+                            if (pr.first == gc) {
+                                dup = true;
+                                break;
+                            }
+                        if (!dup) row.emplace_back(gc, va * vb * vc);
                     }
                 }
             }
-            std::sort(row.begin(), row.end(),
-                      [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
-                          return x.first < y.first;
-                      });
         }
-    });
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                      return x.first < y.first;
+                  });
+    };
     HostCSR P;
     P.nrows = n_fine;
     P.ncols = n_coarse;
     P.rp.assign(n_fine + 1, 0);
-    for (int64_t r = 0; r < n_fine; ++r) P.rp[r + 1] = P.rp[r] + (int64_t)rows[r].size();
+    parallel_for(n_fine, 4096, [&](int64_t b, int64_t e) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t r = b; r < e; ++r) {
+            build_row(r, row);
+            P.rp[r + 1] = (int64_t)row.size();
+        }
+    });
+    for (int64_t r = 0; r < n_fine; ++r) P.rp[r + 1] += P.rp[r];
     P.ci.resize(P.rp.back());
     P.val.resize(P.rp.back());
-    for (int64_t r = 0; r < n_fine; ++r) {
-        int64_t o = P.rp[r];
-        for (auto& pr : rows[r]) { P.ci[o] = pr.first; P.val[o] = pr.second; ++o; }
-    }
+    parallel_for(n_fine, 4096, [&](int64_t b, int64_t e) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t r = b; r < e; ++r) {
+            build_row(r, row);
+            int64_t o = P.rp[r];
+            for (const auto& pr : row) {
+                P.ci[o] = pr.first;
+                P.val[o] = pr.second;
+                ++o;
+            }
+        }
+    });
     return P;
 }
 
