@@ -28,8 +28,9 @@ def test_traffic_entry_follows_the_kernel_sources(tmp_path, monkeypatch):
     f.write_text(json.dumps(fresh))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.traffic_entry("helmholtz16_p4") == entry["bytes_per_launch"]
-    stale = dict(rec)
-    stale["helmholtz16_p4"] = dict(entry, kernel_source_hash="0" * 16)
+    stale = {k: dict(v, kernel_source_hash="0" * 16) for k, v in rec.items()}
     f.write_text(json.dumps(stale))
     assert bench.traffic_entry("helmholtz16_p4") is None
+    assert bench.traffic_entry("helmholtz32_p4") is None
+    f.write_text(json.dumps({}))
     assert bench.traffic_entry("helmholtz32_p4") is None
