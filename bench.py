@@ -145,7 +145,9 @@ def traffic_entry(workload):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(mesh, b, lam, w, gpu_iters):
+def cpu_baseline(mesh, b, lam, w, gpu_iters, name):
+    """The oracle's whole FP64 solve on workload `name` (setup untimed), a
+    few solves on one core; value in solves/s of that workload."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import hierarchy, krylov
@@ -165,9 +167,11 @@ def cpu_baseline(mesh, b, lam, w, gpu_iters):
             reps += 1
             log(f"cpu baseline: oracle solve {reps}: {iters} iterations")
     return {"value": reps / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} complete oracle solves (FP64 PCG to 1e-10, {iters} iterations each; "
-                      f"GPU took {gpu_iters}) on the same hierarchy and right-hand side, "
-                      f"BLAS limited to 1 thread; oracle setup {setup_s:.1f} s not timed"}
+            "sample": f"{reps} complete oracle solves of the {name} workload ({w['n']}^3 hexahedra, "
+                      f"p = {w['p']}, {mesh.n_nodes} nodes; FP64 PCG to 1e-10, {iters} iterations each, "
+                      f"the GPU took {gpu_iters} on it), BLAS limited to 1 thread; oracle setup "
+                      f"{setup_s:.1f} s not timed; the headline workload's oracle setup does not fit "
+                      f"a bench run"}
 
 
 def modal_leg(torch, Solver, Options, w, lam, reps=3):
@@ -644,7 +648,8 @@ def main():
         # the oracle builds a 16^3, p = 4 hierarchy in about ten seconds; the
         # headline 32^3 one (8x the elements) does not fit a bench run
         cmesh, cb, clam, cw = problem("helmholtz16_p4")
-        cpu = cpu_baseline(cmesh, cb, clam, cw, extra.get("helmholtz16_p4", {}).get("fp64", {}).get("iterations"))
+        cpu = cpu_baseline(cmesh, cb, clam, cw, extra.get("helmholtz16_p4", {}).get("fp64", {}).get("iterations"),
+                           "helmholtz16_p4")
     solver.close()
 
     out = {
