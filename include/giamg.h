@@ -141,15 +141,16 @@ typedef struct giamg_opts {
                               giamg_solve and giamg_solve_noalloc only (batched solves,
                               sessions and the V-cycle steps of giamg_apply return
                               GIAMG_ENOTSUP) */
-    int32_t  assembly;     /* GIAMG_ASSEMBLY_*: where the fine operator A = K + lambda M is
-                              assembled (Section 3.1's element integrals).  AUTO (the
-                              default): on the device when every row's candidate columns
-                              and the element-row work fit the kernels' LDS lists (p <= 8
-                              on hexahedral meshes with at most 8 elements per node), on
-                              the host otherwise; DEVICE: on the device or GIAMG_ENOTSUP;
-                              HOST: on the host (C++ threads), then copied.  Same pattern
-                              and entry order; the element integrals are contracted in
-                              another order, so values agree to rounding */
+    int32_t  assembly;     /* GIAMG_ASSEMBLY_*: where the fine operator A = K + lambda M
+                              (Section 3.1's element integrals) and the p-transfer
+                              operators P, R = P^T (Algorithms 2-4, 7) are built.  AUTO
+                              (the default): each on the device when its rows fit the
+                              kernels' LDS lists (p <= 9 on hexahedral meshes with at
+                              most 8 elements per node), else on the host; DEVICE: on
+                              the device or GIAMG_ENOTSUP; HOST: on the host (C++
+                              threads), then copied.  Same patterns; P and R bit for bit,
+                              A's element integrals are contracted in another order, so
+                              its values agree to rounding */
 } giamg_opts;
 
 /* Fill *opts with the defaults listed above. */

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["setup_host.cpp", "kernels.hip", "assembly.hip", "groups.cpp", "spgemm.hip", "solver.hip", "batch.hip",
+SOURCES = ["setup_host.cpp", "kernels.hip", "assembly.hip", "ptransfer.hip", "groups.cpp", "spgemm.hip", "solver.hip", "batch.hip",
            "serve.cpp", "capi.cpp"]
 
 FLAGS = [

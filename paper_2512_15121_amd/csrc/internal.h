@@ -276,6 +276,13 @@ void reference_tables(int p, int basis, std::vector<double>& L, std::vector<doub
 void node_elements(const int32_t* l2g, int64_t n_elem, int nl, int64_t n_nodes, std::vector<int64_t>& nstart,
                    std::vector<int32_t>& nel, std::vector<int32_t>& nloc);
 struct DevCSR;
+// The p-transfer P (n_fine x n_coarse) and R = P^T built on the device, with
+// the maps of p_transfer_maps; the same rows and values as p_transfer.
+// make32 adds FP32 values and blocks.  Throws GIAMG_ENOTSUP when a row's
+// candidates exceed the kernels' LDS lists (nothing is built then).
+void p_transfer_device(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q, int64_t n_fine,
+                       const std::vector<uint8_t>& free_mask, std::vector<int32_t>& l2g_next,
+                       int64_t& n_coarse, int basis, DevCSR& P, DevCSR& R, bool make32, hipStream_t s);
 // The same operator as assemble_fine (same pattern and entries, each entry
 // summed over its elements in ascending order), built on the device into d
 // (rows, columns, values and the FP64 row blocks).  Throws GIAMG_ENOTSUP when
@@ -289,6 +296,11 @@ void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t
                  const double* fq, double* b, int basis);
 
 // p-transfer: returns P (n_fine x n_coarse) and fills the next l2g.
+// The maps of a p-transfer (Algorithms 2-4): l2g_next of the coarse order,
+// the coarse node count, and the 1-D factor I1[i][a] ((p + 1) x (q + 1)).
+void p_transfer_maps(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q, int64_t n_fine,
+                     const std::vector<uint8_t>& free_mask, std::vector<int32_t>& l2g_next,
+                     int64_t& n_coarse, std::vector<double>& I1, int basis);
 HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q,
                    int64_t n_fine, const std::vector<uint8_t>& free_mask,
                    std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis);

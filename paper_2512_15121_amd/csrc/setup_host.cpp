@@ -576,9 +576,9 @@ void load_vector(const std::vector<double>& corners, const int32_t* l2g, int64_t
 // p-coarsening transfer (Algorithms 2-4 and 7): nodal interpolation, or
 // injection for the modal basis
 // ---------------------------------------------------------------------------
-HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q,
-                   int64_t n_fine, const std::vector<uint8_t>& free_mask,
-                   std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis) {
+void p_transfer_maps(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q, int64_t n_fine,
+                     const std::vector<uint8_t>& free_mask, std::vector<int32_t>& l2g_next,
+                     int64_t& n_coarse, std::vector<double>& I1, int basis) {
     const bool modal = basis == GIAMG_BASIS_MODAL;
     const int nl = (p + 1) * (p + 1) * (p + 1);
     const int ncl = (q + 1) * (q + 1) * (q + 1);
@@ -611,7 +611,7 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
         }
     // 1-D factor: interpolation I1[i][a] = l^q_a(xi^p_i) (|.| <= 1e-12 is a
     // structural zero), or the injection I1[a][a] = 1 of the modal basis
-    std::vector<double> I1((p + 1) * (q + 1), 0.0);
+    I1.assign((p + 1) * (q + 1), 0.0);
     if (modal) {
         for (int a = 0; a <= q; ++a) I1[a * (q + 1) + a] = 1.0;
     } else {
@@ -624,6 +624,16 @@ HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q
                 I1[i * (q + 1) + a] = std::fabs(v) <= 1e-12 ? 0.0 : v;
             }
     }
+}
+
+HostCSR p_transfer(const std::vector<int32_t>& l2g, int64_t n_elem, int p, int q,
+                   int64_t n_fine, const std::vector<uint8_t>& free_mask,
+                   std::vector<int32_t>& l2g_next, int64_t& n_coarse, int basis) {
+    const int nl = (p + 1) * (p + 1) * (p + 1);
+    const int ncl = (q + 1) * (q + 1) * (q + 1);
+    std::vector<double> I1;
+    p_transfer_maps(l2g, n_elem, p, q, n_fine, free_mask, l2g_next, n_coarse, I1, basis);
+    auto is_free = [&](int32_t g) { return g >= 0 && free_mask[g]; };
     // node -> elements (ascending) for the rows of P
     std::vector<int64_t> nstart(n_fine + 1, 0);
     for (int64_t i = 0; i < n_elem * nl; ++i)

@@ -356,12 +356,33 @@ void build_hierarchy(Handle& H, const double* coords, const int32_t* l2g) {
         std::vector<int32_t> l2g_next;
         int64_t nc = 0;
         Level& F = H.levels.back();
-        HostCSR P = p_transfer(F.l2g, ne, order, q, F.n, free_mask, l2g_next, nc, o.basis);
+        bool on_device = false;
+        if (o.assembly != GIAMG_ASSEMBLY_HOST) {
+            try {
+                p_transfer_device(F.l2g, ne, order, q, F.n, free_mask, l2g_next, nc, o.basis, F.P, F.R, mixed,
+                                  H.stream);
+                on_device = true;
+            } catch (const Error& e) {
+                // AUTO: rows that outgrow the kernels' LDS lists go to the host
+                if (e.code != GIAMG_ENOTSUP || o.assembly == GIAMG_ASSEMBLY_DEVICE) throw;
+                F.P = DevCSR();
+                F.R = DevCSR();
+            }
+        }
+        if (!on_device) {
+            HostCSR P = p_transfer(F.l2g, ne, order, q, F.n, free_mask, l2g_next, nc, o.basis);
+            if (nc > 0) {
+                HostCSR R = transpose(P);
+                upload_csr(P, F.P, H.stream, mixed);
+                upload_csr(R, F.R, H.stream, mixed);
+            }
+        }
         H.setup_ms[1] += ms_since(t0);
-        if (nc == 0) break;
-        HostCSR R = transpose(P);
-        upload_csr(P, F.P, H.stream, mixed);
-        upload_csr(R, F.R, H.stream, mixed);
+        if (nc == 0) {
+            F.P = DevCSR();
+            F.R = DevCSR();
+            break;
+        }
         t0 = clock_t_::now();
         spgemm(F.A, F.P, F.AP, H.stream);
         Level C;

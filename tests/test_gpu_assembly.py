@@ -111,3 +111,42 @@ def test_device_assembly_full_size_16cube_p4(torch_dev):
     assert np.max(np.abs(v_d - v_h)) <= 1e-13 * scale
     A = sp.csr_matrix((v_d, ci_d, rp_d), shape=(m.n_nodes, m.n_nodes))
     assert abs(A - A.T).max() <= 1e-13 * scale
+
+
+TRANSFER_CASES = {
+    # name: (n, p, bc, basis, schedule, keep_boundary)
+    "p4_dirichlet": (4, 4, "dirichlet", "nodal", (), False),
+    "p6_pin": (3, 6, "pin", "nodal", (), False),
+    "p5_by_one": (3, 5, "dirichlet", "nodal", (4, 3, 2, 1), False),
+    "p5_non_divisor": (3, 5, "dirichlet", "nodal", (4, 2, 1), False),
+    "p4_modal": (3, 4, "dirichlet", "modal", (), False),
+    "p8_keep_boundary": (2, 8, "dirichlet", "nodal", (), True),
+}
+
+
+@pytest.mark.parametrize("name", list(TRANSFER_CASES))
+def test_device_p_transfer_matches_host_bitwise(torch_dev, name):
+    """P and R = P^T of every p-level built on the device equal the host
+    build bit for bit (rows, columns, values), and so do the coarse element
+    maps."""
+    from paper_2512_15121_amd import Solver, Options
+    n, p, bc, basis, sched, keep = TRANSFER_CASES[name]
+    print(f"case {name}", flush=True)
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=3, basis=basis)
+    out = {}
+    for where in ("device", "host"):
+        s = Solver(m.coords, m.l2g, p, 1.0, Options(bc=bc, basis=basis, schedule=sched, keep_boundary=keep,
+                                                     assembly=where, coarse_max=50))
+        levels = []
+        for l in range(s.num_levels() - 1):
+            d = s.level(l)
+            if d["kind"] != "p" or s.level(l + 1)["kind"] != "p":
+                break
+            levels.append((s.level_csr(l, "P"), s.level_csr(l, "R"), s.level_l2g(l + 1)))
+        out[where] = levels
+        s.close()
+    assert len(out["device"]) == len(out["host"]) > 0
+    for (pd, rd, gd), (ph, rh, gh) in zip(out["device"], out["host"]):
+        for a, b in ((pd, ph), (rd, rh)):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b))
+        assert np.array_equal(gd, gh)
