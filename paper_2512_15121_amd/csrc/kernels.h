@@ -87,6 +87,9 @@ struct SpmvArgs {
     int block_cap = 0, block_threads = 0;   // shape the row blocks were built for
     int lanes = 16;                  // lanes that reduce one row (16, 4 or 1)
     const int* stop = nullptr;       // device stop flag (null: the thread's StopScope flag)
+    const double* vnz = nullptr;     // SPMV_RINIT: when set and *vnz == 0, v is all +0 and
+                                     // y = f exactly (A v = +0 row by row: every row has a
+                                     // positive diagonal entry), so no product is formed
     // host only: events the dispatch itself records at kernel start and end
     // (timing; null for ordinary launches)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -157,6 +160,8 @@ void launch_convert(int64_t n, const Tin* a, Tout* b, hipStream_t s);
 template <typename T>
 void launch_coarse_apply(int64_t n, const double* inv, const T* f, T* x, hipStream_t s);
 void launch_fill(int64_t n, double v, double* x, hipStream_t s);
+// *flag = 1 if some x[i] has a nonzero bit pattern (flag must start at 0).
+void launch_nonzero_flag(int64_t n, const double* x, double* flag, hipStream_t s);
 // y = d .* x (elementwise; the diagonal preconditioner)
 void launch_mul(int64_t n, const double* d, const double* x, double* y, hipStream_t s);
 
@@ -179,7 +184,9 @@ void launch_reduce(int64_t m, const double* partial, int64_t stride, int ncomp, 
 // device scalar slots; (S_BB, S_RR) and (S_RZNEW, S_ZROLD) are written as pairs
 enum ScalarSlot : int {
     S_BB = 0, S_RR = 1, S_RZ = 2, S_PQ = 3, S_ALPHA = 4, S_BETA = 5, S_RZNEW = 6, S_ZROLD = 7,
-    S_FLAG = 8, S_TMP = 9, S_TOL = 10, S_COUNT = 16
+    S_FLAG = 8, S_TMP = 9, S_TOL = 10,
+    S_XNZ = 11,   // 1 when the initial guess has a nonzero bit pattern, else 0
+    S_COUNT = 16
 };
 // CG control block (device ints): stop flag, iterations done, iteration cap
 enum CtlSlot : int { C_STOP = 0, C_ITERS = 1, C_MAXIT = 2, C_COUNT = 4 };

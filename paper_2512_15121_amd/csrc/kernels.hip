@@ -408,6 +408,23 @@ spmv_stream_kernel(SpmvArgs<T> a) {
     const BlockDesc B = a.bdesc[lb];   // one load: no dependent row-pointer reads ahead of the values
     const int64_t r0 = B.r0, base = B.base, cnt = B.n;
     double dot = 0.0, dot2 = 0.0;
+    if constexpr (MODE == SPMV_RINIT) {
+        if (a.vnz != nullptr && *a.vnz == 0.0) {
+            // v = +0 everywhere: the row sums are +0, y = f - 0 = f
+            const int nr = cnt > CAP ? 1 : B.nrows;
+            if (tid < nr) {
+                RowIn<T> in{};
+                epilogue_load<T, MODE>(a, r0 + tid, in);
+                epilogue_store<T, MODE>(a, r0 + tid, T(0), in, dot, dot2);
+            }
+            block_sum_to0<NT, n_partials<MODE>()>(red, tid, dot, dot2);
+            if (tid == 0) {
+                a.partial[lb] = dot;
+                a.partial[a.nblk + lb] = dot2;
+            }
+            return;
+        }
+    }
     if constexpr (STAGE != 1) {
         if (cnt > CAP) {
             // one long row: block-wide strided sum, fixed-order block sum
@@ -1188,6 +1205,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // b FP64, or the FP32 output of a mixed-precision V-cycle widened exactly
+// flag = 1 when some entry of x has a nonzero bit pattern (-0 counts as
+// nonzero); the flag starts at 0 and is only ever set to 1.
+__global__ void __launch_bounds__(VEC_THREADS) nonzero_flag_kernel(int64_t n, const double* __restrict__ x,
+                                                                   double* __restrict__ flag) {
+    bool nz = false;
+    for (int64_t i = blockIdx.x * (int64_t)VEC_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VEC_THREADS)
+        nz = nz || __double_as_longlong(x[i]) != 0;
+    if (__ballot(nz) != 0 && threadIdx.x % WAVE == 0) *flag = 1.0;
+}
+
+void launch_nonzero_flag(int64_t n, const double* x, double* flag, hipStream_t s) {
+    if (n <= 0) return;
+    nonzero_flag_kernel<<<(unsigned)vec_blocks(n), VEC_THREADS, 0, s>>>(n, x, flag);
+    GIAMG_HIP(hipGetLastError());
+}
+
 template <typename TB>
 __global__ void __launch_bounds__(VEC_THREADS) dot_partial_kernel(int64_t n, const double* __restrict__ a,
                                                                   const TB* __restrict__ b,

@@ -920,9 +920,12 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
     const bool flexible = H.opts.precision == GIAMG_PREC_MIXED;
     hipStream_t s = H.stream;
     const int64_t gs = product_blocks(L0.A), gv = vec_blocks(n);
-    auto rinit = [&](double* out) {
+    // initial: a zero guess (flagged on the device) skips the product; at
+    // exit the true residual of the solution is always formed
+    auto rinit = [&](double* out, bool initial) {
         SpmvArgs<double> a = args_of<double>(L0.A, L0.A.val.get());
         a.v = x; a.f = b; a.y = out; a.partial = w.partial;
+        if (initial) a.vnz = w.scal + S_XNZ;
         run_spmv(H, SPMV_RINIT, a);
     };
     H.bytes = 0.0;
@@ -930,7 +933,8 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
     H.prof.half = 0;
     GIAMG_HIP(hipEventRecord(H.ev0, s));
     launch_fill(S_COUNT, 0.0, w.scal, s);
-    rinit(w.r);
+    launch_nonzero_flag(n, x, w.scal + S_XNZ, s);
+    rinit(w.r, true);
     launch_reduce(gs, w.partial, gs, 2, w.scal + S_BB, s);
     fetch_scalars(H, w.scal);
     const double bnorm = std::sqrt(H.host_scal[S_BB]);
@@ -1130,7 +1134,7 @@ int solve_on(Handle& H, const CgWork& w, bool allow_graph, const double* b, doub
         prof_harvest(H, iters, prof_first, prof_second);
     }
     // true residual at exit (outside the timed region)
-    rinit(w.tmp);
+    rinit(w.tmp, false);
     launch_reduce(gs, w.partial, gs, 2, w.scal + S_BB, s);
     fetch_scalars(H, w.scal);
     if (info) {

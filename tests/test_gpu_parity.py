@@ -781,6 +781,28 @@ def test_kernel_timing_and_read_bandwidth(torch_dev):
     assert giamg.read_bandwidth(1 << 24, 3) > 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_initial_guess_skips_the_product_with_the_same_bits(torch_dev, precision):
+    """A zero initial guess is detected on the device and the first residual
+    is b itself, without the product A x: the solve equals, bit for bit, the
+    one started from -0 everywhere (a nonzero bit pattern, so the product is
+    formed), and a nonzero guess is still honoured."""
+    torch, dev = torch_dev
+    name = "p4_6cube_cheb_sa"
+    m, H = _case(name)
+    b = _to(torch, dev, synth.normal_rhs(m.n_nodes, 31))
+    s = _solver(name, precision=precision)
+    x0 = torch.zeros_like(b)
+    xa, ia = s.solve(b, x0.clone(), tol=1e-10)
+    xb, ib = s.solve(b, torch.full_like(b, -0.0), tol=1e-10)
+    assert ia.iters == ib.iters and torch.equal(xa, xb)
+    assert ia.true_relres < 1e-9
+    # a converged guess: no iterations, unchanged
+    xc, ic = s.solve(b, xa.clone(), tol=1e-6)
+    assert ic.iters == 0 and torch.equal(xc, xa)
+    s.close()
+
+
 def test_jacobi_pcg_baseline_parity(torch_dev):
     """The diagonally preconditioned CG baseline of the paper's comparison
     (Section 3.2): one level, against the oracle's Jacobi-PCG.  A run of a
