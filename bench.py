@@ -367,11 +367,12 @@ def batched_leg(torch, Solver, Options, k=64, reps=3):
 
 
 def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4), slots=8,
-                chunk=2, seed=5, budget=100e9, min_window_s=3.0):
+                chunk=2, seed=5, budget=100e9, min_window_s=3.0, precision="mixed", direct=False):
     """Serving trace: requests for Helmholtz problems on n^3 perturbed meshes,
     n and p uniform in the given ranges, one mesh seed and one lambda
-    (log-uniform [0.1, 100]) per (n, p) key, right-hand sides N(0, 1); mixed
-    GIAMG-PCG to 1e-10.  A warm-up pass builds every hierarchy; a closed-loop
+    (log-uniform [0.1, 100]) per (n, p) key, right-hand sides N(0, 1);
+    GIAMG-PCG to 1e-10 (mixed precision unless stated; direct=True keeps no
+    staged-gather tables, which the block products of the server never read).  A warm-up pass builds every hierarchy; a closed-loop
     pass (every request submitted at once) gives the saturation throughput S;
     open-loop passes with Poisson arrivals at 0.7 S and 0.4 S replay the
     trace until the arrivals span at least min_window_s (so the latency tail
@@ -391,7 +392,8 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
         if (n, p) not in problems:
             mesh = synth.hex_mesh(n, p, perturb=0.1, seed=1000 + 10 * n + p)
             lam = synth.loguniform_lambda(2000 + 10 * n + p)
-            pid = srv.add_problem(mesh.coords, mesh.l2g, p, lam, Options(precision="mixed"))
+            pid = srv.add_problem(mesh.coords, mesh.l2g, p, lam,
+                                  Options(precision=precision, direct_gathers=direct))
             problems[(n, p)] = (pid, mesh.n_nodes)
         pid, nn = problems[(n, p)]
         trace.append((pid, synth.normal_rhs(nn, 50000 + i)))
@@ -477,7 +479,8 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
     finally:
         srv.close()
     out = {"workload": f"{n_req} requests, n in {list(n_range)}, p in {list(p_range)}, "
-                       f"{len(problems)} hierarchies, mixed, {slots} slots per hierarchy, "
+                       f"{len(problems)} hierarchies, {precision}{', no staged tables' if direct else ''}, "
+                       f"{slots} slots per hierarchy, "
                        f"chunk {chunk}, HBM budget {budget / 1e9:.0f} GB",
            "saturation_solves_per_s": round(sat, 2),
            "closed_p50_ms": round(float(np.percentile(lat_closed, 50)), 3),
@@ -674,12 +677,12 @@ def serving(torch, Server, Options, size, slots=8, chunk=2):
     p <= 4; medium: 2000 requests, n <= 16, p <= 6, ~78 GB of hierarchies;
     large: 2000 requests, n <= 20, p <= 6, ~187 GB, the largest n range
     whose hierarchies all fit one MI355X's HBM; full: n <= 24, ~381 GB of
-    hierarchies for a 250 GB budget, so the cache evicts and sets
-    hierarchies up again)."""
+    hierarchies in mixed precision, so the full trace runs in FP64 without
+    staged-gather tables, ~15 B per fine nonzero, within a 270 GB budget)."""
     try:
         if size == "full":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24), p_range=(2, 6),
-                               budget=250e9, slots=slots, chunk=chunk)
+                               budget=270e9, slots=slots, chunk=chunk, precision="fp64", direct=True)
         if size == "large":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 20), p_range=(2, 6),
                                budget=250e9, slots=slots, chunk=chunk)
