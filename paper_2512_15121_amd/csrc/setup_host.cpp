@@ -7,6 +7,7 @@
 // Algorithm 7 (prolongation, nodal-interpolation variant); Section 2.5
 // (MIS aggregation, tentative prolongation, SPAI smoothing).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <thread>
 
@@ -886,38 +887,66 @@ HostCSR transpose(const HostCSR& M) {
     return T;
 }
 
-// Cholesky A = L L^T, then A^-1 = L^-T L^-1 column by column.
+// Cholesky A = L L^T, then A^-1 = L^-T L^-1 column by column.  Every sum
+// runs over k in ascending order, so the result does not depend on the
+// thread count.  The factor is computed column by column by one team of
+// threads (rows dealt out cyclically, a barrier per column) instead of a
+// thread launch per column; the solves skip the leading zeros of e_c (the
+// terms they drop are exact zeros) and read L^T row-wise.
 bool spd_inverse(const std::vector<double>& A, int64_t n, std::vector<double>& inv) {
     std::vector<double> L(A);
-    for (int64_t j = 0; j < n; ++j) {
-        double d = L[j * n + j];
-        for (int64_t k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
-        if (!(d > 0.0)) return false;
-        d = std::sqrt(d);
-        L[j * n + j] = d;
-        parallel_for(n - j - 1, 64, [&](int64_t b, int64_t e) {
-            for (int64_t ii = b; ii < e; ++ii) {
-                int64_t i = j + 1 + ii;
-                double s = L[i * n + j];
-                for (int64_t k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
-                L[i * n + j] = s / d;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, n / 32}));
+    std::atomic<int64_t> arrived{0};
+    std::atomic<bool> ok{true};
+    auto factor = [&](int t) {
+        for (int64_t j = 0; j < n; ++j) {
+            double d = L[j * n + j];
+            for (int64_t k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+            if (!(d > 0.0)) {
+                ok = false;
+            } else {
+                d = std::sqrt(d);
+                for (int64_t i = j + 1 + t; i < n; i += nt) {
+                    double s = L[i * n + j];
+                    for (int64_t k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+                    L[i * n + j] = s / d;
+                }
             }
-        });
+            arrived.fetch_add(1);   // column j done: the next reads it
+            while (arrived.load() < (j + 1) * nt) std::this_thread::yield();
+            if (!ok) return;
+            // every thread has read the diagonal entry of column j; later
+            // columns do not read it, the solves do
+            if (t == 0) L[j * n + j] = d;
+        }
+    };
+    {
+        std::vector<std::thread> team;
+        for (int t = 1; t < nt; ++t) team.emplace_back(factor, t);
+        factor(0);
+        for (auto& th : team) th.join();
     }
+    if (!ok) return false;
+    std::vector<double> U((size_t)(n * n));   // U = L^T, row-major
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = 0; k < n; ++k) U[k * n + i] = L[i * n + k];
     inv.assign(n * n, 0.0);
     parallel_for(n, 8, [&](int64_t b, int64_t e) {
-        std::vector<double> y(n);
+        std::vector<double> y(n), z(n);
         for (int64_t c = b; c < e; ++c) {
-            for (int64_t i = 0; i < n; ++i) {          // L y = e_c
+            std::fill(y.begin(), y.begin() + c, 0.0);
+            for (int64_t i = c; i < n; ++i) {          // L y = e_c (y_i = 0 for i < c)
                 double s = (i == c) ? 1.0 : 0.0;
-                for (int64_t k = 0; k < i; ++k) s -= L[i * n + k] * y[k];
+                for (int64_t k = c; k < i; ++k) s -= L[i * n + k] * y[k];
                 y[i] = s / L[i * n + i];
             }
             for (int64_t i = n - 1; i >= 0; --i) {     // L^T z = y
                 double s = y[i];
-                for (int64_t k = i + 1; k < n; ++k) s -= L[k * n + i] * inv[k * n + c];
-                inv[i * n + c] = s / L[i * n + i];
+                for (int64_t k = i + 1; k < n; ++k) s -= U[i * n + k] * z[k];
+                z[i] = s / U[i * n + i];
             }
+            for (int64_t i = 0; i < n; ++i) inv[i * n + c] = z[i];
         }
     });
     // symmetrise exactly
