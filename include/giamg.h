@@ -477,6 +477,16 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
                          int64_t n, uint64_t seed, double theta, int32_t* agg, int64_t* n_agg,
                          giamg_hcsr* P_out);
 
+/* Dense inverse of the coarsest operator as giamg_setup forms it for the
+ * direct solve on the last level of Algorithm 1 (Section 2.1): Cholesky
+ * factor A = L L^T, the columns of A^-1 by forward and back substitution,
+ * then the result symmetrised exactly.  A: host double [n][n], row-major,
+ * symmetric positive definite (only its lower triangle and diagonal are
+ * read); inv: host double [n][n], written in full.  1 <= n <= 16384 (the
+ * coarsest size giamg_setup accepts); GIAMG_EINVAL if a pivot is not
+ * positive (A not positive definite, or NaN), inv then undefined. */
+int giamg_host_coarse_inverse(const double* A, int64_t n, double* inv);
+
 /*
  * giamg_time_kernel -- time one device kernel of a level in the launch
  * configuration the solve uses: `reps` (1 to 100000) launches on the handle's stream, each

@@ -542,6 +542,17 @@ int giamg_host_aggregate(const int64_t* row_ptr, const int32_t* col, const doubl
     });
 }
 
+int giamg_host_coarse_inverse(const double* A, int64_t n, double* inv) {
+    return guarded([&]() -> int {
+        GIAMG_REQUIRE(A != nullptr && inv != nullptr, "null argument");
+        GIAMG_REQUIRE(n >= 1 && n <= 16384, "n must be in [1, 16384]");
+        std::vector<double> a(A, A + n * n), out;
+        GIAMG_REQUIRE(giamg::spd_inverse(a, n, out), "matrix is not positive definite");
+        std::memcpy(inv, out.data(), out.size() * sizeof(double));
+        return GIAMG_OK;
+    });
+}
+
 int giamg_time_kernel(giamg_handle h, int32_t kernel, int32_t level, int32_t reps, double* ms,
                       double* bytes) {
     return guarded([&]() -> int {

@@ -186,6 +186,7 @@ _SIGNATURES = {
     "giamg_host_assemble": (I32, [P, I64, P, I64, I32, F64, I32, I64, I32, ctypes.POINTER(P)]),
     "giamg_host_p_transfer": (I32, [P, I64, I32, I32, I64, P, I32, P, P, ctypes.POINTER(P)]),
     "giamg_host_aggregate": (I32, [P, P, P, I64, ctypes.c_uint64, F64, P, P, ctypes.POINTER(P)]),
+    "giamg_host_coarse_inverse": (I32, [P, I64, P]),
     "giamg_time_kernel": (I32, [P, I32, I32, I32, P, P]),
     "giamg_session_create": (I32, [P, I32, F64, ctypes.POINTER(P)]),
     "giamg_session_admit": (I32, [P, I32, P, P]),
@@ -563,6 +564,17 @@ def host_aggregate(rp, ci, val, seed=0, theta=0.0):
     _check(library().giamg_host_aggregate(_ptr(rp), _ptr(ci), _ptr(val), n, seed, float(theta),
                                           _ptr(agg), ctypes.byref(na), ctypes.byref(h)))
     return agg, na.value, _take_hcsr(h)
+
+
+def host_coarse_inverse(A):
+    """Dense inverse of a symmetric positive definite matrix as the setup
+    forms it for the coarsest level (host float64 [n][n])."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    inv = np.empty_like(A)
+    _check(library().giamg_host_coarse_inverse(_ptr(A), A.shape[0], _ptr(inv)))
+    return inv
 
 
 # ---- continuous batching ---------------------------------------------------

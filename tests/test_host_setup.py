@@ -167,3 +167,78 @@ def test_transfer_rejects_non_decreasing_order():
     m = synth.hex_mesh(2, 3, basis="nodal")
     with pytest.raises(giamg.GiamgError):
         giamg.host_p_transfer(m.l2g, 3, 3, m.n_nodes, np.ones(m.n_nodes, dtype=bool))
+
+
+# ---- dense inverse of the coarsest operator --------------------------------
+def _spd(n, seed, cond=1e3):
+    """Symmetric positive definite test matrix with eigenvalues spread
+    log-uniformly over [1, cond] in a random orthonormal basis."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.logspace(0.0, np.log10(cond), n)
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T)
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 63, 64, 65, 200, 721])
+def test_coarse_inverse_against_lapack(n):
+    """Sizes below and above the point where the factorisation splits its
+    columns over threads.  The inverse is exactly symmetric, and A X = I and
+    X equals LAPACK's inverse to the rounding error of a condition-1000
+    system."""
+    A = _spd(n, 100 + n)
+    X = giamg.host_coarse_inverse(A)
+    assert np.array_equal(X, X.T)
+    assert np.max(np.abs(A @ X - np.eye(n))) <= 1e-11
+    ref = np.linalg.inv(A)
+    assert np.max(np.abs(X - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_coarse_inverse_reads_the_lower_triangle_only():
+    A = _spd(90, 7)
+    B = A.copy()
+    B[np.triu_indices(90, 1)] = np.nan
+    assert np.array_equal(giamg.host_coarse_inverse(A), giamg.host_coarse_inverse(B))
+
+
+def test_coarse_inverse_closed_forms():
+    # 1 x 1 and diagonal: the factor is the square root, the solves divide
+    # by it twice (within two roundings of 1/d)
+    assert giamg.host_coarse_inverse(np.array([[4.0]]))[0, 0] == 0.25
+    d = np.linspace(0.5, 50.0, 70)
+    X = giamg.host_coarse_inverse(np.diag(d))
+    assert np.count_nonzero(X - np.diag(np.diag(X))) == 0
+    assert np.max(np.abs(np.diag(X) * d - 1.0)) <= 4e-16
+    # tridiagonal [-1, 2, -1]: (A^-1)_ij = min(i, j) (n + 1 - max(i, j)) / (n + 1)
+    n = 80
+    T = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    i = np.arange(1, n + 1)
+    exact = np.minimum.outer(i, i) * (n + 1 - np.maximum.outer(i, i)) / (n + 1)
+    assert np.max(np.abs(giamg.host_coarse_inverse(T) - exact)) <= 1e-11 * exact.max()
+
+
+def test_coarse_inverse_of_table1_coarsest_operator():
+    """Table 1's mesh with the boundary kept: the 27-row order-1 operator at
+    the bottom of the p-hierarchy (oracle), inverted as the setup does."""
+    from oracle import hierarchy
+    m = synth.hex_mesh(2, 8, perturb=0.1, seed=3)
+    H = hierarchy.build(m.coords, m.l2g, 8, 1.0,
+                        hierarchy.Options(smoother="chebyshev", degree=3, keep_boundary=True))
+    A = H.levels[-1].A.toarray()
+    assert A.shape == (27, 27)
+    X = giamg.host_coarse_inverse(A)
+    assert np.max(np.abs(A @ X - np.eye(27))) <= 1e-12 * np.linalg.cond(A)
+
+
+def test_coarse_inverse_rejects_indefinite_and_bad_sizes():
+    for A in (np.array([[1.0, 2.0], [2.0, 1.0]]), np.zeros((100, 100)), np.array([[np.nan]]),
+              -np.eye(70)):
+        with pytest.raises(giamg.GiamgError) as e:
+            giamg.host_coarse_inverse(A)
+        assert e.value.code == giamg.EINVAL
+    lib = giamg.library()
+    buf = np.zeros(4)
+    for n in (0, -1, 16385):   # rejected before any element is read
+        assert lib.giamg_host_coarse_inverse(giamg._ptr(buf), n, giamg._ptr(buf)) == giamg.EINVAL
+    with pytest.raises(ValueError):
+        giamg.host_coarse_inverse(np.zeros((3, 4)))
