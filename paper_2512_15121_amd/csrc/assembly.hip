@@ -308,6 +308,9 @@ void assemble_fine_device(const std::vector<double>& corners, const int32_t* l2g
                           hipStream_t s) {
     const int n1 = p + 1, nq = p + 2, nl = n1 * n1 * n1, Q = nq * nq * nq;
     GIAMG_REQUIRE(n < (int64_t(1) << 31), "too many nodes for 32-bit column ids");
+    // one wavefront per row: a launch covers at most 2^32 - 1 work-items
+    if (n * ASM_WAVE > (int64_t)UINT32_MAX)
+        throw Error(GIAMG_ENOTSUP, "device assembly: more rows than one launch covers");
     std::vector<int64_t> nstart;
     std::vector<int32_t> nel, nloc;
     node_elements(l2g, ne, nl, n, nstart, nel, nloc);

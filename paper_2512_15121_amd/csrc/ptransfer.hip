@@ -228,6 +228,10 @@ void p_transfer_device(const std::vector<int32_t>& l2g, int64_t ne, int p, int q
     const int limit = pt_lds_limit();
     if (p2 * 8 > limit || maxe * ncl >= (int64_t(1) << PT_CAND_BITS) || ne >= (int64_t(1) << 31))
         throw Error(GIAMG_ENOTSUP, "device p-transfer: a row's candidates exceed the kernel's LDS list");
+    // one wavefront per fine row (and per coarse row in the sort): a launch
+    // covers at most 2^32 - 1 work-items
+    if (n_fine * PT_WAVE > (int64_t)UINT32_MAX)
+        throw Error(GIAMG_ENOTSUP, "device p-transfer: more rows than one launch covers");
     std::vector<double> I1;
     p_transfer_maps(l2g, ne, p, q, n_fine, free_mask, l2g_next, n_coarse, I1, basis);
 

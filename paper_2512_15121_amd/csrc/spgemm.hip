@@ -171,6 +171,9 @@ void spgemm(const DevCSR& A, const DevCSR& B, DevCSR& C, hipStream_t s) {
     }
     DevBuf<int32_t> counts(n);
     GIAMG_REQUIRE(n < (int64_t(1) << 31), "spgemm: too many rows");
+    // one wavefront per row: a launch covers at most 2^32 - 1 work-items
+    if (n * SG_WAVE > (int64_t)UINT32_MAX)
+        throw Error(GIAMG_ENOTSUP, "spgemm: more rows than one launch covers");
     sg_count_kernel<<<(unsigned)n, SG_WAVE, 0, s>>>(n, A.rp.get(), A.ci.get(), B.rp.get(), B.ci.get(),
                                                    counts.get());
     GIAMG_HIP(hipGetLastError());
