@@ -98,6 +98,38 @@ def test_server_mixed_hierarchies(torch_dev):
         assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
 
 
+def test_server_fp64_without_staged_tables(torch_dev):
+    """The configuration of the largest serving trace: FP64 hierarchies
+    built with direct gathers (no staged-gather tables kept; the server's
+    block products never read them).  Results are bitwise those of the same
+    right-hand side solved alone on a default FP64 handle, and match the
+    oracle."""
+    torch, dev = torch_dev
+    from paper_2512_15121_amd import Server, Options
+    meshes = [synth.hex_mesh(n, p, perturb=0.1, seed=sd) for n, p, lam, sd in PROBLEMS]
+    srv = Server(hbm_budget=8 << 30, slots=4, chunk=2, tol=1e-10)
+    pids = [srv.add_problem(m.coords, m.l2g, p, lam, Options(precision="fp64", direct_gathers=True))
+            for m, (n, p, lam, sd) in zip(meshes, PROBLEMS)]
+    reqs = []
+    for i in range(9):
+        j = i % 3
+        b = synth.normal_rhs(meshes[j].n_nodes, 200 + i)
+        reqs.append((srv.submit(pids[j], b), j, b))
+    results = [(srv.wait(r), j, b) for r, j, b in reqs]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 9 and st["setups"] == 3
+    for (x, info, lat), j, b in results:
+        n, p, lam, sd = PROBLEMS[j]
+        assert info.status == 0
+        xa, ia = _alone(torch, dev, meshes[j], p, lam, b, precision="fp64")
+        assert info.iters == ia.iters and np.array_equal(x, xa)
+        H = hierarchy.build(meshes[j].coords, meshes[j].l2g, p, lam)
+        ref = krylov.giamg_pcg(H, b, tol=1e-10)
+        assert abs(info.iters - ref.iters) <= 1
+        assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
 def test_server_budget_evicts_and_stays_exact(torch_dev):
     torch, dev = torch_dev
     from paper_2512_15121_amd import Server, Options
