@@ -367,7 +367,8 @@ def batched_leg(torch, Solver, Options, k=64, reps=3):
 
 
 def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4), slots=8,
-                chunk=2, seed=5, budget=100e9, min_window_s=3.0, precision="mixed", direct=False):
+                chunk=2, seed=5, budget=100e9, min_window_s=3.0, precision="mixed", direct=False,
+                hold_ms=0):
     """Serving trace: requests for Helmholtz problems on n^3 perturbed meshes,
     n and p uniform in the given ranges, one mesh seed and one lambda
     (log-uniform [0.1, 100]) per (n, p) key, right-hand sides N(0, 1);
@@ -383,7 +384,7 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
     import threading
     import synth
     rng = np.random.Generator(np.random.PCG64(seed))
-    srv = Server(hbm_budget=int(budget), slots=slots, chunk=chunk, tol=1e-10)
+    srv = Server(hbm_budget=int(budget), slots=slots, chunk=chunk, tol=1e-10, hold_ms=hold_ms)
     problems = {}
     trace = []
     for i in range(n_req):
@@ -481,6 +482,7 @@ def serving_leg(torch, Server, Options, n_req=200, n_range=(4, 8), p_range=(2, 4
     out = {"workload": f"{n_req} requests, n in {list(n_range)}, p in {list(p_range)}, "
                        f"{len(problems)} hierarchies, {precision}{', no staged tables' if direct else ''}, "
                        f"{slots} slots per hierarchy, "
+                       f"{'admission hold ' + str(hold_ms) + ' ms, ' if hold_ms else ''}"
                        f"chunk {chunk}, HBM budget {budget / 1e9:.0f} GB",
            "saturation_solves_per_s": round(sat, 2),
            "closed_p50_ms": round(float(np.percentile(lat_closed, 50)), 3),
@@ -519,6 +521,10 @@ def main():
                     help="right-hand sides batched per hierarchy in the serving leg")
     ap.add_argument("--serving-chunk", type=int, default=2,
                     help="CG iterations between admission points in the serving leg")
+    ap.add_argument("--serving-hold", type=int, default=None,
+                    help="serving: admission hold in ms (requests join a hierarchy once they fill its free "
+                         "slots or the oldest has waited this long; 0 = at the next chunk boundary); "
+                         "default 0 for the small trace, 1000 for the others")
     ap.add_argument("--serving-only", action="store_true",
                     help="only run the serving leg given by --serving and print it as one JSON line")
     ap.add_argument("--batched-only", action="store_true",
@@ -547,7 +553,7 @@ def main():
     if args.serving_only:
         from paper_2512_15121_amd import Server
         print(json.dumps({"serving": serving(torch, Server, Options, args.serving, args.serving_slots,
-                                             args.serving_chunk)}), flush=True)
+                                             args.serving_chunk, args.serving_hold)}), flush=True)
         return
     mesh, b, lam, w = problem(args.workload)
     if args.pmc_probe:
@@ -644,7 +650,7 @@ def main():
     if args.serving != "off":
         from paper_2512_15121_amd import Server
         extra["serving"] = serving(torch, Server, Options, args.serving, args.serving_slots,
-                                   args.serving_chunk)
+                                   args.serving_chunk, args.serving_hold)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -672,24 +678,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def serving(torch, Server, Options, size, slots=8, chunk=2):
+def serving(torch, Server, Options, size, slots=8, chunk=2, hold_ms=None):
     """The serving trace of the chosen size (small: 200 requests, n <= 8,
     p <= 4; medium: 2000 requests, n <= 16, p <= 6, ~78 GB of hierarchies;
     large: 2000 requests, n <= 20, p <= 6, ~187 GB, the largest n range
     whose hierarchies all fit one MI355X's HBM; full: n <= 24, ~381 GB of
     hierarchies in mixed precision, so the full trace runs in FP64 without
     staged-gather tables, ~15 B per fine nonzero, within a 270 GB budget)."""
+    if hold_ms is None:   # solves of tens of ms: join at once; of seconds: admit in batches
+        hold_ms = 0 if size == "small" else 1000
     try:
         if size == "full":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24), p_range=(2, 6),
-                               budget=270e9, slots=slots, chunk=chunk, precision="fp64", direct=True)
+                               budget=270e9, slots=slots, chunk=chunk, precision="fp64", direct=True,
+                               hold_ms=hold_ms)
         if size == "large":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 20), p_range=(2, 6),
-                               budget=250e9, slots=slots, chunk=chunk)
+                               budget=250e9, slots=slots, chunk=chunk, hold_ms=hold_ms)
         if size == "medium":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 16), p_range=(2, 6),
-                               slots=slots, chunk=chunk)
-        return serving_leg(torch, Server, Options, slots=slots, chunk=chunk)
+                               slots=slots, chunk=chunk, hold_ms=hold_ms)
+        return serving_leg(torch, Server, Options, slots=slots, chunk=chunk, hold_ms=hold_ms)
     except Exception as e:
         log(f"serving leg failed: {e}")
         return {"error": str(e)}

@@ -548,6 +548,11 @@ typedef struct giamg_server_opts {
     int32_t slots;        /* concurrent right-hand sides per hierarchy */
     int32_t chunk;        /* CG iterations between admission points */
     double  tol;          /* relative residual target of every request */
+    int32_t hold_ms;      /* 0 (default): requests join a hierarchy's free slots at the
+                             next chunk boundary; > 0: they join only once they fill the
+                             free slots or the oldest has waited hold_ms (fuller batches,
+                             longer latency) */
+    int32_t pad;
 } giamg_server_opts;
 
 typedef struct giamg_server_stats {

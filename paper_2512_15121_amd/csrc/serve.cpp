@@ -274,7 +274,12 @@ struct Server {
     // One pass over a group at a chunk boundary (no step in flight): drain
     // the columns that finished, admit pending requests into free slots,
     // queue the next chunk of iterations.  Every call here is asynchronous.
-    bool group_boundary(Group& g, bool requests_waiting, std::vector<int>& state,
+    // With hold_ms > 0 pending requests enter a group only once they fill its
+    // free slots or the oldest of them has waited hold_ms: an admission runs
+    // a start sequence for the columns it brings, and a product costs the
+    // same for one running column as for all, so admitting in batches gives
+    // fuller steps at the price of latency.
+    bool group_boundary(Group& g, int n_waiting, Clock::time_point oldest, std::vector<int>& state,
                         std::vector<giamg_info>& infos) {
         bool progress = false;
         const int64_t n = problems[g.problem].n_nodes;
@@ -308,8 +313,12 @@ struct Server {
         }
         // admissions into the free slots
         const int room = (int)std::count(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1);
+        const bool admit =
+            room > 0 && n_waiting > 0 &&
+            (o.hold_ms <= 0 || n_waiting >= room ||
+             Clock::now() - oldest >= std::chrono::milliseconds(o.hold_ms));
         std::vector<Request*> adm;
-        if (room > 0 && requests_waiting) {
+        if (admit) {
             std::lock_guard<std::mutex> lk(mu);
             adm = take_pending(g.problem, room);
         }
@@ -426,7 +435,10 @@ struct Server {
                     }
                 }
                 if (g.inflight && !session_ready(g.S)) continue;
-                if (group_boundary(g, wanted.count((int)gi) > 0, state, infos)) progress = true;
+                const auto w = wanted.find((int)gi);
+                const int n_waiting = w == wanted.end() ? 0 : (int)w->second.size();
+                const Clock::time_point oldest = n_waiting ? w->second.front()->submit : Clock::now();
+                if (group_boundary(g, n_waiting, oldest, state, infos)) progress = true;
             }
             if (!progress) {
                 std::unique_lock<std::mutex> lk3(mu);
@@ -469,7 +481,7 @@ int giamg_server_create(const giamg_server_opts* o, giamg_server* out) {
     return sguard([&]() -> int {
         GIAMG_REQUIRE(o && out, "null argument");
         GIAMG_REQUIRE(o->hbm_budget > 0 && o->slots >= 1 && o->slots <= 1024 && o->chunk >= 1 &&
-                          o->tol >= 0.0,
+                          o->tol >= 0.0 && o->hold_ms >= 0 && o->hold_ms <= 60000,
                       "bad server options");
         std::unique_ptr<giamg_server_s> own(new giamg_server_s());
         giamg_server_s* s = own.get();

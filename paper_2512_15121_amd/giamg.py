@@ -59,7 +59,8 @@ class _Info(ctypes.Structure):
 
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_int64), ("slots", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("chunk", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("hold_ms", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -644,9 +645,9 @@ class Server:
     """Request loop with continuous batching, device hierarchy cache and HBM
     budget (runs on a background thread inside the library)."""
 
-    def __init__(self, hbm_budget, slots=8, chunk=2, tol=1e-10):
+    def __init__(self, hbm_budget, slots=8, chunk=2, tol=1e-10, hold_ms=0):
         self.lib = library()
-        o = _ServerOpts(int(hbm_budget), int(slots), int(chunk), float(tol))
+        o = _ServerOpts(int(hbm_budget), int(slots), int(chunk), float(tol), int(hold_ms), 0)
         self._s = ctypes.c_void_p()
         _check(self.lib.giamg_server_create(ctypes.byref(o), ctypes.byref(self._s)))
         self._sizes = []

@@ -229,3 +229,18 @@ def test_theta_and_hierarchy_info_validation_without_device_work():
     assert lib.giamg_read_bandwidth(1024, 3, giamg._ptr(g)) == giamg.EINVAL
     assert b"1 MiB" in lib.giamg_last_error()
     assert lib.giamg_read_bandwidth(1 << 20, 0, giamg._ptr(g)) == giamg.EINVAL
+
+
+def test_server_options_are_checked_before_device_work():
+    """Out-of-range server options (a negative or over-long admission hold,
+    no slots) are rejected before the library touches a device."""
+    from paper_2512_15121_amd import giamg
+    lib = giamg.library()
+    for kw in ({"hold_ms": -1}, {"hold_ms": 60001}, {"slots": 0}, {"chunk": 0}):
+        f = dict(hbm_budget=1 << 30, slots=4, chunk=2, tol=1e-10, hold_ms=0, pad=0)
+        f.update(kw)
+        o = giamg._ServerOpts(**f)
+        s = ctypes.c_void_p()
+        assert lib.giamg_server_create(ctypes.byref(o), ctypes.byref(s)) == giamg.EINVAL, kw
+        assert b"server options" in lib.giamg_last_error()
+        assert not s.value

@@ -130,6 +130,32 @@ def test_server_fp64_without_staged_tables(torch_dev):
         assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
 
 
+def test_server_admission_hold(torch_dev):
+    """With an admission hold, requests that do not fill a hierarchy's free
+    slots join only once the oldest has waited the hold (so the slowest
+    request here takes at least that long), and every result is bitwise the
+    solve alone."""
+    torch, dev = torch_dev
+    from paper_2512_15121_amd import Server, Options
+    n, p, lam, sd = PROBLEMS[1]
+    m = synth.hex_mesh(n, p, perturb=0.1, seed=sd)
+    hold = 300
+    srv = Server(hbm_budget=8 << 30, slots=4, chunk=2, tol=1e-10, hold_ms=hold)
+    pid = srv.add_problem(m.coords, m.l2g, p, lam, Options(precision="mixed"))
+    srv.wait(srv.submit(pid, synth.normal_rhs(m.n_nodes, 299)))   # hierarchy resident
+    bs = [synth.normal_rhs(m.n_nodes, 300 + i) for i in range(3)]   # 3 < 4 free slots
+    out = [srv.wait(r) for r in [srv.submit(pid, b) for b in bs]]
+    # then more than the free slots: admitted without waiting for the hold
+    bs2 = [synth.normal_rhs(m.n_nodes, 310 + i) for i in range(6)]
+    out2 = [srv.wait(r) for r in [srv.submit(pid, b) for b in bs2]]
+    srv.close()
+    assert max(lat for _, _, lat in out) >= hold
+    for (x, info, lat), b in zip(out + out2, bs + bs2):
+        assert info.status == 0
+        xa, ia = _alone(torch, dev, m, p, lam, b)
+        assert info.iters == ia.iters and np.array_equal(x, xa)
+
+
 def test_server_budget_evicts_and_stays_exact(torch_dev):
     torch, dev = torch_dev
     from paper_2512_15121_amd import Server, Options
