@@ -118,6 +118,17 @@ __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Load of the matrix stream (values, slots, column ids) of a product whose
+// values have type V: non-temporal in FP64, plain in FP32.  Measured at
+// 32^3 p = 4: plain loads slow the FP64 products by ~2 % (Chebyshev step
+// 946 -> 961 us) and speed the FP32 ones by ~3 % (549 -> 533 us; mixed
+// solve 32.9 -> 33.8 solves/s), results bitwise the same.
+template <typename V, typename U>
+__device__ __forceinline__ U ld_matrix(const U* p) {
+    if constexpr (sizeof(V) == 8) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, int64_t max_rows, std::vector<int64_t>& blocks,
                      int& lanes) {
     blocks.clear();
@@ -311,8 +322,8 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
         // between the loads.  Unsigned offsets keep scalar-base addressing.
         const unsigned idx = (unsigned)(tid + k * NT);
         if (idx < (unsigned)n) {
-            c[k] = (int)ldnt(sl + idx);
-            av[k] = ldnt(val + idx);
+            c[k] = (int)ld_matrix<T>(sl + idx);
+            av[k] = ld_matrix<T>(val + idx);
         } else {
             c[k] = 0;
             av[k] = T(0);
@@ -345,8 +356,8 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const unsigned idx = min((unsigned)(tid + k * NT), (unsigned)(n - 1));
-        c[k] = ldnt(ci + idx);
-        av[k] = ldnt(val + idx);
+        c[k] = ld_matrix<T>(ci + idx);
+        av[k] = ld_matrix<T>(val + idx);
     }
     T xv[PER];
 #pragma unroll
@@ -436,12 +447,12 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             T acc0 = 0, acc1 = 0;
             int64_t i = tid;
             for (; i + NT < cnt; i += 2 * NT) {
-                const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + NT);
-                const T a0 = ldnt(val + i), a1 = ldnt(val + i + NT);
+                const int32_t c0 = ld_matrix<T>(ci + i), c1 = ld_matrix<T>(ci + i + NT);
+                const T a0 = ld_matrix<T>(val + i), a1 = ld_matrix<T>(val + i + NT);
                 acc0 += a0 * v[c0];
                 acc1 += a1 * v[c1];
             }
-            if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
+            if (i < cnt) acc0 += ld_matrix<T>(val + i) * v[ld_matrix<T>(ci + i)];
             double s = (double)(acc0 + acc1), unused = 0.0;
             block_sum_to0<NT, 1>(red, tid, s, unused);
             const T y = (T)s;
@@ -538,9 +549,9 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
         for (int k = 0; k < KPT; ++k) {
             const unsigned idx = (unsigned)(tid + k * GROUP_THREADS);
             if (idx < (unsigned)E) {
-                c[k] = (int)ldnt(sl + idx);
+                c[k] = (int)ld_matrix<T>(sl + idx);
 #pragma unroll
-                for (int i = 0; i < G; ++i) av[k][i] = ldnt(val + (unsigned)(i * E) + idx);
+                for (int i = 0; i < G; ++i) av[k][i] = ld_matrix<T>(val + (unsigned)(i * E) + idx);
             } else {
                 c[k] = 0;
 #pragma unroll
