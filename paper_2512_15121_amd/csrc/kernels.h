@@ -51,6 +51,15 @@ constexpr int CHEB_LAST = 2;     // add the new direction as well (last step)
 
 // A row block of the CSR product form (DevCSR::bdesc): rows [r0, r0 + nrows)
 // with n nonzeros from base; staged blocks own runs [run0, run0 + nruns).
+// FP32 products of operators with at least this many nonzeros load the
+// matrix stream with plain loads, smaller ones (and every FP64 product)
+// non-temporal ones.  Measured on the MI355X (mixed solves, same bits
+// either way): at 424 M nonzeros plain loads speed the FP32 products by
+// ~3 % (solve 32.9 -> 33.9 solves/s); at 49 M they slow the solve by ~4 %
+// (220 -> 210 solves/s: the stream then evicts what the rest of the
+// V-cycle reuses from the caches); FP64 products lose ~2 % with them.
+constexpr int64_t FP32_PLAIN_MIN_NNZ = int64_t(128) << 20;
+
 struct BlockDesc {
     int64_t base, r0;
     int32_t nrows, n, run0, nruns;

@@ -118,15 +118,14 @@ __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-// Load of the matrix stream (values, slots, column ids) of a product whose
-// values have type V: non-temporal in FP64, plain in FP32.  Measured at
-// 32^3 p = 4: plain loads slow the FP64 products by ~2 % (Chebyshev step
-// 946 -> 961 us) and speed the FP32 ones by ~3 % (549 -> 533 us; mixed
-// solve 32.9 -> 33.8 solves/s), results bitwise the same.
-template <typename V, typename U>
+// Load of the matrix stream (values, slots, column ids): non-temporal, or
+// plain where PLAIN (FP32 products of operators with at least
+// FP32_PLAIN_MIN_NNZ nonzeros, see kernels.h).  Results are the same bits
+// either way.
+template <bool PLAIN, typename U>
 __device__ __forceinline__ U ld_matrix(const U* p) {
-    if constexpr (sizeof(V) == 8) return __builtin_nontemporal_load(p);
-    else return *p;
+    if constexpr (PLAIN) return *p;
+    else return __builtin_nontemporal_load(p);
 }
 
 void make_row_blocks(const int64_t* rp, int64_t n, int64_t cap, int64_t max_rows, std::vector<int64_t>& blocks,
@@ -299,7 +298,7 @@ __device__ __forceinline__ void stage_runs(const T* __restrict__ v, int2 dsc, in
 
 // Staged: run table first, then values and slots, then the vector runs
 // (copied into prod), then the products (into prod).  nruns > 0.
-template <typename T>
+template <typename T, bool PLAIN>
 __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, int64_t base, int n,
                                                int nruns, T* prod) {
     constexpr int NT = spmv_threads<T>();
@@ -322,8 +321,8 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
         // between the loads.  Unsigned offsets keep scalar-base addressing.
         const unsigned idx = (unsigned)(tid + k * NT);
         if (idx < (unsigned)n) {
-            c[k] = (int)ld_matrix<T>(sl + idx);
-            av[k] = ld_matrix<T>(val + idx);
+            c[k] = (int)ld_matrix<PLAIN>(sl + idx);
+            av[k] = ld_matrix<PLAIN>(val + idx);
         } else {
             c[k] = 0;
             av[k] = T(0);
@@ -343,7 +342,7 @@ __device__ __forceinline__ void stage_products(const SpmvArgs<T>& a, int run0, i
 }
 
 // Direct: column ids and values first, then the gathers.  n > 0.
-template <typename T>
+template <typename T, bool PLAIN>
 __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t base, int n, T* prod) {
     constexpr int NT = spmv_threads<T>();
     constexpr int PER = spmv_cap<T>() / NT;
@@ -356,8 +355,8 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const unsigned idx = min((unsigned)(tid + k * NT), (unsigned)(n - 1));
-        c[k] = ld_matrix<T>(ci + idx);
-        av[k] = ld_matrix<T>(val + idx);
+        c[k] = ld_matrix<PLAIN>(ci + idx);
+        av[k] = ld_matrix<PLAIN>(val + idx);
     }
     T xv[PER];
 #pragma unroll
@@ -395,19 +394,22 @@ __device__ __forceinline__ void direct_products(const SpmvArgs<T>& a, int64_t ba
 // (the run count decides).  Forms 0 and 1 keep the other form's code out of
 // the kernel, so nothing ahead of the value stream waits on loads.  A row
 // longer than the capacity (forms 0 and 2 only) has a block of its own, summed
-// straight from memory by the whole block.
+// straight from memory by the whole block.  STAGE bit 4 (with form 1, FP32
+// only) loads the matrix stream with plain instead of non-temporal loads.
 // Occupancy target of the streaming product: 8 waves per SIMD (64 VGPRs),
 // except the FP32 form that carries both the staged and the direct gathers
 // (16 values per thread of each), which needs a few more registers and runs
 // at 7 rather than spill to scratch.
 template <typename T, int STAGE>
-constexpr int stream_waves() { return (sizeof(T) == 4 && STAGE == 2) ? 7 : 8; }
+constexpr int stream_waves() { return (sizeof(T) == 4 && (STAGE & 3) == 2) ? 7 : 8; }
 
 template <typename T, int MODE, int L, int STAGE>
 __global__ void __launch_bounds__(spmv_threads<T>())
 __attribute__((amdgpu_waves_per_eu(stream_waves<T, STAGE>(), 8)))
 spmv_stream_kernel(SpmvArgs<T> a) {
     if (stopped(a.stop)) return;
+    constexpr int FORM = STAGE & 3;              // 0 direct, 1 staged, 2 per block
+    constexpr bool PLAIN = (STAGE & 4) != 0;     // plain matrix-stream loads
     constexpr int CAP = spmv_cap<T>();
     constexpr int NT = spmv_threads<T>();
     __shared__ T prod[CAP];
@@ -436,7 +438,7 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             return;
         }
     }
-    if constexpr (STAGE != 1) {
+    if constexpr (FORM != 1) {
         if (cnt > CAP) {
             // one long row: block-wide strided sum, fixed-order block sum
             const int32_t* __restrict__ ci = a.ci + base;
@@ -447,12 +449,12 @@ spmv_stream_kernel(SpmvArgs<T> a) {
             T acc0 = 0, acc1 = 0;
             int64_t i = tid;
             for (; i + NT < cnt; i += 2 * NT) {
-                const int32_t c0 = ld_matrix<T>(ci + i), c1 = ld_matrix<T>(ci + i + NT);
-                const T a0 = ld_matrix<T>(val + i), a1 = ld_matrix<T>(val + i + NT);
+                const int32_t c0 = ldnt(ci + i), c1 = ldnt(ci + i + NT);
+                const T a0 = ldnt(val + i), a1 = ldnt(val + i + NT);
                 acc0 += a0 * v[c0];
                 acc1 += a1 * v[c1];
             }
-            if (i < cnt) acc0 += ld_matrix<T>(val + i) * v[ld_matrix<T>(ci + i)];
+            if (i < cnt) acc0 += ldnt(val + i) * v[ldnt(ci + i)];
             double s = (double)(acc0 + acc1), unused = 0.0;
             block_sum_to0<NT, 1>(red, tid, s, unused);
             const T y = (T)s;
@@ -481,15 +483,15 @@ spmv_stream_kernel(SpmvArgs<T> a) {
         row_end = reinterpret_cast<const uint32_t*>(a.rp)[2 * (row + 1)];
     }
     // 1. products into LDS
-    if constexpr (STAGE == 0) {
-        if (n > 0) direct_products<T>(a, base, n, prod);
-    } else if constexpr (STAGE == 1) {
-        if (B.nruns > 0) stage_products<T>(a, B.run0, base, n, B.nruns, prod);   // 0: empty rows only
+    if constexpr (FORM == 0) {
+        if (n > 0) direct_products<T, PLAIN>(a, base, n, prod);
+    } else if constexpr (FORM == 1) {
+        if (B.nruns > 0) stage_products<T, PLAIN>(a, B.run0, base, n, B.nruns, prod);   // 0: empty rows only
     } else {
         if (B.nruns > 0)
-            stage_products<T>(a, B.run0, base, n, B.nruns, prod);
+            stage_products<T, PLAIN>(a, B.run0, base, n, B.nruns, prod);
         else if (n > 0)
-            direct_products<T>(a, base, n, prod);
+            direct_products<T, PLAIN>(a, base, n, prod);
     }
     if (own) rowoff[tid + 1] = (int)(row_end - (uint32_t)base);
     if (tid == 0) rowoff[0] = 0;
@@ -549,9 +551,9 @@ __device__ __forceinline__ void group_block(const SpmvArgs<T>& a, int64_t lb, co
         for (int k = 0; k < KPT; ++k) {
             const unsigned idx = (unsigned)(tid + k * GROUP_THREADS);
             if (idx < (unsigned)E) {
-                c[k] = (int)ld_matrix<T>(sl + idx);
+                c[k] = (int)ldnt(sl + idx);
 #pragma unroll
-                for (int i = 0; i < G; ++i) av[k][i] = ld_matrix<T>(val + (unsigned)(i * E) + idx);
+                for (int i = 0; i < G; ++i) av[k][i] = ldnt(val + (unsigned)(i * E) + idx);
             } else {
                 c[k] = 0;
 #pragma unroll
@@ -928,12 +930,19 @@ void launch_spmv_mode(const SpmvArgs<T>& a, hipStream_t s) {
             case 1: launch_group_kernel<T, MODE, 1>(a, s); break;
             default: throw Error(GIAMG_EINVAL, "unsupported reduction width");
         }
-    } else if (a.run_ptr == nullptr)
+    } else if (a.run_ptr == nullptr) {
         launch_spmv_form<T, MODE, 0>(a, s);
-    else if (a.nnz_staged == a.nnz)
+    } else if (a.nnz_staged == a.nnz) {
+        if constexpr (sizeof(T) == sizeof(float)) {
+            if (a.nnz >= FP32_PLAIN_MIN_NNZ) {
+                launch_spmv_form<T, MODE, 1 | 4>(a, s);
+                return;
+            }
+        }
         launch_spmv_form<T, MODE, 1>(a, s);
-    else
+    } else {
         launch_spmv_form<T, MODE, 2>(a, s);
+    }
 }
 
 template <typename T>
