@@ -569,6 +569,14 @@ def main():
             f"({by:.0f} format bytes, {ms * 1e3:.1f} us each)")
         return
     log(f"workload {args.workload}: n={w['n']} p={w['p']} nodes={mesh.n_nodes} lambda={lam:.6g}")
+    # a process's first setup also pays the runtime's one-time load of the
+    # library's code objects (~0.15 s): a tiny hierarchy takes it first, so
+    # setup_s is the hierarchy's own setup
+    import synth
+    tiny = synth.hex_mesh(2, 2, perturb=0.1, seed=1)
+    t0 = time.perf_counter()
+    Solver(tiny.coords, tiny.l2g, 2, 1.0, Options()).close()
+    first_use_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     solver = Solver(mesh.coords, mesh.l2g, w["p"], lam, Options())
     setup_s = time.perf_counter() - t0
@@ -614,6 +622,7 @@ def main():
              "solve_gbs": round(bytes_per_solve / (ms_per_step * 1e-3) / 1e9, 1),
              "solve_bytes": bytes_per_solve,
              "setup_s": round(setup_s, 3), "setup_ms": solver.setup_times(),
+             "first_use_s": round(first_use_s, 3),
              "levels": levels}
     for kname in ("spmv", "restrict", "prolong"):
         kms, kb = solver.time_kernel(kname, level=0, reps=20)
