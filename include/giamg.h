@@ -550,8 +550,10 @@ typedef struct giamg_server_opts {
     double  tol;          /* relative residual target of every request */
     int32_t hold_ms;      /* 0 (default): requests join a hierarchy's free slots at the
                              next chunk boundary; > 0: they join only once they fill the
-                             free slots or the oldest has waited hold_ms (fuller batches,
-                             longer latency) */
+                             free slots or the oldest has waited hold_ms, or, once a
+                             request has finished on that hierarchy, the shorter of
+                             hold_ms and that request's admission-to-completion time
+                             (fuller batches, longer latency) */
     int32_t pad;
 } giamg_server_opts;
 

@@ -59,7 +59,7 @@ struct Request {
     int problem = 0;
     std::vector<double> b;
     double* x = nullptr;
-    Clock::time_point submit, done;
+    Clock::time_point submit, admitted, done;
     giamg_info info{};
     bool finished = false;
     bool counted = false;    // cache hit/miss recorded
@@ -85,6 +85,7 @@ struct Group {
     hipEvent_t drained = nullptr;
     bool inflight = false;           // a step is queued and not yet complete
     Clock::time_point last_used;
+    double solve_ms = 0.0;           // admission to completion of its last finished request
     int64_t bytes = 0;
     DevBuf<double> stage;            // [slots][n] right-hand sides / results
     double* pin_in = nullptr;        // [slots][n] host staging of right-hand sides
@@ -275,10 +276,13 @@ struct Server {
     // the columns that finished, admit pending requests into free slots,
     // queue the next chunk of iterations.  Every call here is asynchronous.
     // With hold_ms > 0 pending requests enter a group only once they fill its
-    // free slots or the oldest of them has waited hold_ms: an admission runs
-    // a start sequence for the columns it brings, and a product costs the
-    // same for one running column as for all, so admitting in batches gives
-    // fuller steps at the price of latency.
+    // free slots or the oldest of them has waited the group's hold: hold_ms,
+    // or less once a request has finished there, the time that request took
+    // from admission to completion (a hold longer than a solve costs more
+    // latency than the batching gains).  An admission runs a start sequence
+    // for the columns it brings, and a product costs the same for one
+    // running column as for all, so admitting in batches gives fuller steps
+    // at the price of latency.
     bool group_boundary(Group& g, int n_waiting, Clock::time_point oldest, std::vector<int>& state,
                         std::vector<giamg_info>& infos) {
         bool progress = false;
@@ -316,7 +320,8 @@ struct Server {
         const bool admit =
             room > 0 && n_waiting > 0 &&
             (o.hold_ms <= 0 || n_waiting >= room ||
-             Clock::now() - oldest >= std::chrono::milliseconds(o.hold_ms));
+             std::chrono::duration<double, std::milli>(Clock::now() - oldest).count() >=
+                 (g.solve_ms > 0.0 ? std::min<double>(o.hold_ms, g.solve_ms) : (double)o.hold_ms));
         std::vector<Request*> adm;
         if (admit) {
             std::lock_guard<std::mutex> lk(mu);
@@ -330,6 +335,7 @@ struct Server {
                     (int)(std::find(g.slot_req.begin(), g.slot_req.end(), (int64_t)-1) - g.slot_req.begin());
                 g.slot_req[sl] = rp->id;
                 g.running[sl] = 1;
+                rp->admitted = Clock::now();
                 double* dst = g.stage.get() + (size_t)sl * n;
                 double* src = g.pin_in + (size_t)sl * n;
                 std::memcpy(src, rp->b.data(), n * sizeof(double));
@@ -428,6 +434,7 @@ struct Server {
                             std::memcpy(r.x, g.pin_out + (size_t)d.first * n, n * sizeof(double));
                             r.info = g.info[d.first];
                             finish(r, g.info[d.first].status);
+                            g.solve_ms = std::chrono::duration<double, std::milli>(r.done - r.admitted).count();
                         }
                         g.draining.clear();
                         g.last_used = Clock::now();
