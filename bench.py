@@ -524,7 +524,7 @@ def main():
     ap.add_argument("--serving-hold", type=int, default=None,
                     help="serving: admission hold in ms (requests join a hierarchy once they fill its free "
                          "slots or the oldest has waited this long, or a hierarchy's last solve time "
-                         "if shorter; 0 = at the next chunk boundary); default 1000")
+                         "if shorter; 0 = at the next chunk boundary); default 10000")
     ap.add_argument("--serving-only", action="store_true",
                     help="only run the serving leg given by --serving and print it as one JSON line")
     ap.add_argument("--batched-only", action="store_true",
@@ -694,8 +694,8 @@ def serving(torch, Server, Options, size, slots=8, chunk=2, hold_ms=None):
     whose hierarchies all fit one MI355X's HBM; full: n <= 24, ~381 GB of
     hierarchies in mixed precision, so the full trace runs in FP64 without
     staged-gather tables, ~15 B per fine nonzero, within a 270 GB budget)."""
-    if hold_ms is None:   # admission in batches, held at most 1 s or one solve's time
-        hold_ms = 1000
+    if hold_ms is None:   # admission in batches, held at most one solve's time (or 10 s)
+        hold_ms = 10000
     try:
         if size == "full":
             return serving_leg(torch, Server, Options, n_req=2000, n_range=(4, 24), p_range=(2, 6),
