@@ -48,7 +48,7 @@ extern "C" {
 #define GIAMG_ENOMEM     (-2) /* device or host allocation failed; no handle is created */
 #define GIAMG_EHIP       (-3) /* a HIP runtime call failed */
 #define GIAMG_EBREAKDOWN (-4) /* CG breakdown: p^T A p <= 0 or a non-finite value */
-#define GIAMG_ENOTSUP    (-5) /* valid input outside what this build supports */
+#define GIAMG_ENOTSUP    (-5) /* valid input outside what the library supports */
 
 /* ---- options ----------------------------------------------------------- */
 #define GIAMG_SMOOTHER_CHEBYSHEV 0
